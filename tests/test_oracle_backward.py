@@ -1,0 +1,137 @@
+"""Pins of the oracle's backward pass: FP64 central finite differences.
+
+The scalar checked is L = sum_pixels (gD D + gN . N + gO O) for random
+upstream gradients, so every term of the Supp. D chain rule (depth, normal and
+opacity channels, s_hat, p_hat, the plane vectors, R, S, mu, o) and the se(3)
+pose gradient enter.  Pixels where some pair sits within the (wide) guard
+band of a decision (support, near, alpha thresholds, stop rule) get zero
+upstream gradient, so the finite differences never cross a discontinuity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import synth
+from tests import helpers as h
+
+GUARD_FD = (5e-3, 5e-4, 5e-3, 5e-3)
+
+
+def tiny_scene(seed, n=10):
+    g = np.random.default_rng(seed)
+    s = O.make_sensor(16, 64)
+    mus, qs, lss, lgs = [], [], [], []
+    for k in range(n):
+        i, j = g.uniform(2, 14), g.uniform(0, 64)
+        v = h.ray_dir(s, i, j)
+        d = g.uniform(2.5, 7.0)
+        nrm = -v + 0.5 * g.normal(size=3)
+        q = h.facing_surfel(d * v, nrm, g.uniform(0, 2 * math.pi))
+        q = q * g.uniform(0.6, 1.7)  # unnormalised on purpose
+        mus.append(d * v + 0.05 * g.normal(size=3))
+        qs.append(q)
+        lss.append(np.log(g.uniform(0.3, 1.2, 2)))
+        lgs.append(g.normal())
+    return s, np.array(mus), np.array(qs), np.array(lss), np.array(lgs)
+
+
+def loss(s, mu, q, ls, lg, T, gD, gN, gO, keep):
+    r = O.render_pixels(mu, q, ls, lg, T, s, guard=GUARD_FD, exact=True)
+    assert (r["flags"][keep] == 0).all()
+    return (gD * r["depth"]).sum() + (gN * r["normal"]).sum() + (gO * r["alpha"]).sum()
+
+
+def clean_scene(seed0):
+    """A tiny scene with enough unflagged, multiply-covered pixels; returns the
+    scene and the mask of pixels kept in the loss."""
+    for seed in range(seed0, seed0 + 50):
+        s, mu, q, ls, lg = tiny_scene(seed)
+        T = synth.perturbed_pose(seed, trans=0.3, rot_deg=4.0)
+        r = O.render_pixels(mu, q, ls, lg, T, s, guard=GUARD_FD, exact=True)
+        keep = r["flags"] == 0
+        if (keep & (r["n_contrib"] > 0)).mean() > 0.15 and r["n_contrib"][keep].max() >= 3:
+            return s, mu, q, ls, lg, T, keep
+    raise RuntimeError("no clean scene")
+
+
+def upstream(seed, keep):
+    P = keep.size
+    g = np.random.default_rng(seed)
+    gD, gN, gO = g.normal(size=P), g.normal(size=(P, 3)), g.normal(size=P)
+    return gD * keep, gN * keep[:, None], gO * keep
+
+
+@pytest.mark.parametrize("seed0", [100, 300])
+def test_param_gradients_match_fd(seed0):
+    s, mu, q, ls, lg, T, keep = clean_scene(seed0)
+    gD, gN, gO = upstream(seed0 + 1, keep)
+    an = O.backward_pixels(mu, q, ls, lg, T, s, O.all_pixels(s), gD, gN, gO, exact=True)
+    eps = 1e-6
+    params = dict(means=mu, quats=q, log_scales=ls, logits=lg)
+    worst = 0.0
+    for name, arr in params.items():
+        fd = np.zeros_like(arr)
+        flat = arr.reshape(-1)
+        for e in range(flat.size):
+            vals = []
+            for sgn in (1, -1):
+                pert = {k: v.copy() for k, v in params.items()}
+                pert[name].reshape(-1)[e] = flat[e] + sgn * eps
+                vals.append(loss(s, pert["means"], pert["quats"], pert["log_scales"], pert["logits"], T,
+                                 gD, gN, gO, keep))
+            fd.reshape(-1)[e] = (vals[0] - vals[1]) / (2 * eps)
+        a = an[name]
+        scale = max(np.abs(fd).max(), 1e-3)
+        err = np.abs(a - fd).max() / scale
+        worst = max(worst, err)
+        assert err < 1e-6, (name, err)
+    assert worst < 1e-6
+
+
+@pytest.mark.parametrize("seed0", [100, 300])
+def test_pose_gradient_matches_fd(seed0):
+    s, mu, q, ls, lg, T, keep = clean_scene(seed0)
+    gD, gN, gO = upstream(seed0 + 2, keep)
+    an = O.backward_pixels(mu, q, ls, lg, T, s, O.all_pixels(s), gD, gN, gO, exact=True)["pose"]
+    eps = 1e-7
+    fd = np.zeros(6)
+    for e in range(6):
+        vals = []
+        for sgn in (1, -1):
+            d = np.zeros(6)
+            d[e] = sgn * eps
+            vals.append(loss(s, mu, q, ls, lg, h.perturb_cw(T, d), gD, gN, gO, keep))
+        fd[e] = (vals[0] - vals[1]) / (2 * eps)
+    err = np.linalg.norm(an - fd) / max(np.linalg.norm(fd), 1e-3)
+    assert err < 1e-6, (an, fd)
+
+
+def test_gradients_vanish_for_culled_and_unseen():
+    """A surfel behind the near range and one outside the field of view get 0."""
+    s, mu, q, ls, lg, T, keep = clean_scene(100)
+    Twc = synth.pose_inverse(T)
+    # one centre 5 cm from the sensor origin, one straight above it (elevation 90 deg)
+    mu2 = np.concatenate([mu, [Twc[:3, 3] + [0.05, 0.0, 0.0], Twc[:3, :3] @ [0.0, 0.0, 30.0] + Twc[:3, 3]]])
+    q2 = np.concatenate([q, [[1, 0, 0, 0], [1, 0, 0, 0]]])
+    ls2 = np.concatenate([ls, [[0.0, 0.0], [-1.0, -1.0]]])
+    lg2 = np.concatenate([lg, [0.0, 0.0]])
+    P = 16 * 64
+    an = O.backward_pixels(mu2, q2, ls2, lg2, T, s, O.all_pixels(s), np.ones(P), np.ones((P, 3)), np.ones(P),
+                           exact=True)
+    for k in ("means", "quats", "log_scales", "logits"):
+        assert not np.any(an[k][-2:])
+
+
+def test_opacity_channel_gradient_closed_form():
+    """dO/do for a single fronto-parallel surfel at its centre pixel is G = 1,
+    so dL/dlogit = o (1 - o) there."""
+    s = O.make_sensor(16, 64)
+    i, j = 8, 20
+    v = h.ray_dir(s, i, j)
+    q = h.facing_surfel(5 * v, -v)
+    o = 0.4
+    an = O.backward_pixels((5 * v)[None], q[None], np.log([[0.05, 0.05]]), [math.log(o / (1 - o))], np.eye(4), s,
+                           [[i, j]], None, None, [1.0], exact=True)
+    assert an["logits"][0] == pytest.approx(o * (1 - o), rel=1e-9)

@@ -1,0 +1,204 @@
+"""Pins of the oracle's binning mirror (Sec. 3.2.1 tiles, Sec. 3.2.3 box).
+
+* Conservativeness by brute force: every (pixel, surfel) pair whose ray meets
+  the 3-sigma square in front of the near range (an independent textbook
+  ray-plane solve over the whole image) lies inside that surfel's pixel box
+  and tiles, on random scenes and on adversarial ones (seam, behind the sensor,
+  z-axis piercing above and below, near-sensor, grazing, huge surfels).
+* The sorted lists equal numpy's lexsort of (tile, key, id) over the tiles the
+  rectangles cover, and the tile ranges delimit them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import synth
+from tests import helpers as h
+
+
+def support_masks(sc, T, s, shrink=1e-6):
+    """[n, H, W] bool: ray meets the square (|s_hat|_inf <= 3 - shrink) at t > near."""
+    H, W = s["height"], s["width"]
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    V = h.ray_dir(s, ii, jj)  # [H, W, 3]
+    out = []
+    for k in range(sc["means"].shape[0]):
+        mu = sc["means"][k].astype(np.float64)
+        q = sc["quats"][k].astype(np.float64)
+        ls = sc["log_scales"][k].astype(np.float64)
+        ba, bb, bc, n, o, _ = h.sensor_frame_vectors(mu, q, ls, 0.0, T)
+        nv = V @ n
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.dot(n, bc) / nv
+            X = t[..., None] * V - bc
+            sa = X @ ba / np.dot(ba, ba)
+            sb = X @ bb / np.dot(bb, bb)
+            m = (np.maximum(np.abs(sa), np.abs(sb)) <= 3 - shrink) & (t > s["near"] + 1e-9) & (nv != 0)
+        if np.linalg.norm(bc) <= s["near"]:
+            m[:] = False
+        out.append(m)
+    return np.stack(out)
+
+
+def check_conservative(sc, T, s, th=16, tw=16):
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s, th, tw)
+    M = support_masks(sc, T, s)
+    H, W = s["height"], s["width"]
+    tx = (W + tw - 1) // tw
+    n_sup = 0
+    for k in range(M.shape[0]):
+        rr, cc = np.nonzero(M[k])
+        if rr.size == 0:
+            continue
+        n_sup += 1
+        pb = b["pixbox"][k]
+        assert b["counts"][k] > 0, k
+        assert (rr >= pb[0]).all() and (rr <= pb[1]).all(), (k, pb, rr.min(), rr.max())
+        inc = (cc >= pb[2]) & (cc <= pb[3])
+        if pb[4] >= 0:
+            inc |= (cc >= pb[4]) & (cc <= pb[5])
+        assert inc.all(), (k, pb, np.unique(cc[~inc]))
+        # and every covered pixel's tile is one of the surfel's tiles
+        tiles = set(np.unique((rr // th) * tx + cc // tw).tolist())
+        rc = b["rects"][k]
+        mine = set()
+        for r in range(2):
+            if rc[4 * r] < 0:
+                continue
+            for ty in range(rc[4 * r + 2], rc[4 * r + 3] + 1):
+                for x in range(rc[4 * r], rc[4 * r + 1] + 1):
+                    mine.add(ty * tx + x)
+        assert tiles <= mine
+        assert len(mine) == b["counts"][k]
+    return b, M, n_sup
+
+
+def test_box_conservative_shell():
+    s = O.make_sensor(32, 256)
+    sc = synth.shell_scene(600, 7)
+    b, M, n_sup = check_conservative(sc, np.eye(4), s)
+    assert n_sup > 120
+
+
+def test_box_conservative_posed_structured():
+    s = O.make_sensor(32, 256)
+    sc, _ = synth.structured_scene(600, 8)
+    T = synth.circle_poses(3, 5)[1]
+    b, M, n_sup = check_conservative(sc, T, s)
+    assert n_sup > 100
+
+
+def adversarial_scene():
+    g = np.random.default_rng(12)
+    mus, qs, lss = [], [], []
+
+    def add(mu, n, scales, spin=0.0):
+        mus.append(mu)
+        qs.append(h.facing_surfel(mu, n, spin))
+        lss.append(np.log(scales))
+
+    for k in range(40):  # straddling the seam (azimuth pi), various elevations
+        el = g.uniform(-0.5, 0.3)
+        az = math.pi + g.uniform(-0.05, 0.05)
+        r = g.uniform(1.0, 20.0)
+        mu = r * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        add(mu, g.normal(size=3), g.uniform(0.1, 2.0, 2), g.uniform(0, 6.3))
+    for z in (2.0, 0.7, -1.8, -0.6):  # horizontal squares pierced by the z-axis above / below
+        for off in (0.0, 0.4, 1.1):
+            add(np.array([off, -0.3 * off, z]), np.array([0, 0, -np.sign(z)]), (0.8, 1.5), off)
+    for k in range(20):  # close to the sensor and large
+        d = g.normal(size=3)
+        d /= np.linalg.norm(d)
+        add(d * g.uniform(0.25, 1.0), g.normal(size=3), g.uniform(0.5, 3.0, 2), g.uniform(0, 6.3))
+    for k in range(30):  # grazing: the plane nearly contains the line of sight
+        d = g.normal(size=3)
+        d[2] *= 0.3
+        d /= np.linalg.norm(d)
+        mu = d * g.uniform(2.0, 15.0)
+        n = np.cross(d, g.normal(size=3))
+        add(mu, n, g.uniform(0.2, 2.0, 2), g.uniform(0, 6.3))
+    for k in range(20):  # huge surfels
+        d = g.normal(size=3)
+        d /= np.linalg.norm(d)
+        add(d * g.uniform(3.0, 10.0), g.normal(size=3), g.uniform(3.0, 8.0, 2), g.uniform(0, 6.3))
+    n = len(mus)
+    return dict(means=np.array(mus, np.float32), quats=np.array(qs, np.float32),
+                log_scales=np.array(lss, np.float32), logits=np.zeros(n, np.float32))
+
+
+@pytest.mark.parametrize("th,tw", [(16, 16), (8, 32), (32, 8), (4, 64)])
+def test_box_conservative_adversarial(th, tw):
+    s = O.make_sensor(32, 256)
+    sc = adversarial_scene()
+    b, M, n_sup = check_conservative(sc, np.eye(4), s, th, tw)
+    assert n_sup > 60
+    # a square pierced by the z-axis below the sensor spans all columns
+    full = (b["pixbox"][:, 2] == 0) & (b["pixbox"][:, 3] == 255)
+    assert full.sum() >= 4
+
+
+def test_box_tightness_aggregate():
+    """The exact angular box costs few tiles beyond the tiles the support touches."""
+    s = O.make_sensor(64, 512)
+    sc = synth.shell_scene(500, 3)
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s)
+    M = support_masks(sc, np.eye(4), s)
+    touched = 0
+    for k in range(M.shape[0]):
+        rr, cc = np.nonzero(M[k])
+        touched += np.unique((rr // 16) * 32 + cc // 16).size
+    assert touched <= b["K"] <= 1.6 * touched
+
+
+def test_sorted_lists_match_lexsort():
+    s = O.make_sensor(64, 512)
+    sc = synth.shell_scene(2000, 1)
+    T = synth.perturbed_pose(4)
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s)
+    tx = b["tiles_x"]
+    tiles, keys, ids = [], [], []
+    for k in range(2000):
+        rc = b["rects"][k]
+        for r in range(2):
+            if rc[4 * r] < 0:
+                continue
+            for ty in range(rc[4 * r + 2], rc[4 * r + 3] + 1):
+                for x in range(rc[4 * r], rc[4 * r + 1] + 1):
+                    tiles.append(ty * tx + x); keys.append(b["keys"][k]); ids.append(k)
+    tiles, keys, ids = np.array(tiles), np.array(keys), np.array(ids)
+    order = np.lexsort((ids, keys, tiles))
+    assert b["K"] == tiles.size == b["counts"].sum()
+    np.testing.assert_array_equal(b["sorted_tile"], tiles[order])
+    np.testing.assert_array_equal(b["sorted_id"], ids[order])
+    nt = b["tiles_x"] * b["tiles_y"]
+    starts = np.searchsorted(tiles[order], np.arange(nt), "left")
+    ends = np.searchsorted(tiles[order], np.arange(nt), "right")
+    empty = starts == ends
+    np.testing.assert_array_equal(b["ranges"][~empty, 0], starts[~empty])
+    np.testing.assert_array_equal(b["ranges"][~empty, 1], ends[~empty])
+    assert (b["ranges"][empty] == 0).all()
+    # keys are the FP32 bit patterns of the centre range (positive floats sort as integers)
+    fr, kk, valid = O.frames(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T)
+    np.testing.assert_array_equal(kk, b["keys"])
+
+
+def test_capacity_overflow_reports_K():
+    s = O.make_sensor(64, 512)
+    sc = synth.shell_scene(2000, 1)
+    full = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s)
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s, capacity=10)
+    assert b["overflow"] and b["K"] == full["K"]
+
+
+def test_non_finite_and_near_are_culled():
+    s = O.make_sensor(32, 256)
+    sc = synth.shell_scene(10, 2)
+    sc["means"][0, 1] = np.nan
+    sc["quats"][1] = 0.0
+    sc["log_scales"][2, 0] = np.inf
+    sc["logits"][3] = np.nan
+    sc["means"][4] = [0.1, 0.05, 0.0]
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s)
+    assert (b["counts"][:5] == 0).all()
