@@ -1,0 +1,193 @@
+#!/usr/bin/env python
+"""Throughput of the spherical surfel rasterizer's fwd+bwd on one MI355X.
+
+Workload: 1,000,000 surfels on the structured synthetic scene (ground, 30
+boxes, 20 cylinders; seed 0), eight 128x1024 keyframes on a 5 m circle at
+sensor height (random yaw, seed 0) sharing that map, range + normal L1 loss
+against analytic ray-cast targets.  One step = for every keyframe: render
+(projection, bounding box, binning with the radix sort, compositing), fused
+loss and gradients, backward (compositing backward, per-surfel gradients
+summed over the keyframes, pose gradient per keyframe).  Inputs are resident
+in HBM before the timed region.
+
+Prints one JSON line (see the design doc for every field's definition).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd iter/s, 128x1024 range image, 1M surfels; batched vs plain"
+N_SURFELS = 1_000_000
+N_KF = 8
+H, W = 128, 1024
+
+# Algorithmic FLOPs (FMA = 2) per unit of compositing work; see the design doc.
+FWD_EVAL_FLOPS = 18      # 3 three-term FP64 dot products + support bound, reciprocal, range
+FWD_CONTRIB_FLOPS = 20   # Gaussian, alpha, blending of range, normal and opacity
+BWD_EVAL_FLOPS = 18
+BWD_CONTRIB_FLOPS = 70   # recompute alpha, transmittance recovery, dL/dalpha, 14 partials
+PEAK_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), unpacked FP32 / FP64
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def build_workload(torch, slr, synth, targets):
+    t0 = time.time()
+    sc, prims = synth.structured_scene(N_SURFELS, 0)
+    poses = synth.circle_poses(N_KF, 0)
+    sensor = slr.make_sensor(H, W)
+    dev = "cuda"
+    d = {k: torch.from_numpy(v).to(dev) for k, v in sc.items()}
+    kfs = []
+    for k, T in enumerate(poses):
+        Dt, Nt = targets.raycast(prims, sensor, T, seed=100 + k)
+        nvalid = int((Dt > 0).sum())
+        kfs.append(dict(T=torch.from_numpy(T).to(dev), Dt=torch.from_numpy(Dt).to(dev),
+                        Nt=torch.from_numpy(Nt).to(dev), w=1.0 / max(nvalid, 1), T_np=T))
+    log(f"workload built in {time.time() - t0:.1f}s")
+    return sc, d, sensor, kfs
+
+
+def plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss):
+    for k, kf in enumerate(kfs):
+        r = rend[k]
+        D, N, O = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], kf["T"])
+        gD, gN = scratch
+        slr.loss_l1_normal(D, N, kf["Dt"], kf["Nt"], kf["w"], kf["w"], gD, gN, loss)
+        if k == 0:
+            g, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], kf["T"], gD, gN, None)
+            for key in grads:
+                grads[key] = g[key]
+            dposes[0] = dp
+        else:
+            r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], kf["T"], gD, gN, None,
+                       out=(grads, dposes[k]))
+
+
+def cpu_baseline(sc, sensor, kfs, budget_s):
+    """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
+    import numpy as np
+
+    import oracle as O
+    T = kfs[0]["T_np"]
+    Dt = kfs[0]["Dt"].cpu().numpy()
+    g = np.random.default_rng(7)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def run(P):
+        pix = np.stack([g.integers(0, H, P), g.integers(0, W, P)], 1).astype(np.int32)
+        t = time.perf_counter()
+        r = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix)
+        valid = Dt[pix[:, 0], pix[:, 1]] > 0
+        gD = np.where(valid, np.sign(r["depth"] - Dt[pix[:, 0], pix[:, 1]]), 0.0)
+        O.backward_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix, gD, None, None)
+        return time.perf_counter() - t
+
+    P0 = 2 * threads
+    t0 = run(P0)
+    P = max(P0, int(P0 * budget_s / max(t0, 1e-3)))
+    t1 = run(P)
+    per_pixel = t1 / P
+    s_per_iter = per_pixel * H * W * N_KF
+    return {"value": 1.0 / s_per_iter, "unit": "iter/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle fwd+bwd of {P} random pixels of keyframe 0 (brute force over {N_SURFELS} "
+                      f"surfels) in {t1:.1f}s, scaled to {N_KF}x{H}x{W} pixels per iteration"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", choices=["plain"], default="plain")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU; the multi-GPU design is described in DESIGN.md "
+              "(keyframe sharding and a gradient all-reduce) and is not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2503_17491_amd import slr, synth, targets
+    slr.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    th, tw = (int(x) for x in args.tile.split("x"))
+    sc, d, sensor, kfs = build_workload(torch, slr, synth, targets)
+    rend = [slr.Renderer(sensor, (th, tw), capacity=4 << 20) for _ in kfs]
+    grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
+    dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
+    scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    for _ in range(args.warmup):
+        plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
+    torch.cuda.synchronize()
+    log("warmup done; pairs per keyframe:", [r.K for r in rend])
+
+    slr.stage_timer(True)
+    slr.stage_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = slr.stage_times()
+    slr.stage_timer(False)
+    dt = t1 - t0
+    iters = args.steps / dt
+    log(f"timed {args.steps} steps in {dt:.3f}s -> {iters:.2f} iter/s")
+
+    # census of the compositing work of the last step (outside the timed region)
+    ef = cf = eb = cb = 0
+    for r in rend:
+        c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
+        ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
+    fwd_ms = stages["raster_fwd"][0] / max(stages["raster_fwd"][1], 1)
+    bwd_ms = stages["raster_bwd"][0] / max(stages["raster_bwd"][1], 1)
+    fwd_flops = (FWD_EVAL_FLOPS * ef + FWD_CONTRIB_FLOPS * cf) / N_KF
+    bwd_flops = (BWD_EVAL_FLOPS * eb + BWD_CONTRIB_FLOPS * cb) / N_KF
+    if bwd_ms >= fwd_ms:
+        dom, flops, ms = "raster_bwd", bwd_flops, bwd_ms
+    else:
+        dom, flops, ms = "raster_fwd", fwd_flops, fwd_ms
+    achieved = flops / (ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
+    stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(sc, sensor, kfs, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": round(iters, 3), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
+                               f"map, fwd + L1 range/normal loss + bwd per keyframe",
+                   "form": args.form, "tile": args.tile, "keyframes": N_KF, "surfels": N_SURFELS,
+                   "pairs_per_step": int(sum(r.K for r in rend)),
+                   "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
+        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

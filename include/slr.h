@@ -1,0 +1,173 @@
+/*
+ * slr.h -- C ABI of the spherical LiDAR surfel rasterizer (MI355X / gfx950).
+ *
+ * Differentiable rasterization of 2D Gaussian surfels into a spherical
+ * (azimuth / elevation) range image, as in Splat-LOAM (Giacomini et al.,
+ * arXiv 2503.17491): forward gives range D, normal N and opacity O per pixel
+ * (Sec. 3.2.1, Eqs. ab_depth / ab_normal / ab_opacity), backward gives the
+ * gradients of a loss w.r.t. the raw surfel parameters and w.r.t. the sensor
+ * pose in se(3) (Supp. D "Gradient Computation"; pose update of Sec. 3.3.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Sensor model (Sec. 3.1, Supp. A): azimuth az = atan2(y, x), elevation
+ *   el = atan2(z, sqrt(x^2 + y^2)); image coordinates u = fu*az + cu,
+ *   v = fv*el + cv.  Pixel (i, j) (row, column) looks along the ray of
+ *   (u, v) = (j + 1/2, i + 1/2).  The azimuth wraps with period 2*pi*|fu|
+ *   pixels.  Sensor axes: x forward, y left, z up.
+ * - Surfel raw parameters (Sec. 3.2): mean mu [3], quaternion (w, x, y, z)
+ *   [4] (normalised inside; rotation columns t_alpha, t_beta, t_n), log-scales
+ *   [2] (s = exp), opacity logit [1] (o = sigmoid).  FP32, row-major, device.
+ * - Pose: T_cw (world -> sensor) as a row-major 4x4 FP64 matrix in DEVICE
+ *   memory.  The pose gradient is w.r.t. delta = (rho; phi) in se(3) for
+ *   T_cw(delta) = exp(-delta^) T_cw, i.e. the sensor pose update
+ *   T_wc <- T_wc exp(delta) of Sec. 3.3.3; rho first.
+ * - Compositing (Sec. 3.2.1, following the 3DGS blending it cites): a pair
+ *   contributes when the ray meets the 3-sigma square |s_alpha|, |s_beta| <= 3
+ *   in front of the near range, alpha = min(0.99, o G(s_hat)) >= 1/255, and
+ *   the running transmittance would not drop below 1e-4.  Per-tile lists are
+ *   ordered by the FP32 rounding of the centre range |R_cw mu + t_cw| and then
+ *   by surfel index.  Outputs are the raw Eq. 4-6 sums (D/O is the expected
+ *   range of the hit surface).
+ * - Ownership: the caller owns every buffer (inputs, outputs, workspace).  The
+ *   library allocates no device memory and keeps no device state between
+ *   calls other than what it writes into the caller's workspace.  All device
+ *   work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *   NULL = the default stream).
+ * - Errors: every call validates its arguments on the host before enqueuing
+ *   anything and returns a negative status; slr_last_error() gives a
+ *   thread-local message.  Gradient outputs are overwritten unless the
+ *   caller asks for accumulation.
+ */
+#ifndef SLR_H
+#define SLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t slr_status;
+#define SLR_OK 0
+#define SLR_E_INVALID (-1)     /* bad argument; nothing was enqueued */
+#define SLR_E_CAPACITY (-2)    /* more (tile, surfel) pairs than the workspace holds */
+#define SLR_E_HIP (-3)         /* a HIP runtime call failed */
+#define SLR_E_UNSUPPORTED (-4) /* a valid request this build does not implement */
+
+/* Spherical sensor: image size and the camera matrix K of Supp. A. */
+typedef struct slr_sensor {
+    int32_t height, width; /* rows (elevation), columns (azimuth) */
+    double fu, cu, fv, cv; /* u = fu*az + cu, v = fv*el + cv; fu, fv must be < 0 */
+    double near_m;         /* pairs with ray range t <= near_m are rejected, and
+                              surfels whose centre range <= near_m are culled */
+} slr_sensor;
+
+/* Tile shape of the binning (Sec. 3.2.1 uses 16x16).  tile_h * tile_w must be
+ * 256; supported shapes: 16x16, 8x32, 32x8, 4x64. */
+typedef struct slr_tiling {
+    int32_t tile_h, tile_w;
+} slr_tiling;
+
+/* Surfel set: raw parameters in device memory, FP32, row-major. */
+typedef struct slr_surfels {
+    int64_t n;
+    const float *means;      /* [n,3] */
+    const float *quats;      /* [n,4]  w, x, y, z */
+    const float *log_scales; /* [n,2] */
+    const float *logits;     /* [n]   */
+} slr_surfels;
+
+/* Device views into a workspace after slr_render (binning results). */
+typedef struct slr_views {
+    const uint32_t *keys;        /* [n]  FP32 bit pattern of the centre range */
+    const int32_t *counts;       /* [n]  tiles per surfel, 0 = culled */
+    const int16_t *pixbox;       /* [n,8] r0, r1, c0, c1, c2, c3 (c2 = c3 = -1 if one interval), 0, 0 */
+    const int32_t *sorted_tile;  /* [K]  tile index ty*tiles_x + tx, ascending */
+    const int32_t *sorted_id;    /* [K]  surfel index, by (range key, index) within a tile */
+    const int32_t *ranges;       /* [tiles,2] [start, end) into the sorted arrays; (0,0) if empty */
+    const float *T_final;        /* [H,W] transmittance after the last contributor */
+    const int32_t *n_proc;       /* [H,W] list entries processed up to the last contributor */
+    const int32_t *census;       /* [4,H,W] work counters: forward evaluated list entries,
+                                    forward contributors, backward evaluated entries,
+                                    backward contributors */
+    int64_t tiles_x, tiles_y;
+} slr_views;
+
+/* Supp. A: camera matrix from an angular extent (radians) and an image size.
+ * out[4] = (fu, cu, fv, cv), host memory.  fu = -(W-1)/(az_max-az_min),
+ * cu = W/2 (1 + (az_max+az_min)/(az_max-az_min)), and likewise for rows. */
+slr_status slr_camera_matrix(double az_min, double az_max, double el_min, double el_max,
+                             int32_t height, int32_t width, double *out);
+
+/* Workspace bytes for one image of this size, n surfels and at most
+ * pair_capacity (tile, surfel) pairs (Sec. 3.2.1 per-tile lists). */
+slr_status slr_workspace_size(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n,
+                              int64_t pair_capacity, size_t *bytes);
+
+/* Forward render (Sec. 3.2.1-3.2.3, Supp. D forward process), plain form:
+ * projection + bounding box, binning with the radix sort, then per-tile
+ * compositing.  Reads back the pair count K once (one host synchronisation)
+ * and returns SLR_E_CAPACITY, with *pairs_out = K, if K exceeds the capacity
+ * the workspace was sized for.  Outputs (device, FP32): depth [H,W],
+ * normal [H,W,3], alpha [H,W].  The workspace keeps the binning and the
+ * per-pixel state that slr_backward reads.  pairs_out: host, nullable. */
+slr_status slr_render(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
+                      const slr_tiling *tiling, void *workspace, size_t workspace_bytes,
+                      int64_t pair_capacity, float *depth, float *normal, float *alpha,
+                      int64_t *pairs_out, void *stream);
+
+/* Backward (Supp. D gradient computation; se(3) pose gradient).  Reads the
+ * workspace left by slr_render with the same surfels, pose, sensor and tiling.
+ * Upstream gradients (device, FP32): dL_ddepth [H,W], dL_dnormal [H,W,3],
+ * dL_dalpha [H,W]; any may be NULL (= zero).  Outputs (device, overwritten):
+ * d_means [n,3], d_quats [n,4], d_log_scales [n,2], d_logits [n] (all four
+ * NULL, or all four set), d_pose [6] FP64 (nullable).  With SLR_POSE_ONLY in
+ * flags the surfel gradients are skipped (they must be NULL); with
+ * SLR_ACCUMULATE the surfel gradients are added to the outputs' current
+ * contents (a map shared by several keyframes); d_pose is always overwritten. */
+#define SLR_POSE_ONLY 1u
+#define SLR_ACCUMULATE 2u /* add into the surfel gradients instead of overwriting */
+slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
+                        const slr_tiling *tiling, void *workspace, size_t workspace_bytes,
+                        int64_t pair_capacity, const float *dL_ddepth, const float *dL_dnormal,
+                        const float *dL_dalpha, float *d_means, float *d_quats, float *d_log_scales,
+                        float *d_logits, double *d_pose, uint32_t flags, void *stream);
+
+/* Device pointers into a workspace filled by slr_render (for inspection and
+ * tests). */
+slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n,
+                               int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                               slr_views *views);
+
+/* Range and normal losses of Sec. 3.3.2 (Eqs. loss_range and loss_normal,
+ * with rho_d = 1 and N(D) replaced by a given target normal), fused with
+ * their gradients:
+ *   L = w_d * sum_valid |D - D_t| + w_n * sum_valid (1 - N . N_t),
+ * valid = D_t > 0 (the mask M_v).  Writes dL/dD [H,W] and dL/dN [H,W,3]
+ * (device, FP32, overwritten) and adds L to *loss (device FP64, nullable).
+ * w_d, w_n are typically 1 / |M_v|. */
+slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *normal, const float *target_depth,
+                              const float *target_normal, float w_d, float w_n, float *dL_ddepth,
+                              float *dL_dnormal, double *loss, void *stream);
+
+/* Stage timers: when enabled, the library records HIP events on the
+ * caller's stream around each stage it launches; slr_stage_times()
+ * synchronises them and returns the accumulated milliseconds and launch
+ * counts per stage (then resets).  Stages: 0 projection, 1 range sort,
+ * 2 count scan, 3 emit + tile sort + ranges, 4 forward compositing,
+ * 5 backward compositing, 6 per-surfel gradients, 7 loss.  ms and counts
+ * are host arrays of SLR_NUM_STAGES entries. */
+#define SLR_NUM_STAGES 8
+slr_status slr_stage_timer_enable(int32_t on);
+slr_status slr_stage_times(double *ms, int64_t *counts);
+
+const char *slr_status_string(slr_status status);
+const char *slr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLR_H */

@@ -15,8 +15,12 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 # guard-band flag bits (oracle.c)
 FLAG_SUPPORT, FLAG_NEAR, FLAG_AMIN, FLAG_TSTOP, FLAG_CLAMP, FLAG_KEYTIE = 1, 2, 4, 8, 16, 32
-# default guard-band widths: support (splat units), near (m), alpha (relative), T-stop (relative)
-DEFAULT_GUARD = (1e-4, 1e-5, 1e-4, 1e-3)
+# default guard-band widths: support (splat units), near (m), alpha (relative), T-stop (relative).
+# Each is >= 20x the FP32 error of the GPU path for that decision: s_hat from
+# FP64 dot products rounded to FP32 (~4e-7), the ray range (~1e-7 relative),
+# alpha = o G (~2e-6 relative), and transmittance accumulated over up to
+# hundreds of contributors (~2e-5 relative).
+DEFAULT_GUARD = (1e-5, 1e-5, 5e-5, 1e-3)
 
 
 class _Sensor(C.Structure):

@@ -1,0 +1,343 @@
+// binning.hip -- per-tile, range-sorted surfel lists (Sec. 3.2.1) on gfx950.
+//
+// The lists are the pairs (tile, surfel) ordered by (tile, range key, surfel
+// index).  They are produced by a least-significant-digit radix sort on the
+// composite (tile, range) key, split in two stages because all pairs of one
+// surfel share its range digits:
+//   1. the range digits are sorted at surfel granularity: a stable LSD radix
+//      sort of the N (key, index) pairs (8-bit digits, 4 passes);
+//   2. the pairs are emitted in that order (exclusive scan of the per-surfel
+//      tile counts, then one thread per surfel writes its tile indices);
+//   3. the tile digits are sorted with the same stable LSD radix passes over
+//      the K pairs (ceil(log2 tiles / 8) passes);
+//   4. tile ranges [start, end) from key boundaries.
+// Every step is integer-only and deterministic.
+//
+// The radix pass is the classic three-kernel form: per-block digit histograms,
+// a per-digit scan over blocks, and a scatter whose in-block ranks are stable.
+// Ranks come from 64-lane ballots: for each row of 64 consecutive items a wave
+// forms, per lane, the mask of lanes holding the same digit (one ballot per
+// digit bit), so the rank in the row is a popcount and a per-wave running
+// counter in LDS carries the rank across rows.
+#include "slr_internal.h"
+
+namespace slr {
+namespace {
+
+constexpr int kWaves = kSortThreads / 64;
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
+// Exclusive scan across a 256-thread block; returns the prefix, *total = sum.
+__device__ uint32_t block_exscan(uint32_t v, uint32_t *s_wave, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        uint32_t s = s_wave[w];
+        pre += (w < wid) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift, int bits, uint32_t *__restrict__ hist,
+             int nblocks)
+{
+    __shared__ uint32_t h[256];
+    const int nb = 1 << bits;
+    for (int d = threadIdx.x; d < nb; d += kSortThreads) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const uint32_t mask = (uint32_t)nb - 1u;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nb; d += kSortThreads) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
+}
+
+// One block per digit: exclusive scan of that digit's counts over blocks.
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += kSortThreads) {
+        int b = b0 + threadIdx.x;
+        uint32_t v = b < nblocks ? row[b] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exscan(v, s_wave, &tot);
+        if (b < nblocks) row[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                uint32_t *__restrict__ vout, int64_t n, int shift, int bits, const uint32_t *__restrict__ hist,
+                const uint32_t *__restrict__ totals, int nblocks)
+{
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_cnt[kWaves][256];
+    __shared__ uint32_t s_wave[kWaves];
+    const int nb = 1 << bits;
+    const uint32_t mask = (uint32_t)nb - 1u;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // digit bases: exclusive scan of the global digit totals
+    {
+        uint32_t v = threadIdx.x < nb ? totals[threadIdx.x] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exscan(v, s_wave, &tot);
+        s_base[threadIdx.x] = ex;
+    }
+    for (int d = lane; d < 256; d += 64) s_cnt[wid][d] = 0;
+    __syncthreads();
+
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (kSortTile / kWaves);
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * 64 + lane;
+        bool valid = idx < n;
+        key[i] = valid ? kin[idx] : 0u;
+        val[i] = valid ? vin[idx] : 0u;
+        uint32_t d = (key[i] >> shift) & mask;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t before = (uint32_t)__popcll(m & lt);
+        uint32_t prev = valid ? s_cnt[wid][d] : 0u;
+        rank[i] = prev + before;
+        // the highest lane of each digit group publishes the new running count
+        if (valid && (m >> lane) == 1ull) s_cnt[wid][d] = prev + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over the waves of this block
+    for (int d = threadIdx.x; d < nb; d += kSortThreads) {
+        uint32_t off = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = off;
+            off += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * 64 + lane;
+        if (idx < n) {
+            uint32_t d = (key[i] >> shift) & mask;
+            uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
+            kout[pos] = key[i];
+            vout[pos] = val[i];
+        }
+    }
+}
+
+// ---- scan of tile counts in range order ----
+__global__ void __launch_bounds__(kSortThreads)
+k_scan_reduce(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
+              uint32_t *__restrict__ blocksum)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) acc += (uint32_t)counts[order[idx]];
+    }
+    uint32_t tot;
+    block_exscan(acc, s_wave, &tot);
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict__ total_out)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    uint64_t carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += kSortThreads) {
+        int b = b0 + threadIdx.x;
+        uint32_t v = b < nblocks ? blocksum[b] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exscan(v, s_wave, &tot);
+        if (b < nblocks) blocksum[b] = (uint32_t)carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
+             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_items[kSortTile];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        s_items[i * kSortThreads + threadIdx.x] = idx < n ? (uint32_t)counts[order[idx]] : 0u;
+    }
+    __syncthreads();
+    // each thread scans a contiguous run of kSortItems
+    uint32_t local[kSortItems], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        local[i] = sum;
+        sum += s_items[threadIdx.x * kSortItems + i];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exscan(sum, s_wave, &tot) + blocksum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) s_items[threadIdx.x * kSortItems + i] = pre + local[i];
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) offsets[idx] = s_items[i * kSortThreads + threadIdx.x];
+    }
+}
+
+// One thread per surfel in range order: write its tile indices and its index.
+__global__ void __launch_bounds__(256)
+k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets, const int32_t *__restrict__ counts,
+       const PixBox *__restrict__ box, int64_t n, int th, int tw, int tiles_x, uint32_t *__restrict__ ptile,
+       uint32_t *__restrict__ pval)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint32_t id = order[r];
+    if (counts[id] == 0) return;
+    PixBox b = box[id];
+    uint32_t o = offsets[r];
+    int ty0 = b.r0 / th, ty1 = b.r1 / th;
+    int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
+    int bx0 = 0, bx1 = -1;
+    if (b.c2 >= 0) {
+        bx0 = b.c2 / tw; bx1 = b.c3 / tw;
+        if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
+    }
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(ty * tiles_x + tx); pval[o] = id; ++o; }
+        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(ty * tiles_x + tx); pval[o] = id; ++o; }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_ranges(const uint32_t *__restrict__ ptile, int64_t K, int2 *__restrict__ ranges)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= K) return;
+    uint32_t t = ptile[p];
+    if (p == 0 || ptile[p - 1] != t) ranges[t].x = (int)p;
+    if (p == K - 1 || ptile[p + 1] != t) ranges[t].y = (int)(p + 1);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n, int shift,
+                int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
+{
+    int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n, shift, bits, hist, nblocks);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
+                       bits, hist, totals, nblocks);
+}
+
+}  // namespace
+
+void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(p), v, count);
+}
+
+void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.n == 0) return;
+    const uint32_t *ks = reinterpret_cast<const uint32_t *>(ws + L.skey);
+    uint32_t *k0 = reinterpret_cast<uint32_t *>(ws + L.key0), *v0 = reinterpret_cast<uint32_t *>(ws + L.val0);
+    uint32_t *k1 = reinterpret_cast<uint32_t *>(ws + L.key1), *v1 = reinterpret_cast<uint32_t *>(ws + L.val1);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc) + 16;
+    // pass 0 reads the per-surfel keys (kept for inspection) and the indices in val0
+    for (int p = 0; p < L.depth_passes; ++p) {
+        const bool even = (p % 2) == 0;
+        const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
+        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.n, 8 * p, 8, hist, totals, stream);
+    }
+}
+
+void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.n == 0) return;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
+    const int32_t *counts = reinterpret_cast<const int32_t *>(ws + L.cnt);
+    uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
+    uint64_t *tot = reinterpret_cast<uint64_t *>(ws + L.misc);
+    int nblocks = (int)((L.n + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.n, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, tot);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.n, bs,
+                       reinterpret_cast<uint32_t *>(ws + L.off));
+}
+
+void launch_emit_and_tile_sort(const Layout &L, char *ws, int64_t K, hipStream_t stream)
+{
+    int2 *ranges = reinterpret_cast<int2 *>(ws + L.ranges);
+    launch_fill_u32(ranges, 0u, 2 * L.ntiles, stream);
+    if (K == 0 || L.n == 0) return;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
+    uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
+    uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, stream, order,
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
+                       reinterpret_cast<const PixBox *>(ws + L.box), L.n, (int)L.th, (int)L.tw, (int)L.tiles_x, t0,
+                       v0);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc) + 16;
+    // split the tile bits evenly over the passes (each <= 8 bits)
+    int done = 0;
+    for (int p = 0; p < L.tile_passes; ++p) {
+        int bits = (L.tile_bits - done + (L.tile_passes - p) - 1) / (L.tile_passes - p);
+        const bool even = (p % 2) == 0;
+        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, K, done, bits, hist, totals,
+                   stream);
+        done += bits;
+    }
+    const uint32_t *ts = L.tile_in_1 ? t1 : t0;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, ts, K, ranges);
+}
+
+}  // namespace slr

@@ -1,0 +1,319 @@
+// project.hip -- per-surfel spherical projection and bounding box (gfx950).
+//
+// One thread per surfel:
+//   * the splat-to-sensor transform T = T_cw H of Supp. D (b_alpha, b_beta,
+//     b_c, n) in FP64, packed into the compositing record (Cramer form, see
+//     RasterRec) and the gradient frame;
+//   * the range key: FP32 rounding of |b_c|;
+//   * the bounding box of Sec. 3.2.3 / Supp. B, computed as the exact angular
+//     box of the 3-sigma splat square, widened by an angular margin, with the
+//     azimuth seam handled by ordering directions instead of angles (no atan2);
+//   * the tile count of the box.
+// The key and the box use only IEEE-exact FP64 +,-,*,/,sqrt in a fixed order
+// (this translation unit is compiled with contraction off) plus host-made
+// direction tables, so the binning is reproducible bit for bit.
+#include "slr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace slr {
+namespace {
+
+// exp for the box scales: reduction by ln 2 and the degree-13 Taylor
+// polynomial of exp on [-ln2/2, ln2/2] (textbook method, a few ulp).
+__device__ double box_exp(double x)
+{
+    const double LN2 = 0.6931471805599453;
+    const double INV_LN2 = 1.4426950408889634;
+    double k = floor(x * INV_LN2 + 0.5);
+    double r = x - k * LN2;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+__device__ inline double xcross(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+// Direction order on (-pi, pi]: true when angle(a) <= angle(b).
+__device__ inline bool angle_le(double ax, double ay, double bx, double by)
+{
+    bool ua = (ay > 0.0) || (ay == 0.0 && ax < 0.0);
+    bool ub = (by > 0.0) || (by == 0.0 && bx < 0.0);
+    if (ua != ub) return !ua && ub;
+    return xcross(ax, ay, bx, by) >= 0.0;
+}
+
+// Elevation of (r, z) strictly below elevation of (r', z') (r, r' >= 0).
+__device__ inline bool elev_below(double r, double z, double r2, double z2) { return z * r2 - r * z2 < 0.0; }
+
+struct BoxOut {
+    int nint;   // 0 = empty
+    int r0, r1, c[4];
+};
+
+// Exact angular box of the square {C + a A + b B : |a|, |b| <= 1}.
+__device__ BoxOut angular_box(const double A[3], const double B[3], const double C[3], int H, int W,
+                              const double2 *__restrict__ col, const double2 *__restrict__ rlo,
+                              const double2 *__restrict__ rhi, double cm, double sm)
+{
+    BoxOut o;
+    o.nint = 0;
+    bool full_az = false, to_top = false, to_bottom = false;
+    double det = A[0] * B[1] - A[1] * B[0];
+    if (det == 0.0) {
+        full_az = to_top = to_bottom = true;
+    } else {
+        // where (if anywhere) the z-axis crosses the square's plane, in splat units
+        double a = (B[0] * C[1] - B[1] * C[0]) / det;
+        double b = (A[1] * C[0] - A[0] * C[1]) / det;
+        if (fabs(a) <= 1.0 + 1e-9 && fabs(b) <= 1.0 + 1e-9) {
+            double zp = (C[2] + a * A[2]) + b * B[2];
+            full_az = true;
+            to_top = zp >= 0.0;
+            to_bottom = zp <= 0.0;
+        }
+    }
+    double V[4][3];
+    const double sa[4] = {-1.0, 1.0, 1.0, -1.0};
+    const double sb[4] = {-1.0, -1.0, 1.0, 1.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) V[k][r] = (C[r] + sa[k] * A[r]) + sb[k] * B[r];
+
+    // elevation extremes over the boundary: vertices + one stationary point per edge
+    double rmax = 0, zmax = 0, rmin = 0, zmin = 0;
+    bool have = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double *P0 = V[k];
+        const double *P1 = V[(k + 1) & 3];
+        double dx = P1[0] - P0[0], dy = P1[1] - P0[1], dz = P1[2] - P0[2];
+        double qd = P0[0] * dx + P0[1] * dy;
+        double q2 = P0[0] * P0[0] + P0[1] * P0[1];
+        double d2 = dx * dx + dy * dy;
+        double den = dz * qd - P0[2] * d2;
+        double cx[2], cy[2], cz[2];
+        int nc = 1;
+        cx[0] = P0[0]; cy[0] = P0[1]; cz[0] = P0[2];
+        if (den != 0.0) {
+            double ts = (P0[2] * qd - dz * q2) / den;
+            if (ts > 0.0 && ts < 1.0) {
+                cx[1] = P0[0] + ts * dx; cy[1] = P0[1] + ts * dy; cz[1] = P0[2] + ts * dz;
+                nc = 2;
+            }
+        }
+        for (int c = 0; c < nc; ++c) {
+            double r = sqrt(cx[c] * cx[c] + cy[c] * cy[c]), z = cz[c];
+            if (!have) { rmax = rmin = r; zmax = zmin = z; have = true; continue; }
+            if (elev_below(rmax, zmax, r, z)) { rmax = r; zmax = z; }
+            if (elev_below(r, z, rmin, zmin)) { rmin = r; zmin = z; }
+        }
+    }
+    // rows: elevation decreases with the row index
+    int r0, r1;
+    if (to_top) {
+        r0 = 0;
+    } else {  // first row with el_i - margin <= el_max
+        int lo = 0, hi = H;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            double2 e = rlo[mid];
+            if (zmax * e.x - rmax * e.y >= 0.0) hi = mid; else lo = mid + 1;
+        }
+        r0 = lo;
+    }
+    if (to_bottom) {
+        r1 = H - 1;
+    } else {  // last row with el_i + margin >= el_min
+        int lo = 0, hi = H;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            double2 e = rhi[mid];
+            if (!(zmin * e.x - rmin * e.y <= 0.0)) hi = mid; else lo = mid + 1;
+        }
+        r1 = lo - 1;
+    }
+    if (r0 > r1) return o;
+    o.r0 = r0; o.r1 = r1;
+
+    if (!full_az) {
+        int klo = 0, khi = 0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            if (xcross(V[klo][0], V[klo][1], V[k][0], V[k][1]) < 0.0) klo = k;
+            if (xcross(V[khi][0], V[khi][1], V[k][0], V[k][1]) > 0.0) khi = k;
+        }
+        // widen the arc by the margin on both sides
+        double lx = V[klo][0] * cm + V[klo][1] * sm, ly = V[klo][1] * cm - V[klo][0] * sm;
+        double ux = V[khi][0] * cm - V[khi][1] * sm, uy = V[khi][0] * sm + V[khi][1] * cm;
+        if (!(xcross(lx, ly, ux, uy) > 0.0)) {
+            full_az = true;
+        } else {
+            int lo = 0, hi = W;  // first column with azimuth <= upper end
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                double2 d = col[mid];
+                if (angle_le(d.x, d.y, ux, uy)) hi = mid; else lo = mid + 1;
+            }
+            int jf = lo;
+            lo = 0; hi = W;      // last column with azimuth >= lower end
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                double2 d = col[mid];
+                if (!angle_le(lx, ly, d.x, d.y)) hi = mid; else lo = mid + 1;
+            }
+            int jl = lo - 1;
+            if (angle_le(lx, ly, ux, uy)) {
+                if (jf > jl) return o;
+                o.c[0] = jf; o.c[1] = jl; o.c[2] = -1; o.c[3] = -1;
+                o.nint = 1;
+                return o;
+            }
+            int m = 0;  // the arc crosses the seam
+            o.c[2] = -1; o.c[3] = -1;
+            if (jl >= 0) { o.c[0] = 0; o.c[1] = jl; m = 1; }
+            if (jf <= W - 1) { o.c[2 * m] = jf; o.c[2 * m + 1] = W - 1; ++m; }
+            o.nint = m;
+            return o;
+        }
+    }
+    o.c[0] = 0; o.c[1] = W - 1; o.c[2] = -1; o.c[3] = -1;
+    o.nint = 1;
+    return o;
+}
+
+__device__ inline void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ quats,
+          const float *__restrict__ lsc, const float *__restrict__ logits, const double *__restrict__ pose,
+          int H, int W, int th, int tw, double near_m, double cm, double sm,
+          const double2 *__restrict__ col, const double2 *__restrict__ rlo, const double2 *__restrict__ rhi,
+          RasterRec *__restrict__ rec, FrameRec *__restrict__ frame, PixBox *__restrict__ box,
+          uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    ids[k] = (uint32_t)k;
+    float fm0 = means[3 * k], fm1 = means[3 * k + 1], fm2 = means[3 * k + 2];
+    float4 fq = *reinterpret_cast<const float4 *>(quats + 4 * k);
+    float fl0 = lsc[2 * k], fl1 = lsc[2 * k + 1], flg = logits[k];
+    bool fin = isfinite(fm0) && isfinite(fm1) && isfinite(fm2) && isfinite(fq.x) && isfinite(fq.y) &&
+               isfinite(fq.z) && isfinite(fq.w) && isfinite(fl0) && isfinite(fl1) && isfinite(flg);
+    double w = fq.x, x = fq.y, y = fq.z, z = fq.w;
+    double qq = ((w * w + x * x) + y * y) + z * z;
+    bool ok = fin && qq > 0.0;
+    double R[9], t[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
+        t[e] = pose[4 * e + 3];
+    }
+    double A[3], B[3], C[3], N[3];
+    double range = 0.0;
+    if (ok) {
+        double qn = sqrt(qq);
+        w = w / qn; x = x / qn; y = y / qn; z = z / qn;
+        double ta[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
+        double tb[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
+        double tn[3] = {2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y)};
+        double s3a = 3.0 * box_exp((double)fl0), s3b = 3.0 * box_exp((double)fl1);
+        double Aw[3] = {s3a * ta[0], s3a * ta[1], s3a * ta[2]};
+        double Bw[3] = {s3b * tb[0], s3b * tb[1], s3b * tb[2]};
+        double m0 = fm0, m1 = fm1, m2 = fm2;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double *Rr = R + 3 * r;
+            A[r] = (Rr[0] * Aw[0] + Rr[1] * Aw[1]) + Rr[2] * Aw[2];
+            B[r] = (Rr[0] * Bw[0] + Rr[1] * Bw[1]) + Rr[2] * Bw[2];
+            C[r] = ((Rr[0] * m0 + Rr[1] * m1) + Rr[2] * m2) + t[r];
+            N[r] = (Rr[0] * tn[0] + Rr[1] * tn[1]) + Rr[2] * tn[2];
+        }
+        range = sqrt((C[0] * C[0] + C[1] * C[1]) + C[2] * C[2]);
+        ok = range > near_m;
+    }
+    BoxOut bx;
+    bx.nint = 0;
+    if (ok) bx = angular_box(A, B, C, H, W, col, rlo, rhi, cm, sm);
+    int32_t cnt = 0;
+    PixBox pb = {-1, -1, -1, -1, -1, -1, 0, 0};
+    if (bx.nint > 0) {
+        int ty0 = bx.r0 / th, ty1 = bx.r1 / th;
+        int ax0 = bx.c[0] / tw, ax1 = bx.c[1] / tw;
+        int nr = 1, bx0 = 0, bx1 = -1;
+        if (bx.nint == 2) {
+            bx0 = bx.c[2] / tw; bx1 = bx.c[3] / tw;
+            if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; }
+            else nr = 2;
+        }
+        cnt = (ax1 - ax0 + 1) * (ty1 - ty0 + 1);
+        if (nr == 2) cnt += (bx1 - bx0 + 1) * (ty1 - ty0 + 1);
+        pb.r0 = (int16_t)bx.r0; pb.r1 = (int16_t)bx.r1;
+        pb.c0 = (int16_t)bx.c[0]; pb.c1 = (int16_t)bx.c[1];
+        pb.c2 = (int16_t)(bx.nint == 2 ? bx.c[2] : -1); pb.c3 = (int16_t)(bx.nint == 2 ? bx.c[3] : -1);
+    }
+    counts[k] = cnt;
+    box[k] = pb;
+    if (cnt == 0) {
+        keys[k] = 0xFFFFFFFFu;
+        return;
+    }
+    float key = (float)range;
+    keys[k] = __float_as_uint(key);
+
+    // compositing record: b_alpha = A / 3, b_beta = B / 3, b_c = C
+    double ba[3] = {A[0] / 3.0, A[1] / 3.0, A[2] / 3.0};
+    double bb[3] = {B[0] / 3.0, B[1] / 3.0, B[2] / 3.0};
+    RasterRec rr;
+    cross3(bb, C, rr.P);
+    cross3(C, ba, rr.Q);
+    cross3(ba, bb, rr.M);
+    rr.tau = (float)((C[0] * rr.M[0] + C[1] * rr.M[1]) + C[2] * rr.M[2]);
+    rr.opac = 1.0f / (1.0f + expf(-flg));
+    rr.n[0] = (float)N[0]; rr.n[1] = (float)N[1]; rr.n[2] = (float)N[2];
+    rr.rows = (uint32_t)bx.r0 | ((uint32_t)bx.r1 << 16);
+    rec[k] = rr;
+    FrameRec fr;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) { fr.ba[r] = ba[r]; fr.bb[r] = bb[r]; fr.bc[r] = C[r]; fr.n[r] = (float)N[r]; }
+    fr.pad[0] = fr.pad[1] = fr.pad[2] = 0.0f;
+    frame[k] = fr;
+}
+
+}  // namespace
+
+void launch_project(const slr_surfels &s, const double *pose, const slr_sensor &sen, const Layout &L, char *ws,
+                    double cos_m, double sin_m, hipStream_t stream)
+{
+    if (s.n == 0) return;
+    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
+    const double2 *col = tab;
+    const double2 *rlo = tab + L.W + L.H;
+    const double2 *rhi = tab + L.W + 2 * L.H;
+    int blocks = (int)((s.n + 255) / 256);
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, stream, s.n, s.means, s.quats, s.log_scales, s.logits,
+                       pose, (int)L.H, (int)L.W, (int)L.th, (int)L.tw, sen.near_m, cos_m, sin_m, col, rlo, rhi,
+                       reinterpret_cast<RasterRec *>(ws + L.rec), reinterpret_cast<FrameRec *>(ws + L.frame),
+                       reinterpret_cast<PixBox *>(ws + L.box), reinterpret_cast<uint32_t *>(ws + L.skey),
+                       reinterpret_cast<uint32_t *>(ws + L.val0), reinterpret_cast<int32_t *>(ws + L.cnt));
+}
+
+}  // namespace slr

@@ -1,0 +1,404 @@
+// raster.hip -- per-tile front-to-back compositing and its reverse-order
+// backward (Sec. 3.2.1-3.2.2, Supp. D) on gfx950.
+//
+// One 256-thread workgroup per tile, one pixel per thread.  The tile's
+// range-sorted list is staged through LDS in batches; every wave reads each
+// staged record with broadcast LDS loads and skips, as a whole, records whose
+// pixel-row interval misses the wave's rows.
+//
+// Intersection (Cramer form of the plane-pair solve): with the FP64 pixel ray
+// v, a = P.v, b = Q.v, c = M.v give s_hat = (a, b) / c and the ray range
+// t = tau / c.  The three dot products run in FP64 (CDNA4 issues FP64 FMA at
+// the rate of unpacked FP32 FMA) because they cancel: far, small surfels
+// would otherwise lose most FP32 digits of s_hat.  Everything after them runs
+// in FP32.
+//
+// Backward: each pixel walks its list from the last contributor to the first,
+// recovering the transmittance before each pair by division, keeping the
+// suffix sums of the depth and normal channels, and forming the 14 per-pair
+// partials dL/dP, dL/dQ, dL/dM (each a multiple of v), dL/dtau, dL/do and
+// dL/dn.  They are summed over the wave with DPP row shifts and broadcasts,
+// then over the block's waves in LDS, and one thread per record converts the
+// sum to sensor-frame splat-axis gradients (FP64), adds the pose-gradient
+// contribution, rotates to the world frame and issues the atomics.
+#include "slr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace slr {
+namespace {
+
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -1 / (2 ln 2)
+
+struct PairEval {
+    float sa, sb, t, rc, G, alpha;
+    bool clamped;
+};
+
+// Shared by forward and backward so both take identical decisions.
+__device__ __forceinline__ bool eval_pair(const RasterRec &r, double vx, double vy, double vz, float near_m,
+                                          PairEval &e)
+{
+    const double a = fma(r.P[2], vz, fma(r.P[1], vy, r.P[0] * vx));
+    const double b = fma(r.Q[2], vz, fma(r.Q[1], vy, r.Q[0] * vx));
+    const double c = fma(r.M[2], vz, fma(r.M[1], vy, r.M[0] * vx));
+    const float af = (float)a, bf = (float)b, cf = (float)c;
+    const float lim = 3.0f * fabsf(cf);
+    if (!(fabsf(af) <= lim && fabsf(bf) <= lim && cf != 0.0f)) return false;
+    const float rc = __builtin_amdgcn_rcpf(cf);
+    const float t = r.tau * rc;
+    if (!(t > near_m)) return false;
+    const float sa = af * rc, sb = bf * rc;
+    const float q = fmaf(sa, sa, sb * sb);
+    const float G = __builtin_amdgcn_exp2f(kNegHalfLog2e * q);
+    const float ag = r.opac * G;
+    if (ag < kAlphaMin) return false;
+    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G;
+    e.clamped = ag > kAlphaMax;
+    e.alpha = e.clamped ? kAlphaMax : ag;
+    return true;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false);
+    return v + __int_as_float(s);
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63 (all lanes must be active).
+__device__ __forceinline__ float wave_sum_lane63(float v)
+{
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31
+    return v;
+}
+
+template <int TW>
+__global__ void __launch_bounds__(256)
+k_raster_fwd(const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+             const double2 *__restrict__ col, const double2 *__restrict__ rowc, int H, int W, int tiles_x,
+             float near_m, float *__restrict__ depth, float *__restrict__ normal, float *__restrict__ alpha,
+             float *__restrict__ stT, int32_t *__restrict__ stN, int32_t *__restrict__ census)
+{
+    constexpr int TH = 256 / TW;
+    __shared__ RasterRec srec[256];
+    const int tile = blockIdx.x;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = ty * TH + ly, j = tx * TW + lx;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wid = threadIdx.x >> 6;
+    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
+    int last = 0, n_eval = 0, n_con = 0;
+    bool done = !inside;
+    for (int b0 = rg.x; b0 < rg.y; b0 += 256) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int idx = b0 + threadIdx.x;
+        if (idx < rg.y) srec[threadIdx.x] = rec[pval[idx]];
+        __syncthreads();
+        const int cnt = min(256, rg.y - b0);
+        for (int k = 0; k < cnt; ++k) {
+            if (__all(done)) break;
+            const uint32_t rows = srec[k].rows;
+            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) continue;
+            if (done) continue;
+            ++n_eval;
+            PairEval e;
+            if (!eval_pair(srec[k], vx, vy, vz, near_m, e)) continue;
+            const float tT = T * (1.0f - e.alpha);
+            if (tT < kTMin) { done = true; continue; }
+            const float w = e.alpha * T;
+            D = fmaf(w, e.t, D);
+            N0 = fmaf(w, srec[k].n[0], N0);
+            N1 = fmaf(w, srec[k].n[1], N1);
+            N2 = fmaf(w, srec[k].n[2], N2);
+            O += w;
+            T = tT;
+            last = b0 + k + 1 - rg.x;
+            ++n_con;
+        }
+    }
+    if (inside) {
+        const int p = i * W + j;
+        census[p] = n_eval;
+        census[(size_t)H * W + p] = n_con;
+        depth[p] = D;
+        alpha[p] = O;
+        normal[3 * p] = N0; normal[3 * p + 1] = N1; normal[3 * p + 2] = N2;
+        stT[p] = T;
+        stN[p] = last;
+    }
+}
+
+constexpr int kBwdBatch = 128;
+constexpr int kNg = 14;
+
+__device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <int TW>
+__global__ void __launch_bounds__(256)
+k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval,
+             const int2 *__restrict__ ranges, const double2 *__restrict__ col, const double2 *__restrict__ rowc, int H,
+             int W, int tiles_x, float near_m, const float *__restrict__ stT, const int32_t *__restrict__ stN,
+             const float *__restrict__ gD, const float *__restrict__ gN, const float *__restrict__ gO,
+             const double *__restrict__ pose, float *__restrict__ acc, double *__restrict__ d_pose, int pose_only,
+             int32_t *__restrict__ census)
+{
+    constexpr int TH = 256 / TW;
+    __shared__ RasterRec srec[kBwdBatch];
+    __shared__ float sred[4][kNg][kBwdBatch];
+    __shared__ int sflag[4][kBwdBatch];
+    __shared__ int s_last;
+    __shared__ double s_pose[4][6];
+
+    const int tile = blockIdx.x;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = ty * TH + ly, j = tx * TW + lx;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    const int2 rg = ranges[tile];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int p = inside ? i * W + j : 0;
+    float T = inside ? stT[p] : 1.0f;
+    const int last = inside ? stN[p] : 0;
+    const float Tfin = T;
+    const float gd = (inside && gD) ? gD[p] : 0.0f;
+    const float go = (inside && gO) ? gO[p] : 0.0f;
+    const float gn0 = (inside && gN) ? gN[3 * p] : 0.0f;
+    const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
+    const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
+    if (threadIdx.x == 0) s_last = 0;
+    __syncthreads();
+    if (last > 0) atomicMax(&s_last, last);
+    __syncthreads();
+    const int end = rg.x + s_last;
+
+    double R[9];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
+    }
+    double pacc[6] = {0, 0, 0, 0, 0, 0};
+    float Bd = 0.0f, Bn0 = 0.0f, Bn1 = 0.0f, Bn2 = 0.0f;
+    int n_eval = 0, n_con = 0;
+
+    for (int b_end = end; b_end > rg.x; b_end -= kBwdBatch) {
+        const int b0 = max(rg.x, b_end - kBwdBatch);
+        const int cnt = b_end - b0;
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) srec[threadIdx.x] = rec[pval[b0 + threadIdx.x]];
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {
+            const uint32_t rows = srec[k].rows;
+            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) {
+                if (lane == 0) sflag[wid][k] = 0;
+                continue;
+            }
+            const int pos = b0 + k - rg.x;
+            float g[kNg];
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+            PairEval e;
+            n_eval += pos < last ? 1 : 0;
+            bool act = pos < last && eval_pair(srec[k], vx, vy, vz, near_m, e);
+            if (act) {
+                ++n_con;
+                const float n0 = srec[k].n[0], n1 = srec[k].n[1], n2 = srec[k].n[2];
+                const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+                const float A = T * r1;  // transmittance in front of this pair
+                float dA = gd * (e.t * A - Bd * r1);
+                dA += gn0 * (n0 * A - Bn0 * r1) + gn1 * (n1 * A - Bn1 * r1) + gn2 * (n2 * A - Bn2 * r1);
+                dA += go * Tfin * r1;
+                const float w = e.alpha * A;
+                Bd = fmaf(e.t, w, Bd);
+                Bn0 = fmaf(n0, w, Bn0); Bn1 = fmaf(n1, w, Bn1); Bn2 = fmaf(n2, w, Bn2);
+                T = A;
+                const float gt = gd * w;  // dL/d(range)
+                float dsa = 0.0f, dsb = 0.0f, dop = 0.0f;
+                if (!e.clamped) {
+                    const float f = -dA * e.alpha;
+                    dsa = f * e.sa; dsb = f * e.sb;
+                    dop = dA * e.G;
+                }
+                const float da = dsa * e.rc, db = dsb * e.rc;
+                const float dc = -(dsa * e.sa + dsb * e.sb + gt * e.t) * e.rc;
+                g[0] = da * fvx; g[1] = da * fvy; g[2] = da * fvz;
+                g[3] = db * fvx; g[4] = db * fvy; g[5] = db * fvz;
+                g[6] = dc * fvx; g[7] = dc * fvy; g[8] = dc * fvz;
+                g[9] = gt * e.rc;
+                g[10] = dop;
+                g[11] = gn0 * w; g[12] = gn1 * w; g[13] = gn2 * w;
+            }
+            if (__any(act)) {
+#pragma unroll
+                for (int v = 0; v < kNg; ++v) g[v] = wave_sum_lane63(g[v]);
+                if (lane == 63) {
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) sred[wid][v][k] = g[v];
+                    sflag[wid][k] = 1;
+                }
+            } else if (lane == 0) {
+                sflag[wid][k] = 0;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const int k = threadIdx.x;
+            float s[kNg];
+            bool any = false;
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) s[v] = 0.0f;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (sflag[w][k]) {
+                    any = true;
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) s[v] += sred[w][v][k];
+                }
+            }
+            if (any) {
+                const uint32_t id = pval[b0 + k];
+                const FrameRec fr = frame[id];
+                const RasterRec &rr = srec[k];
+                double dP[3] = {s[0], s[1], s[2]}, dQ[3] = {s[3], s[4], s[5]}, dM[3] = {s[6], s[7], s[8]};
+                const double dtau = s[9];
+                double t1[3], t2[3];
+                double ga[3], gb[3], gc[3];
+                dcross(dQ, fr.bc, t1); dcross(fr.bb, dM, t2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ga[c] = t1[c] + t2[c] + dtau * rr.P[c];
+                dcross(fr.bc, dP, t1); dcross(dM, fr.ba, t2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gb[c] = t1[c] + t2[c] + dtau * rr.Q[c];
+                dcross(dP, fr.bb, t1); dcross(fr.ba, dQ, t2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gc[c] = t1[c] + t2[c] + dtau * rr.M[c];
+                const double gn[3] = {s[11], s[12], s[13]};
+                const double nn[3] = {fr.n[0], fr.n[1], fr.n[2]};
+                // pose: d b / d rho = -I, d b / d phi = [b]_x
+                double c1[3], c2[3], c3[3], c4[3];
+                dcross(gc, fr.bc, c1); dcross(ga, fr.ba, c2); dcross(gb, fr.bb, c3); dcross(gn, nn, c4);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pacc[c] -= gc[c];
+                    pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
+                }
+                if (!pose_only) {
+                    float *a = acc + (size_t)id * kAccStride;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
+                        const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
+                        const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
+                        const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
+                        atomicAdd(a + c, (float)wa);
+                        atomicAdd(a + 3 + c, (float)wb);
+                        atomicAdd(a + 6 + c, (float)wc);
+                        atomicAdd(a + 9 + c, (float)wn);
+                    }
+                    atomicAdd(a + 12, s[10]);
+                }
+            }
+        }
+    }
+    if (inside) {
+        census[2 * (size_t)H * W + p] = n_eval;
+        census[3 * (size_t)H * W + p] = n_con;
+    }
+    // block reduction of the pose partials, then FP64 atomics
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double v = pacc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        pacc[c] = v;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s_pose[wid][c] = pacc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double v = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] +
+                         s_pose[3][threadIdx.x];
+        if (v != 0.0) atomicAdd(d_pose + threadIdx.x, v);
+    }
+}
+
+template <int TW>
+void fwd_launch(const Layout &L, const slr_sensor &sen, char *ws, float *depth, float *normal, float *alpha,
+                hipStream_t stream)
+{
+    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
+    const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    hipLaunchKernelGGL(k_raster_fwd<TW>, dim3((unsigned)L.ntiles), dim3(256), 0, stream,
+                       reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
+                       reinterpret_cast<const int2 *>(ws + L.ranges), tab, tab + L.W, (int)L.H, (int)L.W,
+                       (int)L.tiles_x, (float)sen.near_m, depth, normal, alpha,
+                       reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
+                       reinterpret_cast<int32_t *>(ws + L.census));
+}
+
+template <int TW>
+void bwd_launch(const Layout &L, const slr_sensor &sen, char *ws, const double *pose, const float *gD,
+                const float *gN, const float *gO, double *d_pose, bool pose_only, hipStream_t stream)
+{
+    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
+    const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.ntiles), dim3(256), 0, stream,
+                       reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
+                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), tab, tab + L.W, (int)L.H, (int)L.W,
+                       (int)L.tiles_x, (float)sen.near_m, reinterpret_cast<const float *>(ws + L.stateT),
+                       reinterpret_cast<const int32_t *>(ws + L.stateN), gD, gN, gO, pose,
+                       reinterpret_cast<float *>(ws + L.acc), d_pose, pose_only ? 1 : 0,
+                       reinterpret_cast<int32_t *>(ws + L.census));
+}
+
+}  // namespace
+
+void launch_raster_fwd(const Layout &L, const slr_sensor &sen, char *ws, int64_t K, float *depth, float *normal,
+                       float *alpha, hipStream_t stream)
+{
+    (void)K;
+    switch (L.tw) {
+    case 16: fwd_launch<16>(L, sen, ws, depth, normal, alpha, stream); break;
+    case 32: fwd_launch<32>(L, sen, ws, depth, normal, alpha, stream); break;
+    case 8: fwd_launch<8>(L, sen, ws, depth, normal, alpha, stream); break;
+    default: fwd_launch<64>(L, sen, ws, depth, normal, alpha, stream); break;
+    }
+}
+
+void launch_raster_bwd(const Layout &L, const slr_sensor &sen, char *ws, const double *pose, const float *gD,
+                       const float *gN, const float *gO, double *d_pose, bool pose_only, hipStream_t stream)
+{
+    switch (L.tw) {
+    case 16: bwd_launch<16>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
+    case 32: bwd_launch<32>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
+    case 8: bwd_launch<8>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
+    default: bwd_launch<64>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
+    }
+}
+
+}  // namespace slr

@@ -1,0 +1,90 @@
+// surfel_grad.hip -- per-surfel parameter gradients (Supp. D, last block).
+//
+// The compositing backward leaves, per surfel, the world-frame gradients
+//   w_a = dL/d(s_a t_a), w_b = dL/d(s_b t_b), w_c = dL/dmu, w_n = dL/dt_n,
+//   g_o = dL/do
+// summed over pixels (and over keyframes that share the surfel).  This kernel
+// maps them to the raw parameters: mean, unnormalised quaternion (through
+// R(q/|q|)), log-scales and opacity logit.
+#include "slr_internal.h"
+
+namespace slr {
+namespace {
+
+__global__ void __launch_bounds__(256)
+k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restrict__ lsc,
+              const float *__restrict__ logits, const int32_t *__restrict__ counts, const float *__restrict__ acc,
+              float *__restrict__ d_means, float *__restrict__ d_quats, float *__restrict__ d_ls,
+              float *__restrict__ d_logits, int accumulate)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float4 gq4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (counts[k] == 0) {
+        if (accumulate) return;
+        d_means[3 * k] = 0.f; d_means[3 * k + 1] = 0.f; d_means[3 * k + 2] = 0.f;
+        *reinterpret_cast<float4 *>(d_quats + 4 * k) = gq4;
+        d_ls[2 * k] = 0.f; d_ls[2 * k + 1] = 0.f;
+        d_logits[k] = 0.f;
+        return;
+    }
+    const float *a = acc + (size_t)k * kAccStride;
+    double wa[3] = {a[0], a[1], a[2]}, wb[3] = {a[3], a[4], a[5]}, wn[3] = {a[9], a[10], a[11]};
+    const float4 q4 = *reinterpret_cast<const float4 *>(quats + 4 * k);
+    const double qn = sqrt((double)q4.x * q4.x + (double)q4.y * q4.y + (double)q4.z * q4.z + (double)q4.w * q4.w);
+    const double w = q4.x / qn, x = q4.y / qn, y = q4.z / qn, z = q4.w / qn;
+    // columns of R(q): t_a, t_b
+    const double ta[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
+    const double tb[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
+    const double sa = exp((double)lsc[2 * k]), sb = exp((double)lsc[2 * k + 1]);
+    // dL/dR, column-wise: (s_a w_a, s_b w_b, w_n)
+    double G0[3], G1[3], G2[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) { G0[r] = sa * wa[r]; G1[r] = sb * wb[r]; G2[r] = wn[r]; }
+    // R entries as functions of (w, x, y, z); d/dw, d/dx, d/dy, d/dz of
+    //   col0 = (1-2(yy+zz), 2(xy+wz), 2(xz-wy))
+    //   col1 = (2(xy-wz), 1-2(xx+zz), 2(yz+wx))
+    //   col2 = (2(xz+wy), 2(yz-wx), 1-2(xx+yy))
+    const double gw = 2.0 * (z * G0[1] - y * G0[2] - z * G1[0] + x * G1[2] + y * G2[0] - x * G2[1]);
+    const double gx = 2.0 * (y * G0[1] + z * G0[2] + y * G1[0] - 2.0 * x * G1[1] + w * G1[2] + z * G2[0] -
+                             w * G2[1] - 2.0 * x * G2[2]);
+    const double gy = 2.0 * (-2.0 * y * G0[0] + x * G0[1] - w * G0[2] + x * G1[0] + z * G1[2] + w * G2[0] +
+                             z * G2[1] - 2.0 * y * G2[2]);
+    const double gz = 2.0 * (-2.0 * z * G0[0] + w * G0[1] + x * G0[2] - w * G1[0] - 2.0 * z * G1[1] + y * G1[2] +
+                             x * G2[0] + y * G2[1]);
+    const double dotq = gw * w + gx * x + gy * y + gz * z;
+    gq4.x = (float)((gw - dotq * w) / qn);
+    gq4.y = (float)((gx - dotq * x) / qn);
+    gq4.z = (float)((gy - dotq * y) / qn);
+    gq4.w = (float)((gz - dotq * z) / qn);
+    float gm[3] = {a[6], a[7], a[8]};
+    float gl0 = (float)(sa * (ta[0] * wa[0] + ta[1] * wa[1] + ta[2] * wa[2]));
+    float gl1 = (float)(sb * (tb[0] * wb[0] + tb[1] * wb[1] + tb[2] * wb[2]));
+    const double o = 1.0 / (1.0 + exp(-(double)logits[k]));
+    float go = (float)(o * (1.0 - o) * a[12]);
+    if (accumulate) {
+        const float4 p = *reinterpret_cast<const float4 *>(d_quats + 4 * k);
+        gq4.x += p.x; gq4.y += p.y; gq4.z += p.z; gq4.w += p.w;
+        gm[0] += d_means[3 * k]; gm[1] += d_means[3 * k + 1]; gm[2] += d_means[3 * k + 2];
+        gl0 += d_ls[2 * k]; gl1 += d_ls[2 * k + 1];
+        go += d_logits[k];
+    }
+    *reinterpret_cast<float4 *>(d_quats + 4 * k) = gq4;
+    d_means[3 * k] = gm[0]; d_means[3 * k + 1] = gm[1]; d_means[3 * k + 2] = gm[2];
+    d_ls[2 * k] = gl0; d_ls[2 * k + 1] = gl1;
+    d_logits[k] = go;
+}
+
+}  // namespace
+
+void launch_surfel_grad(const slr_surfels &s, const Layout &L, char *ws, float *d_means, float *d_quats,
+                        float *d_log_scales, float *d_logits, bool accumulate, hipStream_t stream)
+{
+    if (s.n == 0) return;
+    hipLaunchKernelGGL(k_surfel_grad, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, stream, s.n, s.quats,
+                       s.log_scales, s.logits, reinterpret_cast<const int32_t *>(ws + L.cnt),
+                       reinterpret_cast<const float *>(ws + L.acc), d_means, d_quats, d_log_scales, d_logits,
+                       accumulate ? 1 : 0);
+}
+
+}  // namespace slr

@@ -1,0 +1,283 @@
+"""Python binding of libslr.so (argument marshalling only).
+
+Every step of the render and its backward runs in the HIP library; PyTorch
+provides device memory and the current stream.  If the library is missing the
+import fails loudly: there is no fallback path.
+"""
+import ctypes as C
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslr.so")
+
+SLR_OK, SLR_E_INVALID, SLR_E_CAPACITY, SLR_E_HIP, SLR_E_UNSUPPORTED = 0, -1, -2, -3, -4
+SLR_POSE_ONLY = 1
+SLR_ACCUMULATE = 2
+NUM_STAGES = 8
+STAGES = ["project", "range_sort", "count_scan", "emit_tile_sort", "raster_fwd", "raster_bwd", "surfel_grad", "loss"]
+
+
+class Sensor(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("fu", C.c_double), ("cu", C.c_double),
+                ("fv", C.c_double), ("cv", C.c_double), ("near_m", C.c_double)]
+
+
+class Tiling(C.Structure):
+    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32)]
+
+
+class Surfels(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("quats", C.c_void_p), ("log_scales", C.c_void_p),
+                ("logits", C.c_void_p)]
+
+
+class Views(C.Structure):
+    _fields_ = [("keys", C.c_void_p), ("counts", C.c_void_p), ("pixbox", C.c_void_p), ("sorted_tile", C.c_void_p),
+                ("sorted_id", C.c_void_p), ("ranges", C.c_void_p), ("T_final", C.c_void_p), ("n_proc", C.c_void_p),
+                ("census", C.c_void_p), ("tiles_x", C.c_int64), ("tiles_y", C.c_int64)]
+
+
+EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
+           "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times", "slr_status_string", "slr_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.slr_camera_matrix.argtypes = [D, D, D, D, I32, I32, P]
+        L.slr_workspace_size.argtypes = [P, P, I64, I64, P]
+        L.slr_render.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P]
+        L.slr_backward.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
+        L.slr_workspace_views.argtypes = [P, P, I64, I64, P, C.c_size_t, P]
+        L.slr_loss_l1_normal.argtypes = [I64, P, P, P, P, C.c_float, C.c_float, P, P, P, P]
+        L.slr_stage_timer_enable.argtypes = [I32]
+        L.slr_stage_times.argtypes = [P, P]
+        L.slr_status_string.argtypes = [I32]
+        L.slr_status_string.restype = C.c_char_p
+        L.slr_last_error.restype = C.c_char_p
+        for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
+                  "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times"):
+            getattr(L, f).restype = I32
+        _lib = L
+    return _lib
+
+
+class SlrError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = lib().slr_last_error().decode()
+        super().__init__(f"{what}: {lib().slr_status_string(status).decode()}: {msg}")
+
+
+def _check(st, what):
+    if st != SLR_OK:
+        raise SlrError(st, what)
+
+
+def camera_matrix(az_min, az_max, el_min, el_max, H, W):
+    """(fu, cu, fv, cv) of the camera matrix K (Supp. A)."""
+    out = (C.c_double * 4)()
+    _check(lib().slr_camera_matrix(az_min, az_max, el_min, el_max, H, W, out), "slr_camera_matrix")
+    return tuple(out)
+
+
+def make_sensor(H, W, az=(-math.pi, math.pi), el=(math.radians(-25.0), math.radians(15.0)), near=0.2):
+    fu, cu, fv, cv = camera_matrix(az[0], az[1], el[0], el[1], H, W)
+    return dict(height=H, width=W, fu=fu, cu=cu, fv=fv, cv=cv, near=near)
+
+
+def _sensor(s):
+    return Sensor(int(s["height"]), int(s["width"]), float(s["fu"]), float(s["cu"]), float(s["fv"]),
+                  float(s["cv"]), float(s["near"]))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def workspace_size(sensor, tiling, n, capacity):
+    b = C.c_size_t(0)
+    s, t = _sensor(sensor), Tiling(*tiling)
+    _check(lib().slr_workspace_size(C.byref(s), C.byref(t), int(n), int(capacity), C.byref(b)), "slr_workspace_size")
+    return int(b.value)
+
+
+def _surfels(means, quats, log_scales, logits):
+    for name, t in (("means", means), ("quats", quats), ("log_scales", log_scales), ("logits", logits)):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return Surfels(means.shape[0], means.data_ptr(), quats.data_ptr(), log_scales.data_ptr(), logits.data_ptr())
+
+
+def _pose(T_cw):
+    if T_cw.dtype != torch.float64 or not T_cw.is_cuda or T_cw.shape != (4, 4) or not T_cw.is_contiguous():
+        raise ValueError("T_cw must be a contiguous float64 CUDA tensor of shape (4, 4)")
+    return T_cw
+
+
+class Renderer:
+    """One image's workspace; grows its pair capacity on demand (plain form)."""
+
+    def __init__(self, sensor, tiling=(16, 16), capacity=1 << 20, device="cuda"):
+        self.sensor = dict(sensor)
+        self.tiling = tuple(tiling)
+        self.capacity = int(capacity)
+        self.device = device
+        self.n = -1
+        self.ws = None
+        self.K = 0
+
+    def _ensure(self, n):
+        need = workspace_size(self.sensor, self.tiling, n, self.capacity)
+        if self.ws is None or self.ws.numel() < need or self.n != n:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self.n = n
+
+    def forward(self, means, quats, log_scales, logits, T_cw):
+        sf = _surfels(means, quats, log_scales, logits)
+        _pose(T_cw)
+        H, W = int(self.sensor["height"]), int(self.sensor["width"])
+        dev = means.device
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        normal = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+        s, t = _sensor(self.sensor), Tiling(*self.tiling)
+        for _ in range(3):
+            self._ensure(sf.n)
+            K = C.c_int64(0)
+            st = lib().slr_render(C.byref(sf), _ptr(T_cw), C.byref(s), C.byref(t), _ptr(self.ws), self.ws.numel(),
+                                  self.capacity, _ptr(depth), _ptr(normal), _ptr(alpha), C.byref(K), _stream())
+            if st == SLR_E_CAPACITY:
+                self.capacity = int(K.value * 1.25) + 1024
+                self.ws = None
+                continue
+            _check(st, "slr_render")
+            self.K = int(K.value)
+            return depth, normal, alpha
+        raise SlrError(SLR_E_CAPACITY, "slr_render")
+
+    def backward(self, means, quats, log_scales, logits, T_cw, dL_dD, dL_dN, dL_dO, pose_only=False,
+                 want_pose=True, out=None):
+        """Gradients of the last render.  out=(grads dict, dpose) adds into
+        existing buffers (SLR_ACCUMULATE) instead of allocating new ones."""
+        sf = _surfels(means, quats, log_scales, logits)
+        _pose(T_cw)
+        for name, g in (("dL_ddepth", dL_dD), ("dL_dnormal", dL_dN), ("dL_dalpha", dL_dO)):
+            if g is not None and (g.dtype != torch.float32 or not g.is_contiguous()):
+                raise ValueError(f"{name} must be contiguous float32")
+        n = sf.n
+        dev = means.device
+        g = None
+        flags = SLR_POSE_ONLY if pose_only else 0
+        if out is not None:
+            g, dpose = out
+            flags |= SLR_ACCUMULATE
+        else:
+            if not pose_only:
+                g = dict(means=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                         quats=torch.empty((n, 4), dtype=torch.float32, device=dev),
+                         log_scales=torch.empty((n, 2), dtype=torch.float32, device=dev),
+                         logits=torch.empty((n,), dtype=torch.float32, device=dev))
+            dpose = torch.empty(6, dtype=torch.float64, device=dev) if (want_pose or pose_only) else None
+        s, t = _sensor(self.sensor), Tiling(*self.tiling)
+        st = lib().slr_backward(C.byref(sf), _ptr(T_cw), C.byref(s), C.byref(t), _ptr(self.ws), self.ws.numel(),
+                                self.capacity, _ptr(dL_dD), _ptr(dL_dN), _ptr(dL_dO),
+                                _ptr(g["means"]) if g else None, _ptr(g["quats"]) if g else None,
+                                _ptr(g["log_scales"]) if g else None, _ptr(g["logits"]) if g else None,
+                                _ptr(dpose), flags, _stream())
+        _check(st, "slr_backward")
+        return g, dpose
+
+    def views(self):
+        """Copies of the binning results and per-pixel state of the last render."""
+        v = Views()
+        s, t = _sensor(self.sensor), Tiling(*self.tiling)
+        _check(lib().slr_workspace_views(C.byref(s), C.byref(t), self.n, self.capacity, _ptr(self.ws),
+                                         self.ws.numel(), C.byref(v)), "slr_workspace_views")
+        base = self.ws.data_ptr()
+        H, W = int(self.sensor["height"]), int(self.sensor["width"])
+
+        def take(ptr, count, dtype):
+            off = ptr - base
+            nbytes = count * torch.tensor([], dtype=dtype).element_size()
+            return self.ws[off:off + nbytes].view(dtype).clone()
+
+        n, K = self.n, self.K
+        nt = int(v.tiles_x * v.tiles_y)
+        return dict(keys=take(v.keys, n, torch.int32), counts=take(v.counts, n, torch.int32),
+                    pixbox=take(v.pixbox, 8 * n, torch.int16).view(n, 8),
+                    sorted_tile=take(v.sorted_tile, K, torch.int32), sorted_id=take(v.sorted_id, K, torch.int32),
+                    ranges=take(v.ranges, 2 * nt, torch.int32).view(nt, 2),
+                    T_final=take(v.T_final, H * W, torch.float32).view(H, W),
+                    n_proc=take(v.n_proc, H * W, torch.int32).view(H, W),
+                    census=take(v.census, 4 * H * W, torch.int32).view(4, H, W), tiles_x=int(v.tiles_x),
+                    tiles_y=int(v.tiles_y), K=K)
+
+
+def loss_l1_normal(D, N, Dt, Nt, w_d, w_n, gD, gN, loss=None):
+    """Fused range + normal loss and its gradients (writes gD, gN; adds to loss)."""
+    P = D.numel()
+    _check(lib().slr_loss_l1_normal(P, _ptr(D), _ptr(N), _ptr(Dt), _ptr(Nt), float(w_d), float(w_n), _ptr(gD),
+                                    _ptr(gN), _ptr(loss), _stream()), "slr_loss_l1_normal")
+
+
+def stage_timer(on):
+    _check(lib().slr_stage_timer_enable(1 if on else 0), "slr_stage_timer_enable")
+
+
+def stage_times():
+    """{stage: (ms, launches)} accumulated since the last call (synchronises)."""
+    ms = (C.c_double * NUM_STAGES)()
+    n = (C.c_int64 * NUM_STAGES)()
+    _check(lib().slr_stage_times(ms, n), "slr_stage_times")
+    return {STAGES[k]: (ms[k], n[k]) for k in range(NUM_STAGES)}
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, quats, log_scales, logits, xi, T_cw, renderer):
+        D, N, O = renderer.forward(means, quats, log_scales, logits, T_cw)
+        ctx.save_for_backward(means, quats, log_scales, logits, T_cw)
+        ctx.renderer = renderer
+        ctx.surfel_grad = any(ctx.needs_input_grad[:4])
+        return D, N, O
+
+    @staticmethod
+    def backward(ctx, gD, gN, gO):
+        means, quats, log_scales, logits, T_cw = ctx.saved_tensors
+        r = ctx.renderer
+        gD = None if gD is None else gD.contiguous().float()
+        gN = None if gN is None else gN.contiguous().float()
+        gO = None if gO is None else gO.contiguous().float()
+        want_pose = ctx.needs_input_grad[4]
+        g, dpose = r.backward(means, quats, log_scales, logits, T_cw, gD, gN, gO,
+                              pose_only=not ctx.surfel_grad, want_pose=want_pose)
+        if g is None:
+            return None, None, None, None, dpose, None, None
+        return g["means"], g["quats"], g["log_scales"], g["logits"], (dpose if want_pose else None), None, None
+
+
+def render(means, quats, log_scales, logits, T_cw, renderer, xi=None):
+    """Differentiable render -> (depth [H,W], normal [H,W,3], alpha [H,W]).
+
+    T_cw: float64 [4,4] CUDA tensor (world -> sensor).  xi: optional float64
+    [6] CUDA leaf standing for the local pose perturbation delta = (rho; phi)
+    of T_wc <- T_wc exp(delta), taken at delta = 0; its .grad is dL/ddelta.
+    """
+    if xi is None:
+        xi = torch.zeros(6, dtype=torch.float64, device=means.device)
+    return _RenderFn.apply(means, quats, log_scales, logits, xi, T_cw, renderer)

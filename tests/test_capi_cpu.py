@@ -1,0 +1,117 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol declared in include/slr.h, and rejects bad arguments on the host
+before enqueuing anything."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import slr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "slr.h")).read()
+    return sorted(set(re.findall(r"\b(slr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    L = slr.lib()
+    names = declared_symbols()
+    assert "slr_render" in names and "slr_backward" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(slr.EXPORTS) == set(names)
+
+
+def test_camera_matrix_matches_oracle():
+    for (H, W, az, el) in [(64, 512, (-math.pi, math.pi), (-25, 15)), (32, 1800, (-1.2, 1.7), (-10, 30))]:
+        a = slr.camera_matrix(az[0], az[1], math.radians(el[0]), math.radians(el[1]), H, W)
+        b = O.camera_matrix(az[0], az[1], math.radians(el[0]), math.radians(el[1]), H, W)
+        assert a == b
+
+
+def test_workspace_size_and_validation():
+    s = slr.make_sensor(128, 1024)
+    n = slr.workspace_size(s, (16, 16), 1000, 5000)
+    assert n > 1000 * 96
+    assert slr.workspace_size(s, (16, 16), 0, 0) > 0
+    with pytest.raises(slr.SlrError) as e:
+        slr.workspace_size(s, (16, 8), 10, 10)
+    assert e.value.status == slr.SLR_E_INVALID
+    bad = dict(s, fu=-s["fu"])
+    with pytest.raises(slr.SlrError):
+        slr.workspace_size(bad, (16, 16), 10, 10)
+    pole = slr.make_sensor(64, 512, el=(math.radians(-89.5), math.radians(10)))
+    with pytest.raises(slr.SlrError) as e:
+        slr.workspace_size(pole, (16, 16), 10, 10)
+    assert "89" in str(e.value)
+
+
+def _args(n=4):
+    s = slr._sensor(slr.make_sensor(64, 512))
+    t = slr.Tiling(16, 16)
+    buf = np.zeros(1 << 16, np.uint8)
+    return s, t, buf
+
+
+def test_render_rejects_bad_arguments_without_gpu():
+    L = slr.lib()
+    s, t, buf = _args()
+    arr = np.zeros(64, np.float32)
+    p = C.c_void_p(arr.ctypes.data)
+    sf = slr.Surfels(4, p, p, p, p)
+    pose = np.zeros(16)
+    out = np.zeros(64 * 512 * 3, np.float32)
+    o = C.c_void_p(out.ctypes.data)
+    # NULL pose
+    st = L.slr_render(C.byref(sf), None, C.byref(s), C.byref(t), C.c_void_p(buf.ctypes.data), buf.size, 100,
+                      o, o, o, None, None)
+    assert st == slr.SLR_E_INVALID
+    # negative count
+    sf_bad = slr.Surfels(-1, p, p, p, p)
+    st = L.slr_render(C.byref(sf_bad), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t),
+                      C.c_void_p(buf.ctypes.data), buf.size, 100, o, o, o, None, None)
+    assert st == slr.SLR_E_INVALID
+    # workspace too small
+    ws = np.zeros(1024 + 256, np.uint8)
+    wp = ws.ctypes.data + (-ws.ctypes.data) % 256
+    st = L.slr_render(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t), C.c_void_p(wp), 1024,
+                      100, o, o, o, None, None)
+    assert st == slr.SLR_E_INVALID
+    assert b"needs" in L.slr_last_error()
+    # unsupported tile shape
+    t_bad = slr.Tiling(8, 8)
+    st = L.slr_render(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t_bad), C.c_void_p(wp), 1024,
+                      100, o, o, o, None, None)
+    assert st == slr.SLR_E_INVALID
+
+
+def test_backward_rejects_inconsistent_gradient_outputs():
+    L = slr.lib()
+    s, t, buf = _args()
+    arr = np.zeros(64, np.float32)
+    p = C.c_void_p(arr.ctypes.data)
+    sf = slr.Surfels(4, p, p, p, p)
+    pose = np.zeros(16)
+    g = np.zeros(64, np.float32)
+    gp = C.c_void_p(g.ctypes.data)
+    big = np.zeros(1 << 24, np.uint8)
+    wp = big.ctypes.data + (-big.ctypes.data) % 256
+    # only some surfel gradients set
+    st = L.slr_backward(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t), C.c_void_p(wp),
+                        big.size - 256, 100, None, None, None, gp, None, None, None, None, 0, None)
+    assert st == slr.SLR_E_INVALID
+    # pose-only with surfel gradients
+    st = L.slr_backward(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t), C.c_void_p(wp),
+                        big.size - 256, 100, None, None, None, gp, gp, gp, gp, gp, slr.SLR_POSE_ONLY, None)
+    assert st == slr.SLR_E_INVALID
+    # unknown flag
+    st = L.slr_backward(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t), C.c_void_p(wp),
+                        big.size - 256, 100, None, None, None, None, None, None, None, gp, 8, None)
+    assert st == slr.SLR_E_INVALID

@@ -1,0 +1,312 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+* Binning (keys, tile counts, pixel boxes, sorted (tile, surfel) lists, tile
+  ranges): bit-exact.
+* Forward: relative 1e-4 on depth / alpha / normal on every pixel outside the
+  oracle's guard band (pairs within rounding distance of a decision); the
+  flagged fraction is bounded and flagged pixels are checked for validity.
+* Backward: relative 1e-3 on per-surfel gradient blocks and on the pose
+  6-vector, against the oracle's analytic FP64 gradients.
+Large configurations compare sampled pixels (forward) or use upstream
+gradients that are non-zero only on sampled pixels (backward).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+EXCL = O.FLAG_SUPPORT | O.FLAG_NEAR | O.FLAG_AMIN | O.FLAG_TSTOP
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def slr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_17491_amd import slr as S
+    S.lib()
+    return S
+
+
+def to_dev(sc):
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in sc.items()}
+
+
+def pose_dev(T):
+    return torch.from_numpy(np.ascontiguousarray(T, dtype=np.float64)).to(DEV)
+
+
+def gpu_render(S, sc, T, sensor, tiling=(16, 16), capacity=1 << 16):
+    r = S.Renderer(sensor, tiling, capacity)
+    d = to_dev(sc)
+    Td = pose_dev(T)
+    D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+    torch.cuda.synchronize()
+    return r, d, Td, D.cpu().numpy().astype(np.float64), N.cpu().numpy().astype(np.float64), \
+        A.cpu().numpy().astype(np.float64)
+
+
+def assert_forward_close(D, N, A, ref, pix=None, max_flagged=0.01):
+    """ref: oracle dict on the pixel list `pix` (or the full image)."""
+    if pix is not None:
+        D, A, N = D[pix[:, 0], pix[:, 1]], A[pix[:, 0], pix[:, 1]], N[pix[:, 0], pix[:, 1]]
+    else:
+        D, A, N = D.reshape(-1), A.reshape(-1), N.reshape(-1, 3)
+    rD, rA, rN = ref["depth"].reshape(-1), ref["alpha"].reshape(-1), ref["normal"].reshape(-1, 3)
+    fl = ref["flags"].reshape(-1)
+    ok = (fl & EXCL) == 0
+    assert (~ok).mean() <= max_flagged, f"flagged fraction {(~ok).mean()}"
+    eD = np.abs(D - rD) / np.maximum(np.abs(rD), 1.0)
+    eA = np.abs(A - rA) / np.maximum(rA, 1e-2)
+    eN = np.linalg.norm(N - rN, axis=1) / np.maximum(np.linalg.norm(rN, axis=1), 1e-2)
+    say(f"pixels {ok.size}, flagged {int((~ok).sum())}, max err depth {eD[ok].max():.2e} alpha {eA[ok].max():.2e} "
+        f"normal {eN[ok].max():.2e}")
+    assert eD[ok].max() <= 1e-4
+    assert eA[ok].max() <= 1e-4
+    assert eN[ok].max() <= 1e-4
+    # flagged pixels: still valid compositing results
+    assert (A >= -1e-6).all() and (A <= 1 + 1e-6).all()
+    assert (np.linalg.norm(N, axis=1) <= A + 1e-5).all()
+
+
+# ---------------------------------------------------------------- binning
+BIN_CASES = [
+    ("shell-2k-64x512", lambda: synth.shell_scene(2000, 1), lambda: np.eye(4), (64, 512), (16, 16)),
+    ("shell-2k-64x512-8x32", lambda: synth.shell_scene(2000, 1), lambda: np.eye(4), (64, 512), (8, 32)),
+    ("shell-5k-posed-4x64", lambda: synth.shell_scene(5000, 4), lambda: synth.perturbed_pose(4, 1.0, 30.0),
+     (32, 1800), (4, 64)),
+    ("structured-20k-posed-32x8", lambda: synth.structured_scene(20000, 8)[0], lambda: synth.circle_poses(8, 3)[5],
+     (128, 1024), (32, 8)),
+    ("ragged-37x300", lambda: synth.shell_scene(3000, 9), lambda: np.eye(4), (37, 300), (16, 16)),
+]
+
+
+@pytest.mark.parametrize("name,mk,mkT,hw,tiling", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_binning_bit_exact(slr, name, mk, mkT, hw, tiling):
+    say("binning", name)
+    sc, T = mk(), mkT()
+    sensor = O.make_sensor(*hw)
+    ssensor = slr.make_sensor(*hw)
+    assert ssensor == sensor
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, ssensor, tiling)
+    v = r.views()
+    ref = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, tiling[0], tiling[1])
+    cnt = v["counts"].cpu().numpy()
+    np.testing.assert_array_equal(cnt, ref["counts"])
+    vis = cnt > 0
+    np.testing.assert_array_equal(v["keys"].cpu().numpy().view(np.uint32)[vis], ref["keys"][vis])
+    np.testing.assert_array_equal(v["pixbox"].cpu().numpy()[vis, :6].astype(np.int32), ref["pixbox"][vis])
+    assert v["K"] == ref["K"]
+    np.testing.assert_array_equal(v["sorted_tile"].cpu().numpy(), ref["sorted_tile"])
+    np.testing.assert_array_equal(v["sorted_id"].cpu().numpy(), ref["sorted_id"])
+    np.testing.assert_array_equal(v["ranges"].cpu().numpy(), ref["ranges"])
+    say("binning", name, "K", ref["K"], "visible", int(vis.sum()))
+
+
+# ---------------------------------------------------------------- forward
+def test_forward_parity_shell_full_image(slr):
+    say("forward shell-2k-64x512 full image")
+    sc = synth.shell_scene(2000, 1)
+    sensor = slr.make_sensor(64, 512)
+    r, d, Td, D, N, A = gpu_render(slr, sc, np.eye(4), sensor)
+    ref = O.render_image(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), sensor)
+    assert_forward_close(D, N, A, ref)
+    v = r.views()
+    ok = (ref["flags"] & EXCL) == 0
+    np.testing.assert_allclose(v["T_final"].cpu().numpy()[ok], ref["T_final"][ok], rtol=1e-4, atol=1e-6)
+
+
+def test_forward_parity_posed_structured(slr):
+    say("forward structured-30k-posed-128x1024 full image")
+    sc, _ = synth.structured_scene(30000, 12)
+    T = synth.circle_poses(8, 0)[3]
+    sensor = slr.make_sensor(128, 1024)
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, (8, 32))
+    ref = O.render_image(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor)
+    assert_forward_close(D, N, A, ref)
+
+
+def test_forward_identical_across_tilings_and_runs(slr):
+    say("forward tiling invariance")
+    sc = synth.shell_scene(4000, 2)
+    sensor = slr.make_sensor(64, 512)
+    outs = []
+    for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16)]:
+        _, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling)
+        outs.append((D, N, A))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_forward_parity_fullsize_sampled(slr):
+    """200k surfels on the structured scene at 128x1024 (the fwd+bwd workload)."""
+    say("forward structured-200k-128x1024 sampled")
+    sc, _ = synth.structured_scene(200000, 2)
+    sensor = slr.make_sensor(128, 1024)
+    r, d, Td, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, (16, 16), 1 << 20)
+    g = np.random.default_rng(0)
+    pix = np.stack([g.integers(0, 128, 600), g.integers(0, 1024, 600)], 1).astype(np.int32)
+    # plus every pixel of one tile at the horizon and one at the seam
+    ii, jj = np.meshgrid(np.arange(48, 64), np.arange(0, 16), indexing="ij")
+    pix = np.concatenate([pix, np.stack([ii.ravel(), jj.ravel()], 1).astype(np.int32)])
+    ref = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), sensor, pix)
+    assert_forward_close(D, N, A, ref, pix)
+
+
+# ---------------------------------------------------------------- backward
+def block_err(g, ref):
+    """max over surfels of |g - ref| / max(|ref|, 1e-3 * RMS(ref)) per parameter block."""
+    g, ref = g.reshape(g.shape[0], -1), ref.reshape(ref.shape[0], -1)
+    rms = math.sqrt(float((ref ** 2).sum(1).mean())) + 1e-30
+    den = np.maximum(np.linalg.norm(ref, axis=1), 1e-3 * rms)
+    return float((np.linalg.norm(g - ref, axis=1) / den).max())
+
+
+def check_backward(slr, sc, T, sensor, pix, gD, gN, gO, tiling=(16, 16), capacity=1 << 16):
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, tiling, capacity)
+    H, W = sensor["height"], sensor["width"]
+    GD = np.zeros((H, W), np.float32); GN = np.zeros((H, W, 3), np.float32); GO = np.zeros((H, W), np.float32)
+    GD[pix[:, 0], pix[:, 1]] = gD; GN[pix[:, 0], pix[:, 1]] = gN; GO[pix[:, 0], pix[:, 1]] = gO
+    g, dpose = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td,
+                          torch.from_numpy(GD).to(DEV), torch.from_numpy(GN).to(DEV), torch.from_numpy(GO).to(DEV))
+    torch.cuda.synchronize()
+    ref = O.backward_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix,
+                            gD.astype(np.float64), gN.astype(np.float64), gO.astype(np.float64))
+    errs = {k: block_err(g[k].cpu().numpy().astype(np.float64), ref[k]) for k in ("means", "quats", "log_scales",
+                                                                                 "logits")}
+    dp = dpose.cpu().numpy()
+    errs["pose"] = float(np.linalg.norm(dp - ref["pose"]) / max(np.linalg.norm(ref["pose"]), 1e-12))
+    say("backward errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-3, (k, v)
+    return r, d, Td, g, dpose
+
+
+def clean_pixels(sc, T, sensor, pix=None):
+    """Pixels whose oracle decisions are away from every threshold (incl. the alpha clamp)."""
+    ref = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix)
+    keep = (ref["flags"] & (EXCL | O.FLAG_CLAMP)) == 0
+    p = O.all_pixels(sensor) if pix is None else pix
+    return p[keep]
+
+
+def test_backward_parity_shell_full_image(slr):
+    say("backward shell-2k-64x512 all pixels")
+    sc = synth.shell_scene(2000, 1)
+    sensor = slr.make_sensor(64, 512)
+    T = synth.perturbed_pose(1, 0.3, 5.0)
+    pix = clean_pixels(sc, T, sensor)
+    g = np.random.default_rng(1)
+    P = pix.shape[0]
+    check_backward(slr, sc, T, sensor, pix, g.normal(size=P).astype(np.float32),
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32))
+
+
+def test_backward_parity_structured_posed(slr):
+    say("backward structured-20k-posed-64x512 all pixels, 8x32 tiles")
+    sc, _ = synth.structured_scene(20000, 5)
+    sensor = slr.make_sensor(64, 512)
+    T = synth.circle_poses(8, 1)[2]
+    pix = clean_pixels(sc, T, sensor)
+    g = np.random.default_rng(2)
+    P = pix.shape[0]
+    check_backward(slr, sc, T, sensor, pix, g.normal(size=P).astype(np.float32),
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (8, 32))
+
+
+def test_backward_parity_fullsize_sparse(slr):
+    say("backward structured-200k-128x1024 sparse upstream")
+    sc, _ = synth.structured_scene(200000, 2)
+    sensor = slr.make_sensor(128, 1024)
+    g = np.random.default_rng(3)
+    pix = np.unique(np.stack([g.integers(0, 128, 500), g.integers(0, 1024, 500)], 1).astype(np.int32), axis=0)
+    pix = clean_pixels(sc, np.eye(4), sensor, pix)
+    P = pix.shape[0]
+    check_backward(slr, sc, np.eye(4), sensor, pix, g.normal(size=P).astype(np.float32),
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (16, 16), 1 << 20)
+
+
+def test_pose_only_matches_full_backward(slr):
+    say("backward pose-only vs full")
+    sc = synth.shell_scene(3000, 6)
+    sensor = slr.make_sensor(64, 512)
+    T = synth.perturbed_pose(2, 0.5, 3.0)
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor)
+    gD = torch.randn(64, 512, device=DEV)
+    _, p_full = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, gD, None, None)
+    g_none, p_only = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, gD, None, None,
+                                pose_only=True)
+    assert g_none is None
+    np.testing.assert_allclose(p_only.cpu().numpy(), p_full.cpu().numpy(), rtol=1e-6)
+
+
+def test_autograd_function(slr):
+    say("autograd wrapper")
+    sc = synth.shell_scene(1500, 7)
+    sensor = slr.make_sensor(64, 512)
+    d = to_dev(sc)
+    for k in d:
+        d[k].requires_grad_(True)
+    Td = pose_dev(synth.perturbed_pose(3))
+    xi = torch.zeros(6, dtype=torch.float64, device=DEV, requires_grad=True)
+    r = slr.Renderer(sensor)
+    D, N, A = slr.render(d["means"], d["quats"], d["log_scales"], d["logits"], Td, r, xi)
+    w = torch.randn_like(D)
+    loss = (D * w).sum() + N.sum() + A.sum()
+    loss.backward()
+    g, dp = r.backward(d["means"].detach(), d["quats"].detach(), d["log_scales"].detach(), d["logits"].detach(), Td,
+                       w, torch.ones_like(N), torch.ones_like(A))
+    for k in ("means", "quats", "log_scales", "logits"):
+        np.testing.assert_allclose(d[k].grad.cpu().numpy(), g[k].cpu().numpy(), rtol=1e-4, atol=1e-5)
+    np.testing.assert_allclose(xi.grad.cpu().numpy(), dp.cpu().numpy(), rtol=1e-6)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_cases(slr):
+    say("edge: empty, all culled, capacity overflow")
+    sensor = slr.make_sensor(64, 512)
+    empty = {k: v[:0] for k, v in synth.shell_scene(1, 0).items()}
+    r, d, Td, D, N, A = gpu_render(slr, empty, np.eye(4), sensor)
+    assert not D.any() and not A.any() and not N.any()
+    g, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, torch.ones(64, 512, device=DEV),
+                       None, None)
+    assert g["means"].numel() == 0 and not dp.cpu().numpy().any()
+    # every surfel culled: inside the near range or non-finite
+    sc = synth.shell_scene(50, 3)
+    sc["means"][:] = 0.05
+    sc["logits"][0] = np.nan
+    r, d, Td, D, N, A = gpu_render(slr, sc, np.eye(4), sensor)
+    assert not D.any() and r.K == 0
+    g, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, torch.ones(64, 512, device=DEV),
+                       None, None)
+    assert not g["means"].cpu().numpy().any()
+    # capacity overflow: explicit status with the needed K, then the renderer grows and succeeds
+    sc = synth.shell_scene(2000, 1)
+    ref = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), sensor)
+    r = slr.Renderer(sensor, (16, 16), capacity=16)
+    dd = to_dev(sc)
+    D, N, A = r.forward(dd["means"], dd["quats"], dd["log_scales"], dd["logits"], pose_dev(np.eye(4)))
+    assert r.K == ref["K"] and r.capacity >= ref["K"]
+    import ctypes as C
+    s, t = slr._sensor(sensor), slr.Tiling(16, 16)
+    sf = slr._surfels(dd["means"], dd["quats"], dd["log_scales"], dd["logits"])
+    ws = torch.empty(slr.workspace_size(sensor, (16, 16), 2000, 10), dtype=torch.uint8, device=DEV)
+    K = C.c_int64(0)
+    Tp = pose_dev(np.eye(4))
+    st = slr.lib().slr_render(C.byref(sf), C.c_void_p(Tp.data_ptr()), C.byref(s), C.byref(t),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), 10, C.c_void_p(D.data_ptr()),
+                              C.c_void_p(N.data_ptr()), C.c_void_p(A.data_ptr()), C.byref(K), slr._stream())
+    assert st == slr.SLR_E_CAPACITY and K.value == ref["K"]
