@@ -73,6 +73,21 @@ def plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss):
                        out=(grads, dposes[k]))
 
 
+def make_batch(torch, slr, d, sensor, kfs, tiling):
+    frames = [dict(set=0, T_cw=kf["T"], sensor=sensor) for kf in kfs]
+    br = slr.BatchRenderer([d], frames, tiling, capacity=24 << 20)
+    return br
+
+
+def batched_step(slr, br, kfs, loss):
+    br.render()
+    for k, kf in enumerate(kfs):
+        D, N, _ = br.out[k]
+        gD, gN, _ = br.up[k]
+        slr.loss_l1_normal(D, N, kf["Dt"], kf["Nt"], kf["w"], kf["w"], gD, gN, loss)
+    br.backward()
+
+
 def cpu_baseline(sc, sensor, kfs, budget_s):
     """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
     import numpy as np
@@ -108,7 +123,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["plain"], default="plain")
+    ap.add_argument("--form", choices=["batched", "plain"], default="batched",
+                    help="form whose iter/s is reported as value (both are always timed)")
+    ap.add_argument("--no-graph", action="store_true", help="batched form without HIP-graph capture")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -132,34 +149,71 @@ def main():
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
 
+    # ---- plain form: per-keyframe launches, one host sync per keyframe for the pair count
     for _ in range(args.warmup):
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
     torch.cuda.synchronize()
-    log("warmup done; pairs per keyframe:", [r.K for r in rend])
-
-    slr.stage_timer(True)
-    slr.stage_times()
-    torch.cuda.synchronize()
+    log("plain warmup done; pairs per keyframe:", [r.K for r in rend])
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = slr.stage_times()
-    slr.stage_timer(False)
-    dt = t1 - t0
-    iters = args.steps / dt
-    log(f"timed {args.steps} steps in {dt:.3f}s -> {iters:.2f} iter/s")
-
-    # census of the compositing work of the last step (outside the timed region)
+    plain_dt = time.perf_counter() - t0
+    plain_iters = args.steps / plain_dt
+    log(f"plain: {args.steps} steps in {plain_dt:.3f}s -> {plain_iters:.2f} iter/s")
     ef = cf = eb = cb = 0
-    for r in rend:
+    for r in rend:  # compositing work census (identical in both forms)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
         ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
+    pairs = int(sum(r.K for r in rend))
+    del rend
+    torch.cuda.empty_cache()
+
+    # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
+    br = make_batch(torch, slr, d, sensor, kfs, (th, tw))
+    batched_step(slr, br, kfs, loss)
+    if br.ensure_capacity():
+        batched_step(slr, br, kfs, loss)
+    K, over = br.pairs()
+    assert over == 0 and K == pairs, (K, over, pairs)
+    # per-kernel durations: HIP events on the launch stream (batched launches, no graph)
+    slr.stage_timer(True)
+    slr.stage_times()
+    for _ in range(max(2, args.steps // 4)):
+        batched_step(slr, br, kfs, loss)
+    stages = slr.stage_times()
+    slr.stage_timer(False)
+    nst = max(2, args.steps // 4)
+    graph = None
+    if not args.no_graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batched_step(slr, br, kfs, loss)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            batched_step(slr, br, kfs, loss)
+    run = (lambda: graph.replay()) if graph is not None else (lambda: batched_step(slr, br, kfs, loss))
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    batched_dt = time.perf_counter() - t0
+    batched_iters = args.steps / batched_dt
+    K, over = br.pairs()
+    assert over == 0
+    log(f"batched{'+graph' if graph is not None else ''}: {args.steps} steps in {batched_dt:.3f}s -> "
+        f"{batched_iters:.2f} iter/s")
+
     fwd_ms = stages["raster_fwd"][0] / max(stages["raster_fwd"][1], 1)
     bwd_ms = stages["raster_bwd"][0] / max(stages["raster_bwd"][1], 1)
-    fwd_flops = (FWD_EVAL_FLOPS * ef + FWD_CONTRIB_FLOPS * cf) / N_KF
-    bwd_flops = (BWD_EVAL_FLOPS * eb + BWD_CONTRIB_FLOPS * cb) / N_KF
+    fwd_flops = FWD_EVAL_FLOPS * ef + FWD_CONTRIB_FLOPS * cf   # one batched launch covers all keyframes
+    bwd_flops = BWD_EVAL_FLOPS * eb + BWD_CONTRIB_FLOPS * cb
     if bwd_ms >= fwd_ms:
         dom, flops, ms = "raster_bwd", bwd_flops, bwd_ms
     else:
@@ -168,7 +222,9 @@ def main():
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
             "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
-    stage_ms = {k: round(v[0] / args.steps, 4) for k, v in stages.items()}
+    stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
+    value = batched_iters if args.form == "batched" else plain_iters
+    dt = batched_dt if args.form == "batched" else plain_dt
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -176,13 +232,14 @@ def main():
         cpu = cpu_baseline(sc, sensor, kfs, args.cpu_seconds)
 
     out = {
-        "metric": METRIC, "value": round(iters, 3), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
-                   "form": args.form, "tile": args.tile, "keyframes": N_KF, "surfels": N_SURFELS,
-                   "pairs_per_step": int(sum(r.K for r in rend)),
+                   "form": args.form, "graph": graph is not None, "tile": args.tile, "keyframes": N_KF,
+                   "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
+                   "plain_iter_s": round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
         "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms,
     }

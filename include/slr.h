@@ -141,6 +141,62 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
                                int64_t pair_capacity, void *workspace, size_t workspace_bytes,
                                slr_views *views);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many frames (keyframes, each with its own pose, sensor and
+ * image size) rendered by one set of launches with no host synchronisation,
+ * so that a whole optimisation iteration can be captured in a HIP graph and
+ * replayed.  Frames reference surfel sets; several frames may share one set
+ * (one map seen from several keyframes), in which case the set's gradients
+ * are summed over those frames.  One tile shape serves the whole batch.
+ *
+ * Usage: size the workspace, call slr_batch_prepare once (it uploads the
+ * sensor tables and the per-frame descriptors, i.e. every pointer below, into
+ * the workspace), then call slr_batch_render / slr_batch_backward any number
+ * of times with the same sets, frames and workspace (these two only enqueue
+ * kernels).  Call slr_batch_prepare again when any pointer or size changes.
+ * The pair count is checked on the device: if it exceeds pair_capacity the
+ * frames render empty and the overflow word (see slr_batch_counters) holds
+ * the required capacity.
+ * ------------------------------------------------------------------------ */
+typedef struct slr_frame {
+    int32_t set;                      /* index into the sets array */
+    const double *pose_cw;            /* device [4,4] FP64 */
+    slr_sensor sensor;
+    float *depth, *normal, *alpha;    /* device outputs [H,W], [H,W,3], [H,W] */
+    const float *dL_ddepth, *dL_dnormal, *dL_dalpha; /* device upstream gradients, nullable */
+    double *d_pose;                   /* device [6] FP64 pose gradient, nullable */
+} slr_frame;
+
+typedef struct slr_surfel_grads {
+    float *means, *quats, *log_scales, *logits; /* device [n,3], [n,4], [n,2], [n] */
+} slr_surfel_grads;
+
+slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int32_t n_frames,
+                                    const slr_frame *frames, const slr_tiling *tiling,
+                                    int64_t pair_capacity, size_t *bytes);
+slr_status slr_batch_prepare(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                             const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
+                             size_t workspace_bytes, void *stream);
+/* Forward of every frame: projection, one range sort and one tile sort for
+ * the batch, one compositing launch over all tiles of all frames. */
+slr_status slr_batch_render(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                            const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
+                            size_t workspace_bytes, void *stream);
+/* Backward of every frame.  grads: host array of n_sets entries (device
+ * pointers; an entry of all-NULL pointers skips that set), or NULL with
+ * SLR_POSE_ONLY.  Frame pose gradients go to frames[f].d_pose when set.
+ * With SLR_ACCUMULATE the set gradients are added to the outputs. */
+slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr_surfel_grads *grads,
+                              int32_t n_frames, const slr_frame *frames, const slr_tiling *tiling,
+                              int64_t pair_capacity, void *workspace, size_t workspace_bytes, uint32_t flags,
+                              void *stream);
+/* Device address of three uint64 words in the workspace: the pair count K
+ * of the last render, the overflow word (K when K > pair_capacity, else 0)
+ * and the pair count actually binned. */
+slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                              const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
+                              size_t workspace_bytes, const uint64_t **counters);
+
 /* Range and normal losses of Sec. 3.3.2 (Eqs. loss_range and loss_normal,
  * with rho_d = 1 and N(D) replaced by a given target normal), fused with
  * their gradients:

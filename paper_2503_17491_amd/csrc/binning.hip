@@ -53,10 +53,11 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t *s_wave, uint32_t *total)
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift, int bits, uint32_t *__restrict__ hist,
-             int nblocks)
+k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift,
+             int bits, uint32_t *__restrict__ hist, int nblocks)
 {
     __shared__ uint32_t h[256];
+    const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
     const int nb = 1 << bits;
     for (int d = threadIdx.x; d < nb; d += kSortThreads) h[d] = 0;
     __syncthreads();
@@ -91,9 +92,10 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__
 
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-                uint32_t *__restrict__ vout, int64_t n, int shift, int bits, const uint32_t *__restrict__ hist,
-                const uint32_t *__restrict__ totals, int nblocks)
+                uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
+                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks)
 {
+    const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_wave[kWaves];
@@ -222,17 +224,28 @@ k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ or
     }
 }
 
-// One thread per surfel in range order: write its tile indices and its index.
+// Pair-capacity check on the device: the effective pair count is K, or 0 with
+// the overflow word set to K when K exceeds the capacity.
+__global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
+{
+    const uint64_t K = misc[0];
+    misc[1] = K > cap ? K : 0;
+    misc[2] = K > cap ? 0 : K;
+}
+
+// One thread per record in range order: write its global tile indices and its index.
 __global__ void __launch_bounds__(256)
-k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets, const int32_t *__restrict__ counts,
-       const PixBox *__restrict__ box, int64_t n, int th, int tw, int tiles_x, uint32_t *__restrict__ ptile,
-       uint32_t *__restrict__ pval)
+k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+       const int32_t *__restrict__ counts, const PixBox *__restrict__ box, int64_t n, const uint64_t *__restrict__ keff,
+       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+    if (r >= n || *keff == 0) return;
     uint32_t id = order[r];
     if (counts[id] == 0) return;
     PixBox b = box[id];
+    const FrameDesc &fd = descs[b.frame];
+    const int th = fd.th, tw = fd.tw, tiles_x = fd.tiles_x, toff = fd.tile_off;
     uint32_t o = offsets[r];
     int ty0 = b.r0 / th, ty1 = b.r1 / th;
     int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
@@ -242,14 +255,15 @@ k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
         if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
     }
     for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(ty * tiles_x + tx); pval[o] = id; ++o; }
-        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(ty * tiles_x + tx); pval[o] = id; ++o; }
+        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
+        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
     }
 }
 
 __global__ void __launch_bounds__(256)
-k_ranges(const uint32_t *__restrict__ ptile, int64_t K, int2 *__restrict__ ranges)
+k_ranges(const uint32_t *__restrict__ ptile, const uint64_t *__restrict__ keff, int2 *__restrict__ ranges)
 {
+    const int64_t K = (int64_t)*keff;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= K) return;
     uint32_t t = ptile[p];
@@ -264,14 +278,16 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 }
 
 // One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n, int shift,
-                int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
+// n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+                const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
 {
-    int nblocks = (int)((n + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n, shift, bits, hist, nblocks);
+    int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
+                       nblocks);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
-                       bits, hist, totals, nblocks);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
+                       shift, bits, hist, totals, nblocks);
 }
 
 }  // namespace
@@ -285,59 +301,65 @@ void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream)
 
 void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
 {
-    if (L.n == 0) return;
+    if (L.items == 0) return;
     const uint32_t *ks = reinterpret_cast<const uint32_t *>(ws + L.skey);
     uint32_t *k0 = reinterpret_cast<uint32_t *>(ws + L.key0), *v0 = reinterpret_cast<uint32_t *>(ws + L.val0);
     uint32_t *k1 = reinterpret_cast<uint32_t *>(ws + L.key1), *v1 = reinterpret_cast<uint32_t *>(ws + L.val1);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
-    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc) + 16;
-    // pass 0 reads the per-surfel keys (kept for inspection) and the indices in val0
+    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
+    // pass 0 reads the per-record keys (kept for inspection) and the indices in val0
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
         const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
-        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.n, 8 * p, 8, hist, totals, stream);
+        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
+                   stream);
     }
 }
 
 void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
 {
-    if (L.n == 0) return;
+    uint64_t *misc = reinterpret_cast<uint64_t *>(ws + L.misc);
+    if (L.items == 0) {
+        launch_fill_u32(misc, 0u, 6, stream);
+        return;
+    }
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     const int32_t *counts = reinterpret_cast<const int32_t *>(ws + L.cnt);
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
-    uint64_t *tot = reinterpret_cast<uint64_t *>(ws + L.misc);
-    int nblocks = (int)((L.n + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.n, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, tot);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.n, bs,
+    int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs,
                        reinterpret_cast<uint32_t *>(ws + L.off));
+    hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
-void launch_emit_and_tile_sort(const Layout &L, char *ws, int64_t K, hipStream_t stream)
+void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
 {
     int2 *ranges = reinterpret_cast<int2 *>(ws + L.ranges);
-    launch_fill_u32(ranges, 0u, 2 * L.ntiles, stream);
-    if (K == 0 || L.n == 0) return;
+    launch_fill_u32(ranges, 0u, 2 * L.tiles, stream);
+    if (L.items == 0 || L.cap == 0) return;
+    const uint64_t *keff = reinterpret_cast<const uint64_t *>(ws + L.misc) + 2;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
     uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, stream, order,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
-                       reinterpret_cast<const PixBox *>(ws + L.box), L.n, (int)L.th, (int)L.tw, (int)L.tiles_x, t0,
-                       v0);
+                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
-    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc) + 16;
+    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)
     int done = 0;
     for (int p = 0; p < L.tile_passes; ++p) {
         int bits = (L.tile_bits - done + (L.tile_passes - p) - 1) / (L.tile_passes - p);
         const bool even = (p % 2) == 0;
-        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, K, done, bits, hist, totals,
-                   stream);
+        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, L.cap, keff, done, bits, hist,
+                   totals, stream);
         done += bits;
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, ts, K, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream, ts, keff, ranges);
 }
 
 }  // namespace slr

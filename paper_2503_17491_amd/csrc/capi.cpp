@@ -1,16 +1,25 @@
 // capi.cpp -- C ABI of the spherical surfel rasterizer: argument validation,
-// workspace layout, host-made sensor tables and launch orchestration.
+// workspace layout, host-made sensor tables, frame descriptors and launch
+// orchestration.  The plain calls (slr_render / slr_backward) are the batch
+// of one frame plus a host read-back of the pair count.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "slr_internal.h"
+
+using slr::FrameDesc;
+using slr::FrameGeom;
+using slr::Layout;
 
 namespace {
 
@@ -32,9 +41,6 @@ slr_status fail(slr_status st, const char *fmt, ...)
         hipError_t e_ = (expr);                                                                 \
         if (e_ != hipSuccess) return fail(SLR_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
-
-// Angular margin (radians) by which the bounding box is widened on every side.
-constexpr double kBoxMargin = 2e-5;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -79,7 +85,8 @@ slr_status check_tiling(const slr_tiling *t)
 slr_status check_surfels(const slr_surfels *s)
 {
     if (!s) return fail(SLR_E_INVALID, "surfels is NULL");
-    if (s->n < 0 || s->n > (int64_t(1) << 30)) return fail(SLR_E_INVALID, "surfel count %lld out of range", (long long)s->n);
+    if (s->n < 0 || s->n > (int64_t(1) << 30))
+        return fail(SLR_E_INVALID, "surfel count %lld out of range", (long long)s->n);
     if (s->n > 0 && (!s->means || !s->quats || !s->log_scales || !s->logits))
         return fail(SLR_E_INVALID, "surfel parameter pointer is NULL");
     if (!aligned(s->means, 4) || !aligned(s->quats, 16) || !aligned(s->log_scales, 8) || !aligned(s->logits, 4))
@@ -87,12 +94,21 @@ slr_status check_surfels(const slr_surfels *s)
     return SLR_OK;
 }
 
-// Host-made direction tables: column centres, row centres, rows -/+ margin.
-std::vector<double> make_tables(const slr_sensor &s)
+// Host-made direction tables (column centres, row centres, rows -/+ margin),
+// cached for the life of the process so that asynchronous uploads never
+// outlive their source.
+std::mutex g_tab_mu;
+std::map<std::tuple<int, int, double, double, double, double>, std::unique_ptr<std::vector<double>>> g_tables;
+
+const std::vector<double> &tables_for(const slr_sensor &s)
 {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto key = std::make_tuple(s.height, s.width, s.fu, s.cu, s.fv, s.cv);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) return *it->second;
     const int H = s.height, W = s.width;
-    std::vector<double> t(2 * (size_t)(W + 3 * H));
-    double *col = t.data(), *row = col + 2 * W, *rlo = row + 2 * H, *rhi = rlo + 2 * H;
+    auto t = std::make_unique<std::vector<double>>(2 * (size_t)(W + 3 * H));
+    double *col = t->data(), *row = col + 2 * W, *rlo = row + 2 * H, *rhi = rlo + 2 * H;
     for (int j = 0; j < W; ++j) {
         const double az = (((double)j + 0.5) - s.cu) / s.fu;
         col[2 * j] = std::cos(az);
@@ -102,12 +118,14 @@ std::vector<double> make_tables(const slr_sensor &s)
         const double el = (((double)i + 0.5) - s.cv) / s.fv;
         row[2 * i] = std::cos(el);
         row[2 * i + 1] = std::sin(el);
-        rlo[2 * i] = std::cos(el - kBoxMargin);
-        rlo[2 * i + 1] = std::sin(el - kBoxMargin);
-        rhi[2 * i] = std::cos(el + kBoxMargin);
-        rhi[2 * i + 1] = std::sin(el + kBoxMargin);
+        rlo[2 * i] = std::cos(el - slr::kBoxMargin);
+        rlo[2 * i + 1] = std::sin(el - slr::kBoxMargin);
+        rhi[2 * i] = std::cos(el + slr::kBoxMargin);
+        rhi[2 * i + 1] = std::sin(el + slr::kBoxMargin);
     }
-    return t;
+    auto &ref = *t;
+    g_tables.emplace(key, std::move(t));
+    return ref;
 }
 
 // ---- stage timers (HIP events on the caller's stream) ----
@@ -129,37 +147,222 @@ struct StageScope {
     {
         if (!g_timer_on) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
-        hipEventRecord(a, s);
+        if (hipEventRecord(a, s) != hipSuccess) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); a = b = nullptr; }
     }
     ~StageScope()
     {
         if (!a) return;
-        hipEventRecord(b, s);
+        if (hipEventRecord(b, s) != hipSuccess) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); return; }
         std::lock_guard<std::mutex> lk(g_timer_mu);
         g_pending.push_back({stage, a, b});
     }
 };
 
+// ---- batch description on the host ----
+struct Batch {
+    std::vector<FrameGeom> geom;
+    std::vector<int64_t> set_n;
+    Layout L;
+    int64_t max_n = 0;
+};
+
+slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                       const slr_tiling *tiling, int64_t cap, Batch *b)
+{
+    slr_status st;
+    if (n_sets < 0 || n_frames < 0 || n_frames > 32767) return fail(SLR_E_INVALID, "bad set or frame count");
+    if ((n_sets > 0 && !sets) || (n_frames > 0 && !frames)) return fail(SLR_E_INVALID, "sets or frames is NULL");
+    if ((st = check_tiling(tiling)) != SLR_OK) return st;
+    if (cap < 0 || cap > 0x7fffffffLL) return fail(SLR_E_INVALID, "pair_capacity must be in [0, 2^31)");
+    b->set_n.resize(n_sets);
+    for (int32_t s = 0; s < n_sets; ++s) {
+        if ((st = check_surfels(&sets[s])) != SLR_OK) return st;
+        b->set_n[s] = sets[s].n;
+    }
+    b->geom.resize(n_frames);
+    int64_t items = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const slr_frame &fr = frames[f];
+        if (fr.set < 0 || fr.set >= n_sets)
+            return fail(SLR_E_INVALID, "frame %d: set index %d out of range", f, fr.set);
+        if ((st = check_sensor(&fr.sensor)) != SLR_OK) return st;
+        if (!fr.pose_cw || !aligned(fr.pose_cw, 8))
+            return fail(SLR_E_INVALID, "frame %d: pose must be a non-NULL, 8-byte aligned device pointer", f);
+        b->geom[f] = FrameGeom{fr.sensor.height, fr.sensor.width, fr.set};
+        items += sets[fr.set].n;
+        if (sets[fr.set].n > b->max_n) b->max_n = sets[fr.set].n;
+    }
+    if (items >= (int64_t(1) << 31)) return fail(SLR_E_INVALID, "batch has %lld records, limit 2^31", (long long)items);
+    b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w);
+    if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");
+    return SLR_OK;
+}
+
+// Host descriptors of every frame (device pointers into the workspace).
+std::vector<FrameDesc> make_descs(const Batch &B, const slr_surfels *sets, const slr_frame *frames,
+                                  const slr_tiling *tiling, char *ws)
+{
+    const Layout &L = B.L;
+    std::vector<int64_t> acc_off(B.set_n.size() + 1, 0);
+    for (size_t s = 0; s < B.set_n.size(); ++s) acc_off[s + 1] = acc_off[s] + B.set_n[s] * slr::kAccStride;
+    std::vector<FrameDesc> d(L.frames);
+    int64_t item = 0, pix = 0, tab = 0, tile = 0;
+    for (int32_t f = 0; f < L.frames; ++f) {
+        const slr_frame &fr = frames[f];
+        const slr_surfels &sf = sets[fr.set];
+        FrameDesc &x = d[f];
+        memset(&x, 0, sizeof(x));
+        x.pose = fr.pose_cw;
+        x.means = sf.means; x.quats = sf.quats; x.lsc = sf.log_scales; x.logits = sf.logits;
+        x.depth = fr.depth; x.normal = fr.normal; x.alpha = fr.alpha;
+        x.gD = fr.dL_ddepth; x.gN = fr.dL_dnormal; x.gO = fr.dL_dalpha;
+        x.d_pose = fr.d_pose ? fr.d_pose : reinterpret_cast<double *>(ws + L.scratch_pose) + 6 * f;
+        x.acc = reinterpret_cast<float *>(ws + L.acc) + acc_off[fr.set];
+        x.n = sf.n;
+        x.item_off = item;
+        x.pix_off = pix;
+        x.tab_off = tab;
+        x.fu = fr.sensor.fu; x.cu = fr.sensor.cu; x.fv = fr.sensor.fv; x.cv = fr.sensor.cv;
+        x.near_m = fr.sensor.near_m;
+        x.H = fr.sensor.height; x.W = fr.sensor.width;
+        x.th = tiling->tile_h; x.tw = tiling->tile_w;
+        x.tiles_x = (x.W + x.tw - 1) / x.tw;
+        x.tiles_y = (x.H + x.th - 1) / x.th;
+        x.tile_off = (int32_t)tile;
+        x.set = fr.set;
+        item += sf.n;
+        pix += (int64_t)x.H * x.W;
+        tab += x.W + 3 * x.H;
+        tile += (int64_t)x.tiles_x * x.tiles_y;
+    }
+    return d;
+}
+
+slr_status upload_tables(const Batch &B, const slr_frame *frames, char *ws, hipStream_t s)
+{
+    int64_t tab = 0;
+    for (int32_t f = 0; f < B.L.frames; ++f) {
+        const std::vector<double> &t = tables_for(frames[f].sensor);
+        HIP_TRY(hipMemcpyAsync(ws + B.L.tables + tab * 16, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice,
+                               s));
+        tab += frames[f].sensor.width + 3 * frames[f].sensor.height;
+    }
+    return SLR_OK;
+}
+
+slr_status check_ws(const Layout &L, void *ws, size_t bytes)
+{
+    if (!ws || !aligned(ws, 256)) return fail(SLR_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (bytes < L.total) return fail(SLR_E_INVALID, "workspace has %zu bytes, needs %zu", bytes, L.total);
+    return SLR_OK;
+}
+
+void enqueue_render_front(const Batch &B, char *ws, hipStream_t s)
+{
+    {
+        StageScope t(0, s);
+        slr::launch_project(B.L, ws, B.max_n, s);
+    }
+    {
+        StageScope t(1, s);
+        slr::launch_depth_sort(B.L, ws, s);
+    }
+    {
+        StageScope t(2, s);
+        slr::launch_scan_counts(B.L, ws, s);
+    }
+}
+
+void enqueue_render_back(const Batch &B, char *ws, hipStream_t s)
+{
+    {
+        StageScope t(3, s);
+        slr::launch_emit_and_tile_sort(B.L, ws, s);
+    }
+    {
+        StageScope t(4, s);
+        slr::launch_raster_fwd(B.L, ws, s);
+    }
+}
+
+void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_grads *grads, char *ws,
+                      bool pose_only, bool accumulate, hipStream_t s)
+{
+    const Layout &L = B.L;
+    // pose gradients are accumulated by FP64 atomics: start from zero
+    slr::launch_fill_u32(ws + L.scratch_pose, 0u, 12 * (int64_t)L.frames, s);
+    if (!pose_only) slr::launch_fill_u32(ws + L.acc, 0u, L.acc_floats, s);
+    {
+        StageScope t(5, s);
+        slr::launch_raster_bwd(L, ws, pose_only, s);
+    }
+    if (pose_only) return;
+    StageScope t(6, s);
+    int64_t off = 0;
+    for (int32_t k = 0; k < L.sets; ++k) {
+        const slr_surfel_grads &g = grads[k];
+        if (g.means)
+            slr::launch_surfel_grad(sets[k].quats, sets[k].log_scales, sets[k].logits, sets[k].n,
+                                    reinterpret_cast<const float *>(ws + L.acc) + off, g.means, g.quats, g.log_scales,
+                                    g.logits, accumulate, s);
+        off += sets[k].n * slr::kAccStride;
+    }
+}
+
+slr_status check_grads(int32_t n_sets, const slr_surfel_grads *grads, bool pose_only)
+{
+    if (pose_only) {
+        if (!grads) return SLR_OK;
+        for (int32_t k = 0; k < n_sets; ++k)
+            if (grads[k].means || grads[k].quats || grads[k].log_scales || grads[k].logits)
+                return fail(SLR_E_INVALID, "SLR_POSE_ONLY takes NULL surfel gradients");
+        return SLR_OK;
+    }
+    if (!grads) return fail(SLR_E_INVALID, "grads is NULL without SLR_POSE_ONLY");
+    for (int32_t k = 0; k < n_sets; ++k) {
+        const slr_surfel_grads &g = grads[k];
+        const int nset = (g.means != nullptr) + (g.quats != nullptr) + (g.log_scales != nullptr) + (g.logits != nullptr);
+        if (nset != 0 && nset != 4) return fail(SLR_E_INVALID, "set %d: surfel gradient pointers must all be set", k);
+        if (nset == 4 && !aligned(g.quats, 16)) return fail(SLR_E_INVALID, "set %d: d_quats must be 16-byte aligned", k);
+    }
+    return SLR_OK;
+}
+
+// Zero the user pose gradients of every frame that has one.
+void zero_user_pose(int32_t n_frames, const slr_frame *frames, hipStream_t s)
+{
+    for (int32_t f = 0; f < n_frames; ++f)
+        if (frames[f].d_pose) slr::launch_fill_u32(frames[f].d_pose, 0u, 12, s);
+}
+
 }  // namespace
 
 namespace slr {
 
-Layout make_layout(int64_t n, int64_t cap, int32_t H, int32_t W, int32_t th, int32_t tw)
+Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, const int64_t *set_n, int64_t cap,
+                   int32_t th, int32_t tw)
 {
     Layout L{};
-    L.n = n; L.cap = cap; L.H = H; L.W = W; L.th = th; L.tw = tw;
-    L.tiles_x = (W + tw - 1) / tw;
-    L.tiles_y = (H + th - 1) / th;
-    L.ntiles = L.tiles_x * L.tiles_y;
-    L.tile_bits = ceil_log2(L.ntiles);
+    L.frames = nframes; L.sets = nsets; L.th = th; L.tw = tw; L.cap = cap;
+    for (int32_t f = 0; f < nframes; ++f) {
+        const int64_t tx = (frames[f].W + tw - 1) / tw, ty = (frames[f].H + th - 1) / th;
+        L.tiles += tx * ty;
+        L.pixels += (int64_t)frames[f].H * frames[f].W;
+        L.tab_entries += frames[f].W + 3 * frames[f].H;
+        L.items += set_n[frames[f].set];
+    }
+    for (int32_t s = 0; s < nsets; ++s) L.acc_floats += set_n[s] * kAccStride;
+    L.tile_bits = ceil_log2(L.tiles > 0 ? L.tiles : 1);
     L.depth_passes = 4;
     L.tile_passes = (L.tile_bits + kMaxDigitBits - 1) / kMaxDigitBits;
     L.depth_in_1 = (L.depth_passes % 2) == 1;
     L.tile_in_1 = (L.tile_passes % 2) == 1;
-    const int64_t nn = n > 0 ? n : 1, cc = cap > 0 ? cap : 1;
+    const int64_t nn = L.items > 0 ? L.items : 1, cc = cap > 0 ? cap : 1;
     size_t o = 0;
-    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
-    L.tables = take(sizeof(double) * 2 * (size_t)(W + 3 * H));
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + (bytes ? bytes : 1), 256); return at; };
+    L.desc = take(sizeof(FrameDesc) * (size_t)(nframes > 0 ? nframes : 1));
+    L.tables = take(16 * (size_t)L.tab_entries);
+    L.tile_frame = take(4 * (size_t)L.tiles);
     L.rec = take(sizeof(RasterRec) * nn);
     L.frame = take(sizeof(FrameRec) * nn);
     L.box = take(sizeof(PixBox) * nn);
@@ -170,20 +373,19 @@ Layout make_layout(int64_t n, int64_t cap, int32_t H, int32_t W, int32_t th, int
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
-    L.ranges = take(8 * (size_t)L.ntiles);
+    L.ranges = take(8 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));
-    L.stateT = take(4 * (size_t)H * W);
-    L.stateN = take(4 * (size_t)H * W);
-    L.census = take(16 * (size_t)H * W);
-    L.acc = take(4 * (size_t)kAccStride * nn);
+    L.stateT = take(4 * (size_t)L.pixels);
+    L.stateN = take(4 * (size_t)L.pixels);
+    L.census = take(16 * (size_t)L.pixels);
+    L.acc = take(4 * (size_t)L.acc_floats);
+    L.scratch_pose = take(48 * (size_t)(nframes > 0 ? nframes : 1));
     L.misc = take(4096);
     L.total = o;
     return L;
 }
 
 }  // namespace slr
-
-using slr::Layout;
 
 extern "C" {
 
@@ -215,6 +417,20 @@ slr_status slr_camera_matrix(double az_min, double az_max, double el_min, double
     return SLR_OK;
 }
 
+// ---------------------------------------------------------------- plain form
+static slr_status plain_batch(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
+                              const slr_tiling *tiling, int64_t cap, slr_frame *frame, Batch *B)
+{
+    slr_status st;
+    if ((st = check_surfels(surfels)) != SLR_OK) return st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    memset(frame, 0, sizeof(*frame));
+    frame->set = 0;
+    frame->pose_cw = pose_cw;
+    frame->sensor = *sensor;
+    return check_batch(1, surfels, 1, frame, tiling, cap, B);
+}
+
 slr_status slr_workspace_size(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n, int64_t pair_capacity,
                               size_t *bytes)
 {
@@ -222,25 +438,10 @@ slr_status slr_workspace_size(const slr_sensor *sensor, const slr_tiling *tiling
     if ((st = check_sensor(sensor)) != SLR_OK) return st;
     if ((st = check_tiling(tiling)) != SLR_OK) return st;
     if (!bytes) return fail(SLR_E_INVALID, "bytes is NULL");
-    if (n < 0 || pair_capacity < 0 || pair_capacity > 0x7fffffffLL)
-        return fail(SLR_E_INVALID, "n and pair_capacity must be in [0, 2^31)");
-    *bytes = slr::make_layout(n, pair_capacity, sensor->height, sensor->width, tiling->tile_h, tiling->tile_w).total;
-    return SLR_OK;
-}
-
-static slr_status common_checks(const slr_surfels *surfels, const double *pose, const slr_sensor *sensor,
-                                const slr_tiling *tiling, void *ws, size_t ws_bytes, int64_t cap, Layout *L)
-{
-    slr_status st;
-    if ((st = check_surfels(surfels)) != SLR_OK) return st;
-    if ((st = check_sensor(sensor)) != SLR_OK) return st;
-    if ((st = check_tiling(tiling)) != SLR_OK) return st;
-    if (!pose || !aligned(pose, 8)) return fail(SLR_E_INVALID, "pose must be a non-NULL, 8-byte aligned device pointer");
-    if (cap < 0 || cap > 0x7fffffffLL) return fail(SLR_E_INVALID, "pair_capacity must be in [0, 2^31)");
-    if (!ws || !aligned(ws, 256)) return fail(SLR_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
-    *L = slr::make_layout(surfels->n, cap, sensor->height, sensor->width, tiling->tile_h, tiling->tile_w);
-    if (ws_bytes < L->total)
-        return fail(SLR_E_INVALID, "workspace has %zu bytes, needs %zu", ws_bytes, L->total);
+    if (n < 0 || pair_capacity < 0 || pair_capacity > 0x7fffffffLL || n > (int64_t(1) << 30))
+        return fail(SLR_E_INVALID, "n and pair_capacity out of range");
+    FrameGeom g{sensor->height, sensor->width, 0};
+    *bytes = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w).total;
     return SLR_OK;
 }
 
@@ -248,44 +449,29 @@ slr_status slr_render(const slr_surfels *surfels, const double *pose_cw, const s
                       const slr_tiling *tiling, void *workspace, size_t workspace_bytes, int64_t pair_capacity,
                       float *depth, float *normal, float *alpha, int64_t *pairs_out, void *stream)
 {
-    Layout L;
-    slr_status st = common_checks(surfels, pose_cw, sensor, tiling, workspace, workspace_bytes, pair_capacity, &L);
+    slr_frame fr;
+    Batch B;
+    slr_status st = plain_batch(surfels, pose_cw, sensor, tiling, pair_capacity, &fr, &B);
     if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
     if (!depth || !normal || !alpha) return fail(SLR_E_INVALID, "output pointer is NULL");
+    fr.depth = depth; fr.normal = normal; fr.alpha = alpha;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *ws = reinterpret_cast<char *>(workspace);
-    std::vector<double> tab = make_tables(*sensor);
-    HIP_TRY(hipMemcpyAsync(ws + L.tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    {
-        StageScope t(0, s);
-        slr::launch_project(*surfels, pose_cw, *sensor, L, ws, std::cos(kBoxMargin), std::sin(kBoxMargin), s);
-    }
-    {
-        StageScope t(1, s);
-        slr::launch_depth_sort(L, ws, s);
-    }
+    if ((st = upload_tables(B, &fr, ws, s)) != SLR_OK) return st;
+    std::vector<FrameDesc> d = make_descs(B, surfels, &fr, tiling, ws);
+    slr::launch_write_desc(d.data(), 1, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
+    slr::launch_tile_frame(B.L, ws, s);
+    enqueue_render_front(B, ws, s);
     uint64_t K = 0;
-    if (L.n > 0) {
-        {
-            StageScope t(2, s);
-            slr::launch_scan_counts(L, ws, s);
-        }
-        HIP_TRY(hipMemcpyAsync(&K, ws + L.misc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));  // K, and the table upload's host buffer
+    HIP_TRY(hipMemcpyAsync(&K, ws + B.L.misc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     if (pairs_out) *pairs_out = (int64_t)K;
     if ((int64_t)K > pair_capacity)
         return fail(SLR_E_CAPACITY, "%llu (tile, surfel) pairs exceed the capacity %lld", (unsigned long long)K,
                     (long long)pair_capacity);
-    {
-        StageScope t(3, s);
-        slr::launch_emit_and_tile_sort(L, ws, (int64_t)K, s);
-    }
-    {
-        StageScope t(4, s);
-        slr::launch_raster_fwd(L, *sensor, ws, (int64_t)K, depth, normal, alpha, s);
-    }
+    enqueue_render_back(B, ws, s);
     HIP_TRY(hipGetLastError());
     return SLR_OK;
 }
@@ -296,9 +482,11 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
                         float *d_quats, float *d_log_scales, float *d_logits, double *d_pose, uint32_t flags,
                         void *stream)
 {
-    Layout L;
-    slr_status st = common_checks(surfels, pose_cw, sensor, tiling, workspace, workspace_bytes, pair_capacity, &L);
+    slr_frame fr;
+    Batch B;
+    slr_status st = plain_batch(surfels, pose_cw, sensor, tiling, pair_capacity, &fr, &B);
     if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
     const bool pose_only = (flags & SLR_POSE_ONLY) != 0;
     const bool accumulate = (flags & SLR_ACCUMULATE) != 0;
     const int nset = (d_means != nullptr) + (d_quats != nullptr) + (d_log_scales != nullptr) + (d_logits != nullptr);
@@ -307,23 +495,103 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
     if (!pose_only && !aligned(d_quats, 16)) return fail(SLR_E_INVALID, "d_quats must be 16-byte aligned");
     if (pose_only && !d_pose) return fail(SLR_E_INVALID, "SLR_POSE_ONLY needs d_pose");
     if (flags & ~(SLR_POSE_ONLY | SLR_ACCUMULATE)) return fail(SLR_E_INVALID, "unknown flags 0x%x", flags);
+    fr.dL_ddepth = dL_ddepth; fr.dL_dnormal = dL_dnormal; fr.dL_dalpha = dL_dalpha;
+    fr.d_pose = d_pose;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *ws = reinterpret_cast<char *>(workspace);
-    double *dpose = d_pose ? d_pose : reinterpret_cast<double *>(ws + L.misc + 2048);
-    slr::launch_fill_u32(dpose, 0u, 12, s);
-    if (!pose_only) slr::launch_fill_u32(ws + L.acc, 0u, (int64_t)slr::kAccStride * L.n, s);
-    if (L.ntiles > 0) {
-        StageScope t(5, s);
-        slr::launch_raster_bwd(L, *sensor, ws, pose_cw, dL_ddepth, dL_dnormal, dL_dalpha, dpose, pose_only, s);
-    }
-    if (!pose_only) {
-        StageScope t(6, s);
-        slr::launch_surfel_grad(*surfels, L, ws, d_means, d_quats, d_log_scales, d_logits, accumulate, s);
-    }
+    // rewrite the descriptor with the backward's pointers (outputs are not read)
+    std::vector<FrameDesc> d = make_descs(B, surfels, &fr, tiling, ws);
+    slr::launch_write_desc(d.data(), 1, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
+    zero_user_pose(1, &fr, s);
+    slr_surfel_grads g{d_means, d_quats, d_log_scales, d_logits};
+    enqueue_backward(B, surfels, &g, ws, pose_only, accumulate, s);
     HIP_TRY(hipGetLastError());
     return SLR_OK;
 }
 
+// ---------------------------------------------------------------- batched form
+slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int32_t n_frames,
+                                    const slr_frame *frames, const slr_tiling *tiling, int64_t pair_capacity,
+                                    size_t *bytes)
+{
+    if (!bytes) return fail(SLR_E_INVALID, "bytes is NULL");
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    *bytes = B.L.total;
+    return SLR_OK;
+}
+
+slr_status slr_batch_prepare(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                             const slr_tiling *tiling, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                             void *stream)
+{
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    for (int32_t f = 0; f < n_frames; ++f)
+        if (!frames[f].depth || !frames[f].normal || !frames[f].alpha)
+            return fail(SLR_E_INVALID, "frame %d: output pointer is NULL", f);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    if ((st = upload_tables(B, frames, ws, s)) != SLR_OK) return st;
+    std::vector<FrameDesc> d = make_descs(B, sets, frames, tiling, ws);
+    slr::launch_write_desc(d.data(), n_frames, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
+    slr::launch_tile_frame(B.L, ws, s);
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_batch_render(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                            const slr_tiling *tiling, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                            void *stream)
+{
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    enqueue_render_front(B, ws, s);
+    enqueue_render_back(B, ws, s);
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr_surfel_grads *grads, int32_t n_frames,
+                              const slr_frame *frames, const slr_tiling *tiling, int64_t pair_capacity,
+                              void *workspace, size_t workspace_bytes, uint32_t flags, void *stream)
+{
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    if (flags & ~(SLR_POSE_ONLY | SLR_ACCUMULATE)) return fail(SLR_E_INVALID, "unknown flags 0x%x", flags);
+    const bool pose_only = (flags & SLR_POSE_ONLY) != 0;
+    if ((st = check_grads(n_sets, grads, pose_only)) != SLR_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    zero_user_pose(n_frames, frames, s);
+    enqueue_backward(B, sets, grads, ws, pose_only, (flags & SLR_ACCUMULATE) != 0, s);
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                              const slr_tiling *tiling, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                              const uint64_t **counters)
+{
+    if (!counters) return fail(SLR_E_INVALID, "counters is NULL");
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    *counters = reinterpret_cast<const uint64_t *>(reinterpret_cast<char *>(workspace) + B.L.misc);
+    return SLR_OK;
+}
+
+// ---------------------------------------------------------------- support
 slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *normal, const float *target_depth,
                               const float *target_normal, float w_d, float w_n, float *dL_ddepth, float *dL_dnormal,
                               double *loss, void *stream)
@@ -363,8 +631,8 @@ slr_status slr_stage_times(double *ms, int64_t *counts)
         if (hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) st = SLR_E_HIP;
         g_stage_ms[e.stage] += t;
         g_stage_n[e.stage] += 1;
-        hipEventDestroy(e.a);
-        hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     for (int k = 0; k < SLR_NUM_STAGES; ++k) {
         ms[k] = g_stage_ms[k];
@@ -384,7 +652,8 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
     if ((st = check_tiling(tiling)) != SLR_OK) return st;
     if (!workspace || !v) return fail(SLR_E_INVALID, "workspace and views must be non-NULL");
     if (n < 0 || pair_capacity < 0) return fail(SLR_E_INVALID, "negative size");
-    Layout L = slr::make_layout(n, pair_capacity, sensor->height, sensor->width, tiling->tile_h, tiling->tile_w);
+    FrameGeom g{sensor->height, sensor->width, 0};
+    Layout L = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w);
     if (workspace_bytes < L.total) return fail(SLR_E_INVALID, "workspace too small");
     char *ws = reinterpret_cast<char *>(workspace);
     v->keys = reinterpret_cast<const uint32_t *>(ws + L.skey);
@@ -396,8 +665,8 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
     v->T_final = reinterpret_cast<const float *>(ws + L.stateT);
     v->n_proc = reinterpret_cast<const int32_t *>(ws + L.stateN);
     v->census = reinterpret_cast<const int32_t *>(ws + L.census);
-    v->tiles_x = L.tiles_x;
-    v->tiles_y = L.tiles_y;
+    v->tiles_x = (sensor->width + tiling->tile_w - 1) / tiling->tile_w;
+    v->tiles_y = (sensor->height + tiling->tile_h - 1) / tiling->tile_h;
     return SLR_OK;
 }
 

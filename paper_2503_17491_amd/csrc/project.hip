@@ -203,19 +203,22 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
 }
 
 __global__ void __launch_bounds__(256)
-k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ quats,
-          const float *__restrict__ lsc, const float *__restrict__ logits, const double *__restrict__ pose,
-          int H, int W, int th, int tw, double near_m, double cm, double sm,
-          const double2 *__restrict__ col, const double2 *__restrict__ rlo, const double2 *__restrict__ rhi,
+k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ tables, double cm, double sm,
           RasterRec *__restrict__ rec, FrameRec *__restrict__ frame, PixBox *__restrict__ box,
           uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    ids[k] = (uint32_t)k;
-    float fm0 = means[3 * k], fm1 = means[3 * k + 1], fm2 = means[3 * k + 2];
-    float4 fq = *reinterpret_cast<const float4 *>(quats + 4 * k);
-    float fl0 = lsc[2 * k], fl1 = lsc[2 * k + 1], flg = logits[k];
+    const FrameDesc &fd = descs[blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= fd.n) return;
+    const int64_t it = fd.item_off + k;
+    const int H = fd.H, W = fd.W;
+    const double2 *col = tables + fd.tab_off;
+    const double2 *rlo = col + W + H;
+    const double2 *rhi = rlo + H;
+    ids[it] = (uint32_t)it;
+    float fm0 = fd.means[3 * k], fm1 = fd.means[3 * k + 1], fm2 = fd.means[3 * k + 2];
+    float4 fq = *reinterpret_cast<const float4 *>(fd.quats + 4 * k);
+    float fl0 = fd.lsc[2 * k], fl1 = fd.lsc[2 * k + 1], flg = fd.logits[k];
     bool fin = isfinite(fm0) && isfinite(fm1) && isfinite(fm2) && isfinite(fq.x) && isfinite(fq.y) &&
                isfinite(fq.z) && isfinite(fq.w) && isfinite(fl0) && isfinite(fl1) && isfinite(flg);
     double w = fq.x, x = fq.y, y = fq.z, z = fq.w;
@@ -224,8 +227,8 @@ k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ 
     double R[9], t[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
-        t[e] = pose[4 * e + 3];
+        R[3 * e] = fd.pose[4 * e]; R[3 * e + 1] = fd.pose[4 * e + 1]; R[3 * e + 2] = fd.pose[4 * e + 2];
+        t[e] = fd.pose[4 * e + 3];
     }
     double A[3], B[3], C[3], N[3];
     double range = 0.0;
@@ -248,14 +251,15 @@ k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ 
             N[r] = (Rr[0] * tn[0] + Rr[1] * tn[1]) + Rr[2] * tn[2];
         }
         range = sqrt((C[0] * C[0] + C[1] * C[1]) + C[2] * C[2]);
-        ok = range > near_m;
+        ok = range > fd.near_m;
     }
     BoxOut bx;
     bx.nint = 0;
     if (ok) bx = angular_box(A, B, C, H, W, col, rlo, rhi, cm, sm);
     int32_t cnt = 0;
-    PixBox pb = {-1, -1, -1, -1, -1, -1, 0, 0};
+    PixBox pb = {-1, -1, -1, -1, -1, -1, (int16_t)blockIdx.y, 0};
     if (bx.nint > 0) {
+        const int th = fd.th, tw = fd.tw;
         int ty0 = bx.r0 / th, ty1 = bx.r1 / th;
         int ax0 = bx.c[0] / tw, ax1 = bx.c[1] / tw;
         int nr = 1, bx0 = 0, bx1 = -1;
@@ -270,14 +274,14 @@ k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ 
         pb.c0 = (int16_t)bx.c[0]; pb.c1 = (int16_t)bx.c[1];
         pb.c2 = (int16_t)(bx.nint == 2 ? bx.c[2] : -1); pb.c3 = (int16_t)(bx.nint == 2 ? bx.c[3] : -1);
     }
-    counts[k] = cnt;
-    box[k] = pb;
+    counts[it] = cnt;
+    box[it] = pb;
     if (cnt == 0) {
-        keys[k] = 0xFFFFFFFFu;
+        keys[it] = 0xFFFFFFFFu;
         return;
     }
     float key = (float)range;
-    keys[k] = __float_as_uint(key);
+    keys[it] = __float_as_uint(key);
 
     // compositing record: b_alpha = A / 3, b_beta = B / 3, b_c = C
     double ba[3] = {A[0] / 3.0, A[1] / 3.0, A[2] / 3.0};
@@ -290,30 +294,63 @@ k_project(int64_t n, const float *__restrict__ means, const float *__restrict__ 
     rr.opac = 1.0f / (1.0f + expf(-flg));
     rr.n[0] = (float)N[0]; rr.n[1] = (float)N[1]; rr.n[2] = (float)N[2];
     rr.rows = (uint32_t)bx.r0 | ((uint32_t)bx.r1 << 16);
-    rec[k] = rr;
+    rec[it] = rr;
     FrameRec fr;
 #pragma unroll
     for (int r = 0; r < 3; ++r) { fr.ba[r] = ba[r]; fr.bb[r] = bb[r]; fr.bc[r] = C[r]; fr.n[r] = (float)N[r]; }
     fr.pad[0] = fr.pad[1] = fr.pad[2] = 0.0f;
-    frame[k] = fr;
+    frame[it] = fr;
+}
+
+// Descriptor upload through kernel arguments (no host buffer outlives the call).
+constexpr int kDescPerLaunch = 8;
+struct DescPack {
+    FrameDesc d[kDescPerLaunch];
+};
+__global__ void k_write_desc(DescPack pack, int count, FrameDesc *__restrict__ dst)
+{
+    const int i = threadIdx.x;
+    if (i < count) dst[i] = pack.d[i];
+}
+
+// Frame index of every global tile.
+__global__ void __launch_bounds__(256)
+k_tile_frame(const FrameDesc *__restrict__ descs, int32_t *__restrict__ tile_frame)
+{
+    const FrameDesc &fd = descs[blockIdx.y];
+    const int nt = fd.tiles_x * fd.tiles_y;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x)
+        tile_frame[fd.tile_off + t] = (int32_t)blockIdx.y;
 }
 
 }  // namespace
 
-void launch_project(const slr_surfels &s, const double *pose, const slr_sensor &sen, const Layout &L, char *ws,
-                    double cos_m, double sin_m, hipStream_t stream)
+void launch_write_desc(const FrameDesc *host_descs, int32_t count, FrameDesc *dev, hipStream_t stream)
 {
-    if (s.n == 0) return;
-    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
-    const double2 *col = tab;
-    const double2 *rlo = tab + L.W + L.H;
-    const double2 *rhi = tab + L.W + 2 * L.H;
-    int blocks = (int)((s.n + 255) / 256);
-    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, stream, s.n, s.means, s.quats, s.log_scales, s.logits,
-                       pose, (int)L.H, (int)L.W, (int)L.th, (int)L.tw, sen.near_m, cos_m, sin_m, col, rlo, rhi,
-                       reinterpret_cast<RasterRec *>(ws + L.rec), reinterpret_cast<FrameRec *>(ws + L.frame),
-                       reinterpret_cast<PixBox *>(ws + L.box), reinterpret_cast<uint32_t *>(ws + L.skey),
-                       reinterpret_cast<uint32_t *>(ws + L.val0), reinterpret_cast<int32_t *>(ws + L.cnt));
+    for (int32_t b = 0; b < count; b += kDescPerLaunch) {
+        DescPack pack;
+        const int c = count - b < kDescPerLaunch ? count - b : kDescPerLaunch;
+        for (int i = 0; i < c; ++i) pack.d[i] = host_descs[b + i];
+        hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(kDescPerLaunch), 0, stream, pack, c, dev + b);
+    }
+}
+
+void launch_tile_frame(const Layout &L, char *ws, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_tile_frame, dim3(8, L.frames), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<int32_t *>(ws + L.tile_frame));
+}
+
+void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream)
+{
+    if (max_n <= 0 || L.frames == 0) return;
+    const int blocks = (int)((max_n + 255) / 256);
+    hipLaunchKernelGGL(k_project, dim3(blocks, L.frames), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double2 *>(ws + L.tables),
+                       cos(kBoxMargin), sin(kBoxMargin), reinterpret_cast<RasterRec *>(ws + L.rec),
+                       reinterpret_cast<FrameRec *>(ws + L.frame), reinterpret_cast<PixBox *>(ws + L.box),
+                       reinterpret_cast<uint32_t *>(ws + L.skey), reinterpret_cast<uint32_t *>(ws + L.val0),
+                       reinterpret_cast<int32_t *>(ws + L.cnt));
 }
 
 }  // namespace slr

@@ -83,15 +83,24 @@ __device__ __forceinline__ float wave_sum_lane63(float v)
 
 template <int TW>
 __global__ void __launch_bounds__(256)
-k_raster_fwd(const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
-             const double2 *__restrict__ col, const double2 *__restrict__ rowc, int H, int W, int tiles_x,
-             float near_m, float *__restrict__ depth, float *__restrict__ normal, float *__restrict__ alpha,
-             float *__restrict__ stT, int32_t *__restrict__ stN, int32_t *__restrict__ census)
+k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+             const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+             const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
+             int32_t *__restrict__ census_all, int64_t total_pixels)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[256];
     const int tile = blockIdx.x;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    float *depth = fd.depth, *normal = fd.normal, *alpha = fd.alpha;
+    float *stT = stT_all + fd.pix_off;
+    int32_t *stN = stN_all + fd.pix_off;
+    int32_t *census = census_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
@@ -133,7 +142,7 @@ k_raster_fwd(const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pva
     if (inside) {
         const int p = i * W + j;
         census[p] = n_eval;
-        census[(size_t)H * W + p] = n_con;
+        census[total_pixels + p] = n_con;
         depth[p] = D;
         alpha[p] = O;
         normal[3 * p] = N0; normal[3 * p + 1] = N1; normal[3 * p + 2] = N2;
@@ -154,12 +163,11 @@ __device__ __forceinline__ void dcross(const double *a, const double *b, double 
 
 template <int TW>
 __global__ void __launch_bounds__(256)
-k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval,
-             const int2 *__restrict__ ranges, const double2 *__restrict__ col, const double2 *__restrict__ rowc, int H,
-             int W, int tiles_x, float near_m, const float *__restrict__ stT, const int32_t *__restrict__ stN,
-             const float *__restrict__ gD, const float *__restrict__ gN, const float *__restrict__ gO,
-             const double *__restrict__ pose, float *__restrict__ acc, double *__restrict__ d_pose, int pose_only,
-             int32_t *__restrict__ census)
+k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+             const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval,
+             const int2 *__restrict__ ranges, const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+             const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
+             int pose_only)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
@@ -169,7 +177,19 @@ k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ fra
     __shared__ double s_pose[4][6];
 
     const int tile = blockIdx.x;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    int32_t *census = census_all + fd.pix_off;
+    const float *gD = fd.gD, *gN = fd.gN, *gO = fd.gO;
+    const double *pose = fd.pose;
+    float *acc = fd.acc;
+    double *d_pose = fd.d_pose;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
@@ -305,7 +325,7 @@ k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ fra
                     pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
                 }
                 if (!pose_only) {
-                    float *a = acc + (size_t)id * kAccStride;
+                    float *a = acc + (size_t)(id - fd.item_off) * kAccStride;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
@@ -323,8 +343,8 @@ k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ fra
         }
     }
     if (inside) {
-        census[2 * (size_t)H * W + p] = n_eval;
-        census[3 * (size_t)H * W + p] = n_con;
+        census[2 * total_pixels + p] = n_eval;
+        census[3 * total_pixels + p] = n_con;
     }
     // block reduction of the pose partials, then FP64 atomics
 #pragma unroll
@@ -348,56 +368,49 @@ k_raster_bwd(const RasterRec *__restrict__ rec, const FrameRec *__restrict__ fra
 }
 
 template <int TW>
-void fwd_launch(const Layout &L, const slr_sensor &sen, char *ws, float *depth, float *normal, float *alpha,
-                hipStream_t stream)
+void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
-    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    hipLaunchKernelGGL(k_raster_fwd<TW>, dim3((unsigned)L.ntiles), dim3(256), 0, stream,
-                       reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
-                       reinterpret_cast<const int2 *>(ws + L.ranges), tab, tab + L.W, (int)L.H, (int)L.W,
-                       (int)L.tiles_x, (float)sen.near_m, depth, normal, alpha,
-                       reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
-                       reinterpret_cast<int32_t *>(ws + L.census));
+    hipLaunchKernelGGL(k_raster_fwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
+                       reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),
+                       reinterpret_cast<const double2 *>(ws + L.tables), reinterpret_cast<float *>(ws + L.stateT),
+                       reinterpret_cast<int32_t *>(ws + L.stateN), reinterpret_cast<int32_t *>(ws + L.census), L.pixels);
 }
 
 template <int TW>
-void bwd_launch(const Layout &L, const slr_sensor &sen, char *ws, const double *pose, const float *gD,
-                const float *gN, const float *gO, double *d_pose, bool pose_only, hipStream_t stream)
+void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
-    const double2 *tab = reinterpret_cast<const double2 *>(ws + L.tables);
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.ntiles), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), tab, tab + L.W, (int)L.H, (int)L.W,
-                       (int)L.tiles_x, (float)sen.near_m, reinterpret_cast<const float *>(ws + L.stateT),
-                       reinterpret_cast<const int32_t *>(ws + L.stateN), gD, gN, gO, pose,
-                       reinterpret_cast<float *>(ws + L.acc), d_pose, pose_only ? 1 : 0,
-                       reinterpret_cast<int32_t *>(ws + L.census));
+                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                       reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
+                       reinterpret_cast<int32_t *>(ws + L.census), L.pixels, pose_only ? 1 : 0);
 }
 
 }  // namespace
 
-void launch_raster_fwd(const Layout &L, const slr_sensor &sen, char *ws, int64_t K, float *depth, float *normal,
-                       float *alpha, hipStream_t stream)
+void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream)
 {
-    (void)K;
+    if (L.tiles == 0) return;
     switch (L.tw) {
-    case 16: fwd_launch<16>(L, sen, ws, depth, normal, alpha, stream); break;
-    case 32: fwd_launch<32>(L, sen, ws, depth, normal, alpha, stream); break;
-    case 8: fwd_launch<8>(L, sen, ws, depth, normal, alpha, stream); break;
-    default: fwd_launch<64>(L, sen, ws, depth, normal, alpha, stream); break;
+    case 16: fwd_launch<16>(L, ws, stream); break;
+    case 32: fwd_launch<32>(L, ws, stream); break;
+    case 8: fwd_launch<8>(L, ws, stream); break;
+    default: fwd_launch<64>(L, ws, stream); break;
     }
 }
 
-void launch_raster_bwd(const Layout &L, const slr_sensor &sen, char *ws, const double *pose, const float *gD,
-                       const float *gN, const float *gO, double *d_pose, bool pose_only, hipStream_t stream)
+void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
+    if (L.tiles == 0) return;
     switch (L.tw) {
-    case 16: bwd_launch<16>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
-    case 32: bwd_launch<32>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
-    case 8: bwd_launch<8>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
-    default: bwd_launch<64>(L, sen, ws, pose, gD, gN, gO, d_pose, pose_only, stream); break;
+    case 16: bwd_launch<16>(L, ws, pose_only, stream); break;
+    case 32: bwd_launch<32>(L, ws, pose_only, stream); break;
+    case 8: bwd_launch<8>(L, ws, pose_only, stream); break;
+    default: bwd_launch<64>(L, ws, pose_only, stream); break;
     }
 }
 

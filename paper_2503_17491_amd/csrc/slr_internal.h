@@ -1,5 +1,12 @@
 // slr_internal.h -- data layouts and launcher declarations shared by the HIP
 // translation units of the rasterizer library.  Not part of the public ABI.
+//
+// The engine renders a batch of frames (keyframes) in one set of launches:
+// every kernel reads a per-frame descriptor from device memory, records are
+// indexed by a global item index (frame offset + surfel index), tiles by a
+// global tile index (frame tile offset + local tile), so one range sort, one
+// tile sort and one launch per compositing pass serve the whole batch.  The
+// plain per-image form is the batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,9 +41,26 @@ struct __align__(16) FrameRec {
 };
 static_assert(sizeof(FrameRec) == 96, "FrameRec layout");
 
-// Pixel box: rows [r0, r1], columns [c0, c1] and optionally [c2, c3].
+// Pixel box: rows [r0, r1], columns [c0, c1] and optionally [c2, c3]; frame
+// index of the record.
 struct __align__(16) PixBox {
-    int16_t r0, r1, c0, c1, c2, c3, pad0, pad1;
+    int16_t r0, r1, c0, c1, c2, c3, frame, pad;
+};
+
+// Per-frame descriptor (device memory).
+struct __align__(16) FrameDesc {
+    const double *pose;                                  // [4,4] T_cw
+    const float *means, *quats, *lsc, *logits;           // the frame's surfel set
+    float *depth, *normal, *alpha;                       // outputs
+    const float *gD, *gN, *gO;                           // upstream gradients (nullable)
+    double *d_pose;                                      // [6] pose gradient (never NULL)
+    float *acc;                                          // the set's gradient accumulator
+    int64_t n;                                           // surfels in the set
+    int64_t item_off;                                    // first record index
+    int64_t pix_off;                                     // first pixel of the per-pixel state
+    int64_t tab_off;                                     // first double2 of the direction tables
+    double fu, cu, fv, cv, near_m;
+    int32_t H, W, th, tw, tiles_x, tiles_y, tile_off, set;
 };
 
 // Gradient accumulator per surfel (world frame): dL/d(s_a t_a), dL/d(s_b t_b),
@@ -49,32 +73,39 @@ constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // items per block
 constexpr int kMaxDigitBits = 8;
 
-// Workspace layout for one image (offsets in bytes from the workspace base).
+// Angular margin (radians) by which the bounding box is widened on every side.
+constexpr double kBoxMargin = 2e-5;
+
+// Workspace layout of a batch (offsets in bytes from the workspace base).
 struct Layout {
-    int64_t n, cap, H, W, th, tw, tiles_x, tiles_y, ntiles;
-    int tile_bits;
-    size_t tables, rec, frame, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, ranges, hist, stateT, stateN, census, acc, misc, total;
-    int depth_passes, tile_passes;
-    // which buffers hold the sorted results after the passes
+    int32_t frames, sets, th, tw;
+    int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
+    int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
+    size_t desc, tables, tile_frame, rec, frame, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
+    size_t pt0, pv0, pt1, pv1, ranges, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
-Layout make_layout(int64_t n, int64_t cap, int32_t H, int32_t W, int32_t th, int32_t tw);
+struct FrameGeom {
+    int32_t H, W, set;
+};
+
+Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, const int64_t *set_n, int64_t cap,
+                   int32_t th, int32_t tw);
 
 // ---- launchers (all enqueue on `stream`) ----
-void launch_project(const slr_surfels &s, const double *pose, const slr_sensor &sen, const Layout &L,
-                    char *ws, double cos_m, double sin_m, hipStream_t stream);
+void launch_write_desc(const FrameDesc *host_descs, int32_t count, FrameDesc *dev, hipStream_t stream);
+void launch_tile_frame(const Layout &L, char *ws, hipStream_t stream);
+void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream);
 void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream);
 void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream);
-void launch_emit_and_tile_sort(const Layout &L, char *ws, int64_t K, hipStream_t stream);
-void launch_raster_fwd(const Layout &L, const slr_sensor &sen, char *ws, int64_t K, float *depth,
-                       float *normal, float *alpha, hipStream_t stream);
-void launch_raster_bwd(const Layout &L, const slr_sensor &sen, char *ws, const double *pose,
-                       const float *gD, const float *gN, const float *gO, double *d_pose, bool pose_only,
-                       hipStream_t stream);
-void launch_surfel_grad(const slr_surfels &s, const Layout &L, char *ws, float *d_means, float *d_quats,
-                        float *d_log_scales, float *d_logits, bool accumulate, hipStream_t stream);
+void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream);
+void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream);
+void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream);
+void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
+                        float *d_means, float *d_quats, float *d_log_scales, float *d_logits,
+                        bool accumulate, hipStream_t stream);
 void launch_loss_l1_normal(int64_t pixels, const float *depth, const float *normal, const float *td,
                            const float *tn, float wd, float wn, float *gD, float *gN, double *loss,
                            hipStream_t stream);

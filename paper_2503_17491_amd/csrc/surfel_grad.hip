@@ -13,14 +13,17 @@ namespace {
 
 __global__ void __launch_bounds__(256)
 k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restrict__ lsc,
-              const float *__restrict__ logits, const int32_t *__restrict__ counts, const float *__restrict__ acc,
-              float *__restrict__ d_means, float *__restrict__ d_quats, float *__restrict__ d_ls,
-              float *__restrict__ d_logits, int accumulate)
+              const float *__restrict__ logits, const float *__restrict__ acc, float *__restrict__ d_means,
+              float *__restrict__ d_quats, float *__restrict__ d_ls, float *__restrict__ d_logits, int accumulate)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     float4 gq4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (counts[k] == 0) {
+    const float *a = acc + (size_t)k * kAccStride;
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < kAccStride; ++c) any |= a[c] != 0.0f;
+    if (!any) {  // culled or never composited: zero gradient
         if (accumulate) return;
         d_means[3 * k] = 0.f; d_means[3 * k + 1] = 0.f; d_means[3 * k + 2] = 0.f;
         *reinterpret_cast<float4 *>(d_quats + 4 * k) = gq4;
@@ -28,7 +31,6 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
         d_logits[k] = 0.f;
         return;
     }
-    const float *a = acc + (size_t)k * kAccStride;
     double wa[3] = {a[0], a[1], a[2]}, wb[3] = {a[3], a[4], a[5]}, wn[3] = {a[9], a[10], a[11]};
     const float4 q4 = *reinterpret_cast<const float4 *>(quats + 4 * k);
     const double qn = sqrt((double)q4.x * q4.x + (double)q4.y * q4.y + (double)q4.z * q4.z + (double)q4.w * q4.w);
@@ -77,14 +79,13 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
 
 }  // namespace
 
-void launch_surfel_grad(const slr_surfels &s, const Layout &L, char *ws, float *d_means, float *d_quats,
-                        float *d_log_scales, float *d_logits, bool accumulate, hipStream_t stream)
+void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
+                        float *d_means, float *d_quats, float *d_log_scales, float *d_logits,
+                        bool accumulate, hipStream_t stream)
 {
-    if (s.n == 0) return;
-    hipLaunchKernelGGL(k_surfel_grad, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, stream, s.n, s.quats,
-                       s.log_scales, s.logits, reinterpret_cast<const int32_t *>(ws + L.cnt),
-                       reinterpret_cast<const float *>(ws + L.acc), d_means, d_quats, d_log_scales, d_logits,
-                       accumulate ? 1 : 0);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_surfel_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, quats, lsc, logits,
+                       acc, d_means, d_quats, d_log_scales, d_logits, accumulate ? 1 : 0);
 }
 
 }  // namespace slr

@@ -40,8 +40,20 @@ class Views(C.Structure):
                 ("census", C.c_void_p), ("tiles_x", C.c_int64), ("tiles_y", C.c_int64)]
 
 
+class Frame(C.Structure):
+    _fields_ = [("set", C.c_int32), ("pose_cw", C.c_void_p), ("sensor", Sensor), ("depth", C.c_void_p),
+                ("normal", C.c_void_p), ("alpha", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dnormal", C.c_void_p),
+                ("dL_dalpha", C.c_void_p), ("d_pose", C.c_void_p)]
+
+
+class SurfelGrads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("quats", C.c_void_p), ("log_scales", C.c_void_p), ("logits", C.c_void_p)]
+
+
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
-           "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times", "slr_status_string", "slr_last_error"]
+           "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
+           "slr_batch_counters", "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times",
+           "slr_status_string", "slr_last_error"]
 
 _lib = None
 
@@ -59,6 +71,12 @@ def lib():
         L.slr_render.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P]
         L.slr_backward.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
         L.slr_workspace_views.argtypes = [P, P, I64, I64, P, C.c_size_t, P]
+        BATCH = [I32, P, I32, P, P, I64, P, C.c_size_t]
+        L.slr_batch_workspace_size.argtypes = [I32, P, I32, P, P, I64, P]
+        L.slr_batch_prepare.argtypes = BATCH + [P]
+        L.slr_batch_render.argtypes = BATCH + [P]
+        L.slr_batch_backward.argtypes = [I32, P, P, I32, P, P, I64, P, C.c_size_t, C.c_uint32, P]
+        L.slr_batch_counters.argtypes = BATCH + [P]
         L.slr_loss_l1_normal.argtypes = [I64, P, P, P, P, C.c_float, C.c_float, P, P, P, P]
         L.slr_stage_timer_enable.argtypes = [I32]
         L.slr_stage_times.argtypes = [P, P]
@@ -66,7 +84,8 @@ def lib():
         L.slr_status_string.restype = C.c_char_p
         L.slr_last_error.restype = C.c_char_p
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
-                  "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times"):
+                  "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
+                  "slr_batch_counters", "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -226,6 +245,87 @@ class Renderer:
                     n_proc=take(v.n_proc, H * W, torch.int32).view(H, W),
                     census=take(v.census, 4 * H * W, torch.int32).view(4, H, W), tiles_x=int(v.tiles_x),
                     tiles_y=int(v.tiles_y), K=K)
+
+
+class BatchRenderer:
+    """Batched form: many frames (each its own pose, sensor and image size;
+    frames may share a surfel set) rendered and differentiated by one set of
+    launches with no host synchronisation, so a whole iteration can be
+    captured in a HIP graph.  Buffers (outputs, upstream gradients, pose and
+    surfel gradients) are owned here and stay at fixed addresses.
+
+    sets:   list of dicts with means, quats, log_scales, logits (CUDA tensors)
+    frames: list of dicts with set (index), T_cw (float64 [4,4] CUDA), sensor
+    """
+
+    def __init__(self, sets, frames, tiling=(16, 16), capacity=1 << 22, device="cuda"):
+        self.sets = sets
+        self.frames = frames
+        self.tiling = tuple(tiling)
+        self.capacity = int(capacity)
+        self.device = device
+        self.out, self.up, self.dpose = [], [], []
+        for f in frames:
+            H, W = int(f["sensor"]["height"]), int(f["sensor"]["width"])
+            _pose(f["T_cw"])
+            self.out.append((torch.zeros((H, W), device=device), torch.zeros((H, W, 3), device=device),
+                             torch.zeros((H, W), device=device)))
+            self.up.append((torch.zeros((H, W), device=device), torch.zeros((H, W, 3), device=device),
+                            torch.zeros((H, W), device=device)))
+            self.dpose.append(torch.zeros(6, dtype=torch.float64, device=device))
+        self.grads = [dict(means=torch.zeros_like(st["means"]), quats=torch.zeros_like(st["quats"]),
+                           log_scales=torch.zeros_like(st["log_scales"]), logits=torch.zeros_like(st["logits"]))
+                      for st in sets]
+        self._c_sets = (Surfels * max(len(sets), 1))(*[_surfels(st["means"], st["quats"], st["log_scales"],
+                                                                 st["logits"]) for st in sets])
+        self._c_grads = (SurfelGrads * max(len(sets), 1))(*[SurfelGrads(g["means"].data_ptr(), g["quats"].data_ptr(),
+                                                                         g["log_scales"].data_ptr(),
+                                                                         g["logits"].data_ptr()) for g in self.grads])
+        self._c_frames = (Frame * max(len(frames), 1))(*[
+            Frame(int(f["set"]), f["T_cw"].data_ptr(), _sensor(f["sensor"]), o[0].data_ptr(), o[1].data_ptr(),
+                  o[2].data_ptr(), u[0].data_ptr(), u[1].data_ptr(), u[2].data_ptr(), dp.data_ptr())
+            for f, o, u, dp in zip(frames, self.out, self.up, self.dpose)])
+        self.ws = None
+        self.prepare()
+
+    def _args(self):
+        t = Tiling(*self.tiling)
+        return [len(self.sets), self._c_sets, len(self.frames), self._c_frames, C.byref(t), self.capacity]
+
+    def prepare(self):
+        b = C.c_size_t(0)
+        _check(lib().slr_batch_workspace_size(*self._args(), C.byref(b)), "slr_batch_workspace_size")
+        if self.ws is None or self.ws.numel() < b.value:
+            self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        _check(lib().slr_batch_prepare(*self._args(), _ptr(self.ws), self.ws.numel(), _stream()), "slr_batch_prepare")
+        ptr = C.c_void_p(0)
+        _check(lib().slr_batch_counters(*self._args(), _ptr(self.ws), self.ws.numel(), C.byref(ptr)),
+               "slr_batch_counters")
+        off = ptr.value - self.ws.data_ptr()
+        self.counters = self.ws[off:off + 24].view(torch.int64)
+
+    def render(self):
+        _check(lib().slr_batch_render(*self._args(), _ptr(self.ws), self.ws.numel(), _stream()), "slr_batch_render")
+
+    def backward(self, pose_only=False, accumulate=False):
+        flags = (SLR_POSE_ONLY if pose_only else 0) | (SLR_ACCUMULATE if accumulate else 0)
+        a = self._args()
+        _check(lib().slr_batch_backward(a[0], a[1], None if pose_only else self._c_grads, a[2], a[3], a[4], a[5],
+                                        _ptr(self.ws), self.ws.numel(), flags, _stream()), "slr_batch_backward")
+
+    def pairs(self):
+        """(K, overflow) of the last render (synchronises)."""
+        c = self.counters.cpu().tolist()
+        return int(c[0]), int(c[1])
+
+    def ensure_capacity(self, margin=1.25):
+        """Grow the pair capacity if the last render overflowed; True if it did."""
+        K, over = self.pairs()
+        if over:
+            self.capacity = int(over * margin) + 4096
+            self.prepare()
+            return True
+        return False
 
 
 def loss_l1_normal(D, N, Dt, Nt, w_d, w_n, gD, gN, loss=None):

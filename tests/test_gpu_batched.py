@@ -1,0 +1,169 @@
+"""Batched form (many keyframes, one set of launches, HIP-graph capturable)
+against the plain per-image form and the oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def say(*a):
+    print("[gpu-batched]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def slr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_17491_amd import slr as S
+    S.lib()
+    return S
+
+
+def dev_set(sc):
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in sc.items()}
+
+
+def make_batch(slr, tiling=(16, 16), capacity=1 << 20):
+    shared, _ = synth.structured_scene(40000, 21)
+    own = synth.shell_scene(5000, 22)
+    sets = [dev_set(shared), dev_set(own)]
+    poses = synth.circle_poses(3, 4)
+    sizes = [(64, 512), (32, 1800), (128, 1024), (37, 300)]
+    frames = []
+    for k, (H, W) in enumerate(sizes):
+        T = poses[k % 3] if k < 3 else synth.perturbed_pose(5)
+        frames.append(dict(set=0 if k < 3 else 1, T_cw=torch.from_numpy(T).to(DEV), T_np=T,
+                           sensor=slr.make_sensor(H, W)))
+    return sets, frames, [shared, own], slr.BatchRenderer(sets, frames, tiling, capacity)
+
+
+def upstream(br, seed):
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    for u in br.up:
+        for t in u:
+            t.copy_(torch.randn(t.shape, generator=g))
+
+
+def plain_frame(slr, st, f, tiling, up):
+    r = slr.Renderer(f["sensor"], tiling, 1 << 20)
+    D, N, A = r.forward(st["means"], st["quats"], st["log_scales"], st["logits"], f["T_cw"])
+    g, dp = r.backward(st["means"], st["quats"], st["log_scales"], st["logits"], f["T_cw"], up[0], up[1], up[2])
+    return (D, N, A), g, dp, r
+
+
+@pytest.mark.parametrize("tiling", [(16, 16), (8, 32)])
+def test_batched_matches_plain(slr, tiling):
+    say("batched vs plain", tiling)
+    sets, frames, _, br = make_batch(slr, tiling)
+    upstream(br, 1)
+    br.render()
+    br.backward()
+    torch.cuda.synchronize()
+    K, over = br.pairs()
+    assert over == 0 and K > 0
+    sum_g = {k: torch.zeros_like(v) for k, v in br.grads[0].items()}
+    Ksum = 0
+    for k, f in enumerate(frames):
+        (D, N, A), g, dp, r = plain_frame(slr, sets[f["set"]], f, tiling, br.up[k])
+        Ksum += r.K
+        # forward: bit-identical (same per-pixel contributor order and arithmetic)
+        for a, b in zip((D, N, A), br.out[k]):
+            assert torch.equal(a, b), f"frame {k}"
+        np.testing.assert_allclose(br.dpose[k].cpu().numpy(), dp.cpu().numpy(), rtol=1e-6, atol=1e-9)
+        if f["set"] == 0:
+            for key in sum_g:
+                sum_g[key] += g[key]
+        else:
+            for key in g:
+                np.testing.assert_allclose(br.grads[1][key].cpu().numpy(), g[key].cpu().numpy(), rtol=1e-4,
+                                           atol=1e-6)
+    assert K == Ksum
+    for key in sum_g:
+        a, b = br.grads[0][key].cpu().numpy(), sum_g[key].cpu().numpy()
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 1e-4 * scale, key
+
+
+def test_batched_forward_matches_oracle(slr):
+    say("batched vs oracle")
+    sets, frames, host_sets, br = make_batch(slr)
+    br.render()
+    torch.cuda.synchronize()
+    EX = O.FLAG_SUPPORT | O.FLAG_NEAR | O.FLAG_AMIN | O.FLAG_TSTOP
+    for k, f in enumerate(frames):
+        sc = host_sets[f["set"]]
+        if f["sensor"]["height"] * f["sensor"]["width"] > 70000:
+            g = np.random.default_rng(k)
+            pix = np.stack([g.integers(0, f["sensor"]["height"], 3000), g.integers(0, f["sensor"]["width"], 3000)],
+                           1).astype(np.int32)
+        else:
+            pix = O.all_pixels(f["sensor"])
+        ref = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], f["T_np"], f["sensor"], pix)
+        D = br.out[k][0].cpu().numpy()[pix[:, 0], pix[:, 1]].astype(np.float64)
+        A = br.out[k][2].cpu().numpy()[pix[:, 0], pix[:, 1]].astype(np.float64)
+        ok = (ref["flags"] & EX) == 0
+        assert ok.mean() > 0.99
+        eD = np.abs(D - ref["depth"]) / np.maximum(np.abs(ref["depth"]), 1.0)
+        eA = np.abs(A - ref["alpha"]) / np.maximum(ref["alpha"], 1e-2)
+        say(f"frame {k}: depth {eD[ok].max():.2e} alpha {eA[ok].max():.2e}")
+        assert eD[ok].max() <= 1e-4 and eA[ok].max() <= 1e-4
+
+
+def test_batched_overflow_flag_then_grow(slr):
+    say("batched overflow")
+    sets, frames, _, br = make_batch(slr, capacity=1000)
+    br.render()
+    K, over = br.pairs()
+    assert over == K and K > 1000
+    assert not any(o[0].any().item() for o in br.out)  # nothing was binned
+    assert br.ensure_capacity()
+    br.render()
+    K2, over2 = br.pairs()
+    assert over2 == 0 and K2 == K
+    assert any(o[0].any().item() for o in br.out)
+
+
+def test_graph_capture_replays_match_eager(slr):
+    say("graph capture")
+    sets, frames, _, br = make_batch(slr)
+    upstream(br, 2)
+    br.render()
+    br.backward()
+    torch.cuda.synchronize()
+    ref_out = [tuple(t.clone() for t in o) for o in br.out]
+    ref_g = {k: v.clone() for k, v in br.grads[0].items()}
+    ref_p = [p.clone() for p in br.dpose]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        br.render()
+        br.backward()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=s):
+        br.render()
+        br.backward()
+    for rep in range(3):
+        for o in br.out:  # eager work between replays
+            for t in o:
+                t.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(br.out, ref_out):
+            for a, b in zip(o, r):
+                assert torch.equal(a, b), f"replay {rep}"
+        for k in ref_g:
+            d = (br.grads[0][k] - ref_g[k]).abs().max().item()
+            assert d <= 1e-4 * ref_g[k].abs().max().item(), (rep, k)
+        for p, r in zip(br.dpose, ref_p):
+            np.testing.assert_allclose(p.cpu().numpy(), r.cpu().numpy(), rtol=1e-6, atol=1e-9)
