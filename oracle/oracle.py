@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB lets the planted-mistake test point the pins at a mutated build.
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 # guard-band flag bits (oracle.c)
 FLAG_SUPPORT, FLAG_NEAR, FLAG_AMIN, FLAG_TSTOP, FLAG_CLAMP, FLAG_KEYTIE = 1, 2, 4, 8, 16, 32

@@ -135,3 +135,22 @@ def test_opacity_channel_gradient_closed_form():
     an = O.backward_pixels((5 * v)[None], q[None], np.log([[0.05, 0.05]]), [math.log(o / (1 - o))], np.eye(4), s,
                            [[i, j]], None, None, [1.0], exact=True)
     assert an["logits"][0] == pytest.approx(o * (1 - o), rel=1e-9)
+
+
+def test_clamped_alpha_has_no_gradient():
+    """alpha = min(0.99, o G): where the clamp is active alpha is constant, so
+    the opacity channel has zero gradient w.r.t. every parameter, at the centre
+    pixel and at a neighbour where s_hat != 0 but o G > 0.99 still."""
+    s = O.make_sensor(16, 512)
+    i, j = 8, 200
+    v = h.ray_dir(s, i, j)
+    q = h.facing_surfel(10 * v, -v)
+    o = 0.9999
+    for jj in (j, j + 1):
+        an = O.backward_pixels((10 * v)[None], q[None], np.log([[1.5, 1.5]]), [math.log(o / (1 - o))], np.eye(4), s,
+                               [[i, jj]], None, None, [1.0], exact=True)
+        r = O.render_pixels((10 * v)[None], q[None], np.log([[1.5, 1.5]]), [math.log(o / (1 - o))], np.eye(4), s,
+                            [[i, jj]], exact=True, guard=None)
+        assert r["alpha"][0] == pytest.approx(0.99, rel=1e-15)
+        for k in ("means", "quats", "log_scales", "logits"):
+            assert not np.any(an[k]), (jj, k)

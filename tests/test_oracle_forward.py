@@ -147,6 +147,30 @@ def test_alpha_thresholds_and_stop():
     assert r["T_final"][0] == pytest.approx(0.05 ** 3, rel=1e-10)
 
 
+def test_support_edge():
+    """The 3-sigma square bounds the support: a fronto-parallel surfel centred on
+    one pixel ray contributes at pixels whose intersection lies just inside
+    |s_hat| = 3 and not at pixels just outside."""
+    s = sensor()
+    i, j, d = 30, 200, 10.0
+    v = h.ray_dir(s, i, j)
+    q = h.facing_surfel(d * v, -v, 0.0)
+    ta = h.rot_from_quat_wxyz(q)[:, 0]
+    hits = {}
+    for jj in range(j - 18, j + 19):
+        w = h.ray_dir(s, i, jj)
+        sh, t = h.ray_plane_shat(*h.sensor_frame_vectors(d * v, q, np.log([0.6, 0.6]), 3.0, np.eye(4))[:4], w)
+        r = O.render_pixels((d * v)[None], q[None], np.log([[0.6, 0.6]]), [3.0], np.eye(4), s, pix=[[i, jj]],
+                            exact=True, guard=None)
+        hits[jj] = (max(abs(sh[0]), abs(sh[1])), r["n_contrib"][0])
+    inside = [m for m, c in hits.values() if c == 1]
+    outside = [m for m, c in hits.values() if c == 0]
+    assert inside and outside
+    # pixels sample s_hat every ~0.2 splat units: the edge is pinned to +-0.2
+    assert 2.8 < max(inside) <= 3.0 < min(outside) < 3.2
+    assert ta is not None
+
+
 def test_near_plane_rejects():
     """An intersection at t <= near contributes nothing."""
     s = sensor(near=0.2)
@@ -154,6 +178,22 @@ def test_near_plane_rejects():
     m, q, l, g, _ = _fronto(s, i, j, 0.19, 0.8, scales=(0.01, 0.01))
     r = O.render_pixels(m[None], q[None], l[None], [g], np.eye(4), s, pix=[[i, j]], exact=True)
     assert r["n_contrib"][0] == 0
+
+
+def test_near_plane_rejects_behind_and_close():
+    """A 6 m horizontal surfel whose plane passes 4 cm below the sensor (centre
+    0.5 m ahead, so not culled).  Upward rays meet its plane behind the sensor
+    and see nothing; downward rays meet it at range 0.04 / sin|el|, which is
+    inside the 0.2 m near range below el = -asin(0.2) and visible above."""
+    s = sensor(32, 256)
+    q = h.quat_wxyz_from_rot(np.eye(3))
+    img = O.render_image(np.array([[0.5, 0.0, -0.04]]), q[None], np.log([[1.0, 1.0]]), [3.0], np.eye(4), s,
+                         exact=True, guard=None)
+    seen = (img["alpha"] > 0).any(axis=1)
+    el = ((np.arange(32) + 0.5) - s["cv"]) / s["fv"]
+    assert not seen[el > 0].any()                                  # behind the sensor
+    assert not seen[el < -math.asin(0.2)].any()                    # within the near range
+    assert seen[(el < -math.radians(1.0)) & (el > -math.asin(0.2) + 0.01)].all()
 
 
 def test_intersection_matches_ray_plane():
