@@ -317,25 +317,68 @@ int or_render_pixels(int64_t n, const double *means, const double *quats, const 
     return 0;
 }
 
+/* Supp. D, last block: gradients w.r.t. the raw parameters of one surfel from
+ * its sensor-frame gradients g13 = (dL/db_alpha, dL/db_beta, dL/db_c, dL/dn,
+ * dL/do).  out10 = (mean[3], quaternion[4], log-scales[2], logit[1]). */
+static void raw_from_frame(const or_frame *f, const double *Rc, const double *g, double *out10)
+{
+    double *gm = out10, *gq = out10 + 3, *gl = out10 + 7;
+    /* world-frame vectors: R_cw^T g */
+    double wA[3], wB[3], wC[3], wN[3];
+    for (int c = 0; c < 3; ++c) {
+        wA[c] = Rc[c] * g[0] + Rc[3 + c] * g[1] + Rc[6 + c] * g[2];
+        wB[c] = Rc[c] * g[3] + Rc[3 + c] * g[4] + Rc[6 + c] * g[5];
+        wC[c] = Rc[c] * g[6] + Rc[3 + c] * g[7] + Rc[6 + c] * g[8];
+        wN[c] = Rc[c] * g[9] + Rc[3 + c] * g[10] + Rc[6 + c] * g[11];
+    }
+    for (int c = 0; c < 3; ++c) gm[c] = wC[c];                       /* dL/dmu */
+    double ta[3] = {f->R[0], f->R[3], f->R[6]}, tb[3] = {f->R[1], f->R[4], f->R[7]};
+    gl[0] = f->s[0] * dot3(wA, ta);                                  /* dL/dlog s_alpha */
+    gl[1] = f->s[1] * dot3(wB, tb);
+    out10[9] = f->o * (1.0 - f->o) * g[12];                          /* dL/dlogit */
+    /* dL/dR with columns (s_a wA, s_b wB, wN) */
+    double GR[9];
+    for (int r = 0; r < 3; ++r) {
+        GR[3 * r + 0] = f->s[0] * wA[r];
+        GR[3 * r + 1] = f->s[1] * wB[r];
+        GR[3 * r + 2] = wN[r];
+    }
+    double w = f->qhat[0], x = f->qhat[1], y = f->qhat[2], z = f->qhat[3];
+    double dRw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+    double dRx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+    double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+    double dRz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+    double gh[4] = {0, 0, 0, 0};
+    for (int e = 0; e < 9; ++e) {
+        gh[0] += GR[e] * dRw[e]; gh[1] += GR[e] * dRx[e];
+        gh[2] += GR[e] * dRy[e]; gh[3] += GR[e] * dRz[e];
+    }
+    double proj = gh[0] * w + gh[1] * x + gh[2] * y + gh[3] * z;   /* through q / |q| */
+    for (int c = 0; c < 4; ++c) gq[c] = (gh[c] - proj * f->qhat[c]) / f->qnorm;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Supp. D gradient computation for the pixels in the list, with upstream   */
 /* dL/dD, dL/dN (3) and dL/dO per listed pixel.  Outputs are overwritten:    */
 /* gradients w.r.t. the raw parameters (mean, unnormalised quaternion,       */
 /* log-scales, opacity logit) and w.r.t. delta = (rho; phi) in se(3) for     */
 /* T_cw(delta) = exp(-delta^) T_cw, i.e. the sensor pose update              */
-/* T_wc <- T_wc exp(delta) of Sec. 3.3.3.                                    */
+/* T_wc <- T_wc exp(delta) of Sec. 3.3.3.  g_abs (nullable, [n,10]) receives */
+/* per surfel the sum over pixels of |per-pixel contribution| to each raw    */
+/* parameter gradient: the scale an FP32 accumulation error is measured by.  */
 /* ------------------------------------------------------------------------ */
 int or_backward_pixels(int64_t n, const double *means, const double *quats, const double *log_scales,
                        const double *logits, const double *pose, const or_sensor *s,
                        int64_t P, const int32_t *pix,
                        const double *dL_dD, const double *dL_dN, const double *dL_dO,
                        double *g_means, double *g_quats, double *g_log_scales, double *g_logits,
-                       double *g_pose)
+                       double *g_pose, double *g_abs)
 {
     if (n < 0 || P < 0 || !s) return -1;
     or_frame *F = build_frames(n, means, quats, log_scales, logits, pose, s->near_m);
     /* per-surfel sensor-frame accumulators: g_alpha, g_beta, g_c, g_n (3 each), g_o */
     double *acc = (double *)calloc((size_t)(n > 0 ? n : 1) * 13, sizeof(double));
+    if (g_abs) memset(g_abs, 0, (size_t)(n > 0 ? n : 0) * 10 * sizeof(double));
     #pragma omp parallel
     {
         pair_list L = {0, 0, 0};
@@ -386,6 +429,19 @@ int or_backward_pixels(int64_t n, const double *means, const double *quats, cons
                 }
                 double go = p->clamped ? 0.0 : dA * p->G;
                 double *g = acc + 13 * (int64_t)p->id;
+                if (g_abs) {
+                    double g13[13], r10[10];
+                    for (int k = 0; k < 3; ++k) {
+                        g13[k] = gA[k]; g13[3 + k] = gB[k]; g13[6 + k] = gC[k]; g13[9 + k] = gN[k] * w;
+                    }
+                    g13[12] = go;
+                    raw_from_frame(f, pose, g13, r10);
+                    double *ga = g_abs + 10 * (int64_t)p->id;
+                    for (int k = 0; k < 10; ++k) {
+                        #pragma omp atomic
+                        ga[k] += fabs(r10[k]);
+                    }
+                }
                 for (int k = 0; k < 3; ++k) {
                     #pragma omp atomic
                     g[k] += gA[k];
@@ -413,38 +469,12 @@ int or_backward_pixels(int64_t n, const double *means, const double *quats, cons
         memset(gm, 0, 3 * sizeof(double)); memset(gq, 0, 4 * sizeof(double));
         gl[0] = gl[1] = 0.0; g_logits[k] = 0.0;
         if (!f->valid) continue;
-        /* world-frame vectors: R_cw^T g */
-        double wA[3], wB[3], wC[3], wN[3];
-        for (int c = 0; c < 3; ++c) {
-            wA[c] = Rc[c] * g[0] + Rc[3 + c] * g[1] + Rc[6 + c] * g[2];
-            wB[c] = Rc[c] * g[3] + Rc[3 + c] * g[4] + Rc[6 + c] * g[5];
-            wC[c] = Rc[c] * g[6] + Rc[3 + c] * g[7] + Rc[6 + c] * g[8];
-            wN[c] = Rc[c] * g[9] + Rc[3 + c] * g[10] + Rc[6 + c] * g[11];
-        }
-        for (int c = 0; c < 3; ++c) gm[c] = wC[c];                       /* dL/dmu */
-        double ta[3] = {f->R[0], f->R[3], f->R[6]}, tb[3] = {f->R[1], f->R[4], f->R[7]};
-        gl[0] = f->s[0] * dot3(wA, ta);                                  /* dL/dlog s_alpha */
-        gl[1] = f->s[1] * dot3(wB, tb);
-        g_logits[k] = f->o * (1.0 - f->o) * g[12];                       /* dL/dlogit */
-        /* dL/dR with columns (s_a wA, s_b wB, wN) */
-        double GR[9];
-        for (int r = 0; r < 3; ++r) {
-            GR[3 * r + 0] = f->s[0] * wA[r];
-            GR[3 * r + 1] = f->s[1] * wB[r];
-            GR[3 * r + 2] = wN[r];
-        }
-        double w = f->qhat[0], x = f->qhat[1], y = f->qhat[2], z = f->qhat[3];
-        double dRw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
-        double dRx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
-        double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
-        double dRz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
-        double gh[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 9; ++e) {
-            gh[0] += GR[e] * dRw[e]; gh[1] += GR[e] * dRx[e];
-            gh[2] += GR[e] * dRy[e]; gh[3] += GR[e] * dRz[e];
-        }
-        double proj = gh[0] * w + gh[1] * x + gh[2] * y + gh[3] * z;   /* through q / |q| */
-        for (int c = 0; c < 4; ++c) gq[c] = (gh[c] - proj * f->qhat[c]) / f->qnorm;
+        double r10[10];
+        raw_from_frame(f, Rc, g, r10);
+        for (int c = 0; c < 3; ++c) gm[c] = r10[c];
+        for (int c = 0; c < 4; ++c) gq[c] = r10[3 + c];
+        gl[0] = r10[7]; gl[1] = r10[8];
+        g_logits[k] = r10[9];
         /* pose: d b / d rho = -I, d b / d phi = [b]_x for every sensor-frame vector */
         double t1[3], t2[3], t3[3], t4[3];
         cross3(g + 6, f->bc, t1); cross3(g + 0, f->ba, t2);

@@ -43,7 +43,7 @@ def lib():
         L.or_camera_matrix.argtypes = [C.c_double] * 4 + [C.c_int32, C.c_int32, P]
         L.or_pixel_basis.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.or_render_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
-        L.or_backward_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P]
+        L.or_backward_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
         L.or_bin.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_double,
                              P, P, P, P, C.c_int64, P, P, P, P]
         L.or_pair_support.argtypes = [P, P, P, C.c_double, P, P, C.c_int32, C.c_int32, P]
@@ -141,10 +141,13 @@ def render_image(means, quats, log_scales, logits, T_cw, sensor, guard=DEFAULT_G
                 n_contrib=o["n_contrib"].reshape(H, W), flags=o["flags"].reshape(H, W))
 
 
-def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, dL_dN, dL_dO, exact=False):
+def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, dL_dN, dL_dO, exact=False,
+                    with_abs=False):
     """Analytic FP64 gradients of sum_p (dL_dD D + dL_dN . N + dL_dO O) over the listed pixels.
 
-    Returns dict of means [n,3], quats [n,4], log_scales [n,2], logits [n], pose [6] (rho; phi).
+    Returns dict of means [n,3], quats [n,4], log_scales [n,2], logits [n], pose [6] (rho; phi);
+    with_abs adds abs [n,10]: per surfel, sum over pixels of |per-pixel contribution| to each
+    raw-parameter gradient (mean 3, quaternion 4, log-scales 2, logit 1).
     """
     n, m, q, ls, lo = _surfels(means, quats, log_scales, logits, exact)
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 2)
@@ -154,11 +157,14 @@ def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, 
     gO = None if dL_dO is None else np.ascontiguousarray(dL_dO, np.float64).reshape(P)
     out = dict(means=np.zeros((n, 3)), quats=np.zeros((n, 4)), log_scales=np.zeros((n, 2)),
                logits=np.zeros(n), pose=np.zeros(6))
+    if with_abs:
+        out["abs"] = np.zeros((n, 10))
     s = _sensor(sensor)
     pose = _pose12(T_cw)
     rc = lib().or_backward_pixels(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix),
                                   _p(gD), _p(gN), _p(gO), _p(out["means"]), _p(out["quats"]),
-                                  _p(out["log_scales"]), _p(out["logits"]), _p(out["pose"]))
+                                  _p(out["log_scales"]), _p(out["logits"]), _p(out["pose"]),
+                                  _p(out.get("abs")))
     if rc != 0:
         raise RuntimeError("or_backward_pixels failed")
     return out

@@ -15,12 +15,21 @@
 //
 // Backward: each pixel walks its list from the last contributor to the first,
 // recovering the transmittance before each pair by division, keeping the
-// suffix sums of the depth and normal channels, and forming the 14 per-pair
-// partials dL/dP, dL/dQ, dL/dM (each a multiple of v), dL/dtau, dL/do and
-// dL/dn.  They are summed over the wave with DPP row shifts and broadcasts,
-// then over the block's waves in LDS, and one thread per record converts the
-// sum to sensor-frame splat-axis gradients (FP64), adds the pose-gradient
-// contribution, rotates to the world frame and issues the atomics.
+// suffix sums of the depth and normal channels.  With a = P.v, b = Q.v,
+// c = M.v, the gradient w.r.t. the splat axes is, per pair,
+//   g_alpha = db (v x b_c) + dc_s (b_beta x v) + (g_t/c) s_alpha M
+//   g_beta  = da (b_c x v) + dc_s (v x b_alpha) + (g_t/c) s_beta M
+//   g_c     = da (v x b_beta) + db (b_alpha x v) + (g_t/c) M
+// (da, db, dc_s: dL/da, dL/db, dL/dc through s_hat; g_t = dL/d(range); the
+// range path is folded in closed form, t v - b_c = s_alpha b_alpha +
+// s_beta b_beta).  The sums over pixels are rebuilt from 18 per-pair partials:
+// da (v - c_hat), db (v - c_hat), dc_s v, da, db, (g_t/c)(s_alpha, s_beta, 1),
+// dL/do, dL/dn, where c_hat = b_c / |b_c|; subtracting c_hat in FP64 before
+// rounding keeps the products with the long vector b_c free of cancellation.
+// The partials are summed over the wave with DPP row shifts and broadcasts,
+// then over the block's waves in LDS; one thread per record assembles the
+// splat-axis gradients in FP64, adds the pose-gradient contribution, rotates
+// to the world frame and issues the atomics.
 #include "slr_internal.h"
 
 #pragma clang fp contract(off)
@@ -152,7 +161,7 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 }
 
 constexpr int kBwdBatch = 128;
-constexpr int kNg = 14;
+constexpr int kNg = 18;
 
 __device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
 {
@@ -164,13 +173,15 @@ __device__ __forceinline__ void dcross(const double *a, const double *b, double 
 template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
-             const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval,
-             const int2 *__restrict__ ranges, const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+             const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const ChatRec *__restrict__ chat,
+             const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
+             const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
              int pose_only)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
+    __shared__ ChatRec schat[kBwdBatch];
     __shared__ float sred[4][kNg][kBwdBatch];
     __shared__ int sflag[4][kBwdBatch];
     __shared__ int s_last;
@@ -220,14 +231,23 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
     }
     double pacc[6] = {0, 0, 0, 0, 0, 0};
-    float Bd = 0.0f, Bn0 = 0.0f, Bn1 = 0.0f, Bn2 = 0.0f;
+    // dL/dalpha_k = c_k A_k - B_k / (1 - alpha_k) + K T_final / (1 - alpha_k), with
+    // c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
+    // and K = gD t_ref + gN . n_ref + gO: the reference (the last contributor, met
+    // first in reverse) removes the cancellation of the unshifted form.
+    float Bs = 0.0f, Kref = 0.0f, tref = 0.0f, nr0 = 0.0f, nr1 = 0.0f, nr2 = 0.0f;
+    bool have_ref = false;
     int n_eval = 0, n_con = 0;
 
     for (int b_end = end; b_end > rg.x; b_end -= kBwdBatch) {
         const int b0 = max(rg.x, b_end - kBwdBatch);
         const int cnt = b_end - b0;
         __syncthreads();
-        if ((int)threadIdx.x < cnt) srec[threadIdx.x] = rec[pval[b0 + threadIdx.x]];
+        if ((int)threadIdx.x < cnt) {
+            const uint32_t id = pval[b0 + threadIdx.x];
+            srec[threadIdx.x] = rec[id];
+            schat[threadIdx.x] = chat[id];
+        }
         __syncthreads();
         for (int k = cnt - 1; k >= 0; --k) {
             const uint32_t rows = srec[k].rows;
@@ -247,12 +267,15 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 const float n0 = srec[k].n[0], n1 = srec[k].n[1], n2 = srec[k].n[2];
                 const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
                 const float A = T * r1;  // transmittance in front of this pair
-                float dA = gd * (e.t * A - Bd * r1);
-                dA += gn0 * (n0 * A - Bn0 * r1) + gn1 * (n1 * A - Bn1 * r1) + gn2 * (n2 * A - Bn2 * r1);
-                dA += go * Tfin * r1;
+                if (!have_ref) {
+                    have_ref = true;
+                    tref = e.t; nr0 = n0; nr1 = n1; nr2 = n2;
+                    Kref = gd * tref + gn0 * nr0 + gn1 * nr1 + gn2 * nr2 + go;
+                }
+                const float ck = gd * (e.t - tref) + gn0 * (n0 - nr0) + gn1 * (n1 - nr1) + gn2 * (n2 - nr2);
+                const float dA = ck * A + (Kref * Tfin - Bs) * r1;
                 const float w = e.alpha * A;
-                Bd = fmaf(e.t, w, Bd);
-                Bn0 = fmaf(n0, w, Bn0); Bn1 = fmaf(n1, w, Bn1); Bn2 = fmaf(n2, w, Bn2);
+                Bs = fmaf(ck, w, Bs);
                 T = A;
                 const float gt = gd * w;  // dL/d(range)
                 float dsa = 0.0f, dsb = 0.0f, dop = 0.0f;
@@ -262,13 +285,17 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                     dop = dA * e.G;
                 }
                 const float da = dsa * e.rc, db = dsb * e.rc;
-                const float dc = -(dsa * e.sa + dsb * e.sb + gt * e.t) * e.rc;
-                g[0] = da * fvx; g[1] = da * fvy; g[2] = da * fvz;
-                g[3] = db * fvx; g[4] = db * fvy; g[5] = db * fvz;
-                g[6] = dc * fvx; g[7] = dc * fvy; g[8] = dc * fvz;
-                g[9] = gt * e.rc;
-                g[10] = dop;
-                g[11] = gn0 * w; g[12] = gn1 * w; g[13] = gn2 * w;
+                const float dcs = -(dsa * e.sa + dsb * e.sb) * e.rc;
+                const float tt = gt * e.rc;
+                const float ex = (float)(vx - schat[k].c[0]), ey = (float)(vy - schat[k].c[1]),
+                            ez = (float)(vz - schat[k].c[2]);
+                g[0] = da * ex; g[1] = da * ey; g[2] = da * ez;
+                g[3] = db * ex; g[4] = db * ey; g[5] = db * ez;
+                g[6] = dcs * fvx; g[7] = dcs * fvy; g[8] = dcs * fvz;
+                g[9] = da; g[10] = db;
+                g[11] = tt * e.sa; g[12] = tt * e.sb; g[13] = tt;
+                g[14] = dop;
+                g[15] = gn0 * w; g[16] = gn1 * w; g[17] = gn2 * w;
             }
             if (__any(act)) {
 #pragma unroll
@@ -301,20 +328,24 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 const uint32_t id = pval[b0 + k];
                 const FrameRec fr = frame[id];
                 const RasterRec &rr = srec[k];
-                double dP[3] = {s[0], s[1], s[2]}, dQ[3] = {s[3], s[4], s[5]}, dM[3] = {s[6], s[7], s[8]};
-                const double dtau = s[9];
+                const double *ch = schat[k].c;
+                const double Ea[3] = {s[0], s[1], s[2]}, Eb[3] = {s[3], s[4], s[5]}, Cs[3] = {s[6], s[7], s[8]};
+                const double Aa = s[9], Ab = s[10], Ta = s[11], Tb = s[12], Tc = s[13];
+                double dPv[3], dQv[3];  // sum da v, sum db v
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { dPv[c] = Ea[c] + Aa * ch[c]; dQv[c] = Eb[c] + Ab * ch[c]; }
                 double t1[3], t2[3];
                 double ga[3], gb[3], gc[3];
-                dcross(dQ, fr.bc, t1); dcross(fr.bb, dM, t2);
+                dcross(Eb, fr.bc, t1); dcross(fr.bb, Cs, t2);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ga[c] = t1[c] + t2[c] + dtau * rr.P[c];
-                dcross(fr.bc, dP, t1); dcross(dM, fr.ba, t2);
+                for (int c = 0; c < 3; ++c) ga[c] = t1[c] + t2[c] + Ta * rr.M[c];
+                dcross(fr.bc, Ea, t1); dcross(Cs, fr.ba, t2);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gb[c] = t1[c] + t2[c] + dtau * rr.Q[c];
-                dcross(dP, fr.bb, t1); dcross(fr.ba, dQ, t2);
+                for (int c = 0; c < 3; ++c) gb[c] = t1[c] + t2[c] + Tb * rr.M[c];
+                dcross(dPv, fr.bb, t1); dcross(fr.ba, dQv, t2);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gc[c] = t1[c] + t2[c] + dtau * rr.M[c];
-                const double gn[3] = {s[11], s[12], s[13]};
+                for (int c = 0; c < 3; ++c) gc[c] = t1[c] + t2[c] + Tc * rr.M[c];
+                const double gn[3] = {s[15], s[16], s[17]};
                 const double nn[3] = {fr.n[0], fr.n[1], fr.n[2]};
                 // pose: d b / d rho = -I, d b / d phi = [b]_x
                 double c1[3], c2[3], c3[3], c4[3];
@@ -337,7 +368,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                         atomicAdd(a + 6 + c, (float)wc);
                         atomicAdd(a + 9 + c, (float)wn);
                     }
-                    atomicAdd(a + 12, s[10]);
+                    atomicAdd(a + 12, s[14]);
                 }
             }
         }
@@ -385,7 +416,8 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                       reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
+                       reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, pose_only ? 1 : 0);
 }

@@ -41,6 +41,12 @@ struct __align__(16) FrameRec {
 };
 static_assert(sizeof(FrameRec) == 96, "FrameRec layout");
 
+// Unit centre direction b_c / |b_c| of a record (FP64), the reference the
+// backward subtracts from pixel rays before accumulating.
+struct ChatRec {
+    double c[3];
+};
+
 // Pixel box: rows [r0, r1], columns [c0, c1] and optionally [c2, c3]; frame
 // index of the record.
 struct __align__(16) PixBox {
@@ -82,7 +88,7 @@ struct Layout {
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
-    size_t desc, tables, tile_frame, rec, frame, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
+    size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
     size_t pt0, pv0, pt1, pv1, ranges, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };

@@ -6,7 +6,10 @@
   oracle's guard band (pairs within rounding distance of a decision); the
   flagged fraction is bounded and flagged pixels are checked for validity.
 * Backward: relative 1e-3 on per-surfel gradient blocks and on the pose
-  6-vector, against the oracle's analytic FP64 gradients.
+  6-vector, against the oracle's analytic FP64 gradients.  A block's error is
+  divided by max(|g_ref|, 1e-3 RMS, 1e-2 sum_pixels |contribution|): a
+  gradient that is a near-cancelling sum of per-pixel contributions is held to
+  1e-5 of the magnitude summed, the precision an FP32 sum can promise.
 Large configurations compare sampled pixels (forward) or use upstream
 gradients that are non-zero only on sampled pixels (backward).
 """
@@ -167,12 +170,19 @@ def test_forward_parity_fullsize_sampled(slr):
 
 
 # ---------------------------------------------------------------- backward
-def block_err(g, ref):
-    """max over surfels of |g - ref| / max(|ref|, 1e-3 * RMS(ref)) per parameter block."""
+def block_err(g, ref, absum):
+    """max over surfels of |g - ref| / max(|ref|, 1e-3 RMS, 1e-2 |absum|) per parameter block;
+    the RMS is taken over the surfels whose reference block is non-zero, absum is the
+    oracle's per-surfel sum over pixels of |per-pixel contribution|."""
     g, ref = g.reshape(g.shape[0], -1), ref.reshape(ref.shape[0], -1)
-    rms = math.sqrt(float((ref ** 2).sum(1).mean())) + 1e-30
-    den = np.maximum(np.linalg.norm(ref, axis=1), 1e-3 * rms)
-    return float((np.linalg.norm(g - ref, axis=1) / den).max())
+    nrm = np.linalg.norm(ref, axis=1)
+    touched = nrm > 0
+    rms = math.sqrt(float((nrm[touched] ** 2).mean())) if touched.any() else 1.0
+    den = np.maximum(np.maximum(nrm, 1e-3 * rms), 1e-2 * np.linalg.norm(absum.reshape(absum.shape[0], -1), axis=1))
+    e = np.linalg.norm(g - ref, axis=1) / den
+    say(f"   block err p50 {np.median(e[touched]) if touched.any() else 0:.1e} p99.9 "
+        f"{np.quantile(e[touched], 0.999) if touched.any() else 0:.1e} max {e.max():.1e} over {int(touched.sum())}")
+    return float(e.max())
 
 
 def check_backward(slr, sc, T, sensor, pix, gD, gN, gO, tiling=(16, 16), capacity=1 << 16):
@@ -184,9 +194,10 @@ def check_backward(slr, sc, T, sensor, pix, gD, gN, gO, tiling=(16, 16), capacit
                           torch.from_numpy(GD).to(DEV), torch.from_numpy(GN).to(DEV), torch.from_numpy(GO).to(DEV))
     torch.cuda.synchronize()
     ref = O.backward_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix,
-                            gD.astype(np.float64), gN.astype(np.float64), gO.astype(np.float64))
-    errs = {k: block_err(g[k].cpu().numpy().astype(np.float64), ref[k]) for k in ("means", "quats", "log_scales",
-                                                                                 "logits")}
+                            gD.astype(np.float64), gN.astype(np.float64), gO.astype(np.float64), with_abs=True)
+    cols = dict(means=slice(0, 3), quats=slice(3, 7), log_scales=slice(7, 9), logits=slice(9, 10))
+    errs = {k: block_err(g[k].cpu().numpy().astype(np.float64), ref[k], ref["abs"][:, cols[k]])
+            for k in ("means", "quats", "log_scales", "logits")}
     dp = dpose.cpu().numpy()
     errs["pose"] = float(np.linalg.norm(dp - ref["pose"]) / max(np.linalg.norm(ref["pose"]), 1e-12))
     say("backward errors", {k: f"{v:.2e}" for k, v in errs.items()})
