@@ -127,6 +127,12 @@ def main():
                     help="form whose iter/s is reported as value (both are always timed)")
     ap.add_argument("--no-graph", action="store_true", help="batched form without HIP-graph capture")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--variant", choices=["default", "lds", "scalar"], default="default",
+                    help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
+    ap.add_argument("--only", choices=["both", "batched"], default="both",
+                    help="batched: skip the plain form (short profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -142,25 +148,38 @@ def main():
     slr.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     th, tw = (int(x) for x in args.tile.split("x"))
+    var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR}[args.variant]
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
     sc, d, sensor, kfs = build_workload(torch, slr, synth, targets)
-    rend = [slr.Renderer(sensor, (th, tw), capacity=4 << 20) for _ in kfs]
+    rend = [slr.Renderer(sensor, (th, tw, var), capacity=4 << 20) for _ in kfs]
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
 
-    # ---- plain form: per-keyframe launches, one host sync per keyframe for the pair count
-    for _ in range(args.warmup):
+    plain_iters = None
+    if args.only == "both":
+        # ---- plain form: per-keyframe launches, one host sync per keyframe for the pair count
+        for _ in range(args.warmup):
+            plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
+        torch.cuda.synchronize()
+        log("plain warmup done; pairs per keyframe:", [r.K for r in rend])
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
+        torch.cuda.synchronize()
+        plain_dt = time.perf_counter() - t0
+        plain_iters = args.steps / plain_dt
+        log(f"plain: {args.steps} steps in {plain_dt:.3f}s -> {plain_iters:.2f} iter/s")
+    else:
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
-    torch.cuda.synchronize()
-    log("plain warmup done; pairs per keyframe:", [r.K for r in rend])
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
-    torch.cuda.synchronize()
-    plain_dt = time.perf_counter() - t0
-    plain_iters = args.steps / plain_dt
-    log(f"plain: {args.steps} steps in {plain_dt:.3f}s -> {plain_iters:.2f} iter/s")
+        torch.cuda.synchronize()
     ef = cf = eb = cb = 0
     for r in rend:  # compositing work census (identical in both forms)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
@@ -170,7 +189,7 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
-    br = make_batch(torch, slr, d, sensor, kfs, (th, tw))
+    br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var))
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -223,6 +242,8 @@ def main():
             "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
             "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
     stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
+    if args.form == "plain" and plain_iters is None:
+        raise SystemExit("--form plain needs --only both")
     value = batched_iters if args.form == "batched" else plain_iters
     dt = batched_dt if args.form == "batched" else plain_dt
 
@@ -237,9 +258,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
-                   "form": args.form, "graph": graph is not None, "tile": args.tile, "keyframes": N_KF,
+                   "form": args.form, "graph": graph is not None, "tile": args.tile, "variant": args.variant, "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
-                   "plain_iter_s": round(plain_iters, 3), "pairs_per_step": pairs,
+                   "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
         "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms,
     }

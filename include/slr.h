@@ -65,10 +65,18 @@ typedef struct slr_sensor {
 } slr_sensor;
 
 /* Tile shape of the binning (Sec. 3.2.1 uses 16x16).  tile_h * tile_w must be
- * 256; supported shapes: 16x16, 8x32, 32x8, 4x64. */
+ * 256; supported shapes: 16x16, 8x32, 32x8, 4x64.  variant selects how the
+ * compositing kernels read a tile's surfel records: 0 = library default,
+ * 1 = staged through LDS in batches by the whole workgroup, 2 = each wave
+ * reads them through the scalar cache (no LDS, no workgroup barrier).  Every
+ * variant produces bit-identical forward outputs. */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
+    int32_t variant;
 } slr_tiling;
+#define SLR_VARIANT_DEFAULT 0
+#define SLR_VARIANT_LDS 1
+#define SLR_VARIANT_SCALAR 2
 
 /* Surfel set: raw parameters in device memory, FP32, row-major. */
 typedef struct slr_surfels {

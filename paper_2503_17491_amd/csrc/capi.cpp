@@ -80,6 +80,8 @@ slr_status check_tiling(const slr_tiling *t)
     const bool ok = (t->tile_h == 16 && t->tile_w == 16) || (t->tile_h == 8 && t->tile_w == 32) ||
                     (t->tile_h == 32 && t->tile_w == 8) || (t->tile_h == 4 && t->tile_w == 64);
     if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
+    if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_SCALAR)
+        return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
     return SLR_OK;
 }
 
@@ -195,6 +197,7 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
     }
     if (items >= (int64_t(1) << 31)) return fail(SLR_E_INVALID, "batch has %lld records, limit 2^31", (long long)items);
     b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w);
+    b->L.variant = tiling->variant == SLR_VARIANT_DEFAULT ? slr::kDefaultVariant : tiling->variant;
     if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");
     return SLR_OK;
 }

@@ -160,6 +160,74 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
 }
 
+// Forward, scalar-cache variant: every wave walks the tile's list on its own.
+// The record index and the record itself are wave-uniform, so they are read
+// with scalar loads into SGPRs and feed the VALU as scalar operands; no LDS,
+// no workgroup barrier, and a wave leaves as soon as its 64 pixels are done.
+template <int TW>
+__global__ void __launch_bounds__(256)
+k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+               const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+               const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
+               int32_t *__restrict__ census_all, int64_t total_pixels)
+{
+    constexpr int TH = 256 / TW;
+    const int tile = blockIdx.x;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = ty * TH + ly, j = tx * TW + lx;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wid = threadIdx.x >> 6;
+    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
+    int last = 0, n_eval = 0, n_con = 0;
+    bool done = !inside;
+    // software pipeline: the next record's scalar loads are issued before the
+    // current record is composited
+    RasterRec nxt;
+    if (rg.x < rg.y) nxt = rec[__builtin_amdgcn_readfirstlane(pval[rg.x])];
+    for (int idx = rg.x; idx < rg.y; ++idx) {
+        if (__all(done)) break;
+        const RasterRec r = nxt;
+        if (idx + 1 < rg.y) nxt = rec[__builtin_amdgcn_readfirstlane(pval[idx + 1])];
+        const uint32_t rows = __builtin_amdgcn_readfirstlane(r.rows);
+        if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) continue;
+        if (done) continue;
+        ++n_eval;
+        PairEval e;
+        if (!eval_pair(r, vx, vy, vz, near_m, e)) continue;
+        const float tT = T * (1.0f - e.alpha);
+        if (tT < kTMin) { done = true; continue; }
+        const float w = e.alpha * T;
+        D = fmaf(w, e.t, D);
+        N0 = fmaf(w, r.n[0], N0);
+        N1 = fmaf(w, r.n[1], N1);
+        N2 = fmaf(w, r.n[2], N2);
+        O += w;
+        T = tT;
+        last = idx + 1 - rg.x;
+        ++n_con;
+    }
+    if (inside) {
+        const int p = i * W + j;
+        fd.depth[p] = D;
+        fd.alpha[p] = O;
+        fd.normal[3 * p] = N0; fd.normal[3 * p + 1] = N1; fd.normal[3 * p + 2] = N2;
+        stT_all[fd.pix_off + p] = T;
+        stN_all[fd.pix_off + p] = last;
+        census_all[fd.pix_off + p] = n_eval;
+        census_all[total_pixels + fd.pix_off + p] = n_con;
+    }
+}
+
 constexpr int kBwdBatch = 128;
 constexpr int kNg = 18;
 
@@ -402,7 +470,8 @@ template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    hipLaunchKernelGGL(k_raster_fwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+    hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>, dim3((unsigned)L.tiles),
+                       dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),
                        reinterpret_cast<const double2 *>(ws + L.tables), reinterpret_cast<float *>(ws + L.stateT),

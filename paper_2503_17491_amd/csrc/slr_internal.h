@@ -79,12 +79,15 @@ constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // items per block
 constexpr int kMaxDigitBits = 8;
 
+// Compositing variant used when the caller asks for the default.
+constexpr int kDefaultVariant = SLR_VARIANT_LDS;
+
 // Angular margin (radians) by which the bounding box is widened on every side.
 constexpr double kBoxMargin = 2e-5;
 
 // Workspace layout of a batch (offsets in bytes from the workspace base).
 struct Layout {
-    int32_t frames, sets, th, tw;
+    int32_t frames, sets, th, tw, variant;
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;

@@ -26,7 +26,10 @@ class Sensor(C.Structure):
 
 
 class Tiling(C.Structure):
-    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32)]
+    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32)]
+
+
+VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR = 0, 1, 2
 
 
 class Surfels(C.Structure):

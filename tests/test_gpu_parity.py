@@ -146,7 +146,8 @@ def test_forward_identical_across_tilings_and_runs(slr):
     sc = synth.shell_scene(4000, 2)
     sensor = slr.make_sensor(64, 512)
     outs = []
-    for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16)]:
+    # (h, w, 2): the forward that reads records through the scalar cache
+    for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16), (16, 16, 2), (8, 32, 2), (4, 64, 2)]:
         _, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling)
         outs.append((D, N, A))
     for o in outs[1:]:
