@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--variant", choices=["default", "lds", "scalar"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
+    ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
+                    help="order in which the compositing kernels take tiles")
     ap.add_argument("--only", choices=["both", "batched"], default="both",
                     help="batched: skip the plain form (short profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -149,6 +151,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     th, tw = (int(x) for x in args.tile.split("x"))
     var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR}[args.variant]
+    sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     if args.copy_calib:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -157,7 +160,7 @@ def main():
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
     sc, d, sensor, kfs = build_workload(torch, slr, synth, targets)
-    rend = [slr.Renderer(sensor, (th, tw, var), capacity=4 << 20) for _ in kfs]
+    rend = [slr.Renderer(sensor, (th, tw, var, sch), capacity=4 << 20) for _ in kfs]
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
@@ -189,7 +192,7 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
-    br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var))
+    br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch))
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -258,7 +261,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
-                   "form": args.form, "graph": graph is not None, "tile": args.tile, "variant": args.variant, "keyframes": N_KF,
+                   "form": args.form, "graph": graph is not None, "tile": args.tile, "variant": args.variant, "schedule": args.schedule, "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},

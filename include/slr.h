@@ -66,17 +66,24 @@ typedef struct slr_sensor {
 
 /* Tile shape of the binning (Sec. 3.2.1 uses 16x16).  tile_h * tile_w must be
  * 256; supported shapes: 16x16, 8x32, 32x8, 4x64.  variant selects how the
- * compositing kernels read a tile's surfel records: 0 = library default,
- * 1 = staged through LDS in batches by the whole workgroup, 2 = each wave
- * reads them through the scalar cache (no LDS, no workgroup barrier).  Every
- * variant produces bit-identical forward outputs. */
+ * forward compositing kernel reads a tile's surfel records: 0 = library
+ * default, 1 = staged through LDS in batches by the whole workgroup, 2 = each
+ * wave reads them through the scalar cache (no LDS, no workgroup barrier).
+ * schedule selects the order in which the compositing kernels take tiles:
+ * 0 = library default, 1 = tile-id order, 2 = longest surfel list first
+ * (computed on the device after binning).  Every variant and schedule
+ * produces bit-identical forward outputs. */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
     int32_t variant;
+    int32_t schedule;
 } slr_tiling;
 #define SLR_VARIANT_DEFAULT 0
 #define SLR_VARIANT_LDS 1
 #define SLR_VARIANT_SCALAR 2
+#define SLR_SCHEDULE_DEFAULT 0
+#define SLR_SCHEDULE_TILE 1
+#define SLR_SCHEDULE_LONGEST 2
 
 /* Surfel set: raw parameters in device memory, FP32, row-major. */
 typedef struct slr_surfels {

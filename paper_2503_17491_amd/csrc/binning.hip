@@ -271,6 +271,44 @@ k_ranges(const uint32_t *__restrict__ ptile, const uint64_t *__restrict__ keff, 
     if (p == K - 1 || ptile[p + 1] != t) ranges[t].y = (int)(p + 1);
 }
 
+// Longest-first tile schedule: tiles are bucketed by their list length on a
+// half-octave scale (bucket 0 = empty) and written out in descending bucket
+// order, so the compositing kernels, which take tile order[blockIdx.x], start
+// the long lists first and fill the end of the launch with short ones.  One
+// workgroup; order within a bucket is arbitrary (it only changes which
+// workgroup runs first, never what a tile computes).
+constexpr int kOrderBuckets = 65;
+
+__device__ __forceinline__ int order_bucket(int len)
+{
+    if (len <= 0) return 0;
+    const int e = 31 - __clz(len);
+    const int half = e > 0 ? (len >> (e - 1)) & 1 : 0;
+    return 1 + 2 * e + half;
+}
+
+__global__ void __launch_bounds__(1024)
+k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t hist[kOrderBuckets];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < tiles; t += blockDim.x) {
+        const int2 r = ranges[t];
+        atomicAdd(&hist[order_bucket(r.y - r.x)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = kOrderBuckets - 1; b >= 0; --b) { const uint32_t c = hist[b]; hist[b] = acc; acc += c; }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < tiles; t += blockDim.x) {
+        const int2 r = ranges[t];
+        order[atomicAdd(&hist[order_bucket(r.y - r.x)], 1u)] = (uint32_t)t;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t count)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -334,11 +372,21 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
+static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.schedule != SLR_SCHEDULE_LONGEST || L.tiles == 0) return;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, reinterpret_cast<const int2 *>(ws + L.ranges),
+                       L.tiles, reinterpret_cast<uint32_t *>(ws + L.order));
+}
+
 void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
 {
     int2 *ranges = reinterpret_cast<int2 *>(ws + L.ranges);
     launch_fill_u32(ranges, 0u, 2 * L.tiles, stream);
-    if (L.items == 0 || L.cap == 0) return;
+    if (L.items == 0 || L.cap == 0) {
+        launch_tile_order(L, ws, stream);
+        return;
+    }
     const uint64_t *keff = reinterpret_cast<const uint64_t *>(ws + L.misc) + 2;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
@@ -360,6 +408,7 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream, ts, keff, ranges);
+    launch_tile_order(L, ws, stream);
 }
 
 }  // namespace slr

@@ -82,6 +82,8 @@ slr_status check_tiling(const slr_tiling *t)
     if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
     if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_SCALAR)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
+    if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
+        return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
     return SLR_OK;
 }
 
@@ -198,6 +200,7 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
     if (items >= (int64_t(1) << 31)) return fail(SLR_E_INVALID, "batch has %lld records, limit 2^31", (long long)items);
     b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w);
     b->L.variant = tiling->variant == SLR_VARIANT_DEFAULT ? slr::kDefaultVariant : tiling->variant;
+    b->L.schedule = tiling->schedule == SLR_SCHEDULE_DEFAULT ? slr::kDefaultSchedule : tiling->schedule;
     if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");
     return SLR_OK;
 }
@@ -379,6 +382,7 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
     L.ranges = take(8 * (size_t)L.tiles);
+    L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));
     L.stateT = take(4 * (size_t)L.pixels);
     L.stateN = take(4 * (size_t)L.pixels);

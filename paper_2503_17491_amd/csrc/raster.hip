@@ -93,13 +93,14 @@ __device__ __forceinline__ float wave_sum_lane63(float v)
 template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+             const uint32_t *__restrict__ order,
              const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
              const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
              int32_t *__restrict__ census_all, int64_t total_pixels)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[256];
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
@@ -167,12 +168,13 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+             const uint32_t *__restrict__ order,
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
                int32_t *__restrict__ census_all, int64_t total_pixels)
 {
     constexpr int TH = 256 / TW;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
@@ -241,6 +243,7 @@ __device__ __forceinline__ void dcross(const double *a, const double *b, double 
 template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+             const uint32_t *__restrict__ order,
              const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const ChatRec *__restrict__ chat,
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
@@ -255,7 +258,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
 
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
@@ -473,6 +476,7 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>, dim3((unsigned)L.tiles),
                        dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
+                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),
                        reinterpret_cast<const double2 *>(ws + L.tables), reinterpret_cast<float *>(ws + L.stateT),
                        reinterpret_cast<int32_t *>(ws + L.stateN), reinterpret_cast<int32_t *>(ws + L.census), L.pixels);
@@ -484,6 +488,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
+                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
                        reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),

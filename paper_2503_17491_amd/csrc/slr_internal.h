@@ -79,20 +79,21 @@ constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // items per block
 constexpr int kMaxDigitBits = 8;
 
-// Compositing variant used when the caller asks for the default.
+// Compositing variant and tile schedule used when the caller asks for the default.
 constexpr int kDefaultVariant = SLR_VARIANT_LDS;
+constexpr int kDefaultSchedule = SLR_SCHEDULE_TILE;
 
 // Angular margin (radians) by which the bounding box is widened on every side.
 constexpr double kBoxMargin = 2e-5;
 
 // Workspace layout of a batch (offsets in bytes from the workspace base).
 struct Layout {
-    int32_t frames, sets, th, tw, variant;
+    int32_t frames, sets, th, tw, variant, schedule;
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, ranges, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 

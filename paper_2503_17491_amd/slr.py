@@ -26,10 +26,11 @@ class Sensor(C.Structure):
 
 
 class Tiling(C.Structure):
-    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32)]
+    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32)]
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR = 0, 1, 2
+SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST = 0, 1, 2
 
 
 class Surfels(C.Structure):

@@ -146,8 +146,10 @@ def test_forward_identical_across_tilings_and_runs(slr):
     sc = synth.shell_scene(4000, 2)
     sensor = slr.make_sensor(64, 512)
     outs = []
-    # (h, w, 2): the forward that reads records through the scalar cache
-    for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16), (16, 16, 2), (8, 32, 2), (4, 64, 2)]:
+    # (h, w, 2): the forward that reads records through the scalar cache;
+    # (h, w, v, 2): tiles taken longest list first
+    for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16), (16, 16, 2), (8, 32, 2), (4, 64, 2),
+                   (16, 16, 1, 2), (32, 8, 2, 2)]:
         _, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling)
         outs.append((D, N, A))
     for o in outs[1:]:
@@ -228,7 +230,7 @@ def test_backward_parity_shell_full_image(slr):
 
 
 def test_backward_parity_structured_posed(slr):
-    say("backward structured-20k-posed-64x512 all pixels, 8x32 tiles")
+    say("backward structured-20k-posed-64x512 all pixels, 8x32 tiles, scalar forward, longest-first")
     sc, _ = synth.structured_scene(20000, 5)
     sensor = slr.make_sensor(64, 512)
     T = synth.circle_poses(8, 1)[2]
@@ -236,7 +238,7 @@ def test_backward_parity_structured_posed(slr):
     g = np.random.default_rng(2)
     P = pix.shape[0]
     check_backward(slr, sc, T, sensor, pix, g.normal(size=P).astype(np.float32),
-                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (8, 32))
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (8, 32, 2, 2))
 
 
 def test_backward_parity_fullsize_sparse(slr):
