@@ -138,7 +138,7 @@ slr_status slr_render(const slr_surfels *surfels, const double *pose_cw, const s
  * Upstream gradients (device, FP32): dL_ddepth [H,W], dL_dnormal [H,W,3],
  * dL_dalpha [H,W]; any may be NULL (= zero).  Outputs (device, overwritten):
  * d_means [n,3], d_quats [n,4], d_log_scales [n,2], d_logits [n] (all four
- * NULL, or all four set), d_pose [6] FP64 (nullable).  With SLR_POSE_ONLY in
+ * set; all four may be NULL when n == 0), d_pose [6] FP64 (nullable).  With SLR_POSE_ONLY in
  * flags the surfel gradients are skipped (they must be NULL); with
  * SLR_ACCUMULATE the surfel gradients are added to the outputs' current
  * contents (a map shared by several keyframes); d_pose is always overwritten. */

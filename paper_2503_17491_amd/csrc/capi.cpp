@@ -500,7 +500,9 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
     const bool accumulate = (flags & SLR_ACCUMULATE) != 0;
     const int nset = (d_means != nullptr) + (d_quats != nullptr) + (d_log_scales != nullptr) + (d_logits != nullptr);
     if (pose_only && nset != 0) return fail(SLR_E_INVALID, "SLR_POSE_ONLY takes NULL surfel gradients");
-    if (!pose_only && nset != 4) return fail(SLR_E_INVALID, "surfel gradient pointers must all be set");
+    // an empty set may pass NULL gradient arrays (there is nothing to write)
+    if (!pose_only && nset != 4 && !(surfels->n == 0 && nset == 0))
+        return fail(SLR_E_INVALID, "surfel gradient pointers must all be set");
     if (!pose_only && !aligned(d_quats, 16)) return fail(SLR_E_INVALID, "d_quats must be 16-byte aligned");
     if (pose_only && !d_pose) return fail(SLR_E_INVALID, "SLR_POSE_ONLY needs d_pose");
     if (flags & ~(SLR_POSE_ONLY | SLR_ACCUMULATE)) return fail(SLR_E_INVALID, "unknown flags 0x%x", flags);
