@@ -31,7 +31,7 @@ def dev_set(sc):
     return {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in sc.items()}
 
 
-def make_batch(slr, tiling=(16, 16), capacity=1 << 20):
+def make_batch(slr, tiling=(16, 16), capacity=4 << 20):
     shared, _ = synth.structured_scene(40000, 21)
     own = synth.shell_scene(5000, 22)
     sets = [dev_set(shared), dev_set(own)]
