@@ -597,13 +597,29 @@ static int surfel_box(const double *mu, const double *q, const double *ls, doubl
 
     const int32_t H = T->H, W = T->W;
     int full_az = 0, rows_top = 0, rows_bot = 0;   /* rows_top: extend to row 0; rows_bot: to row H-1 */
+    /* Does the sensor's z-axis meet the square?  With n = A x B (det = n_z) the
+     * axis meets the plane at height z* = (n.C)/det, and every point of the
+     * square lies within Rb = |C| + |A| + |B| of the sensor.  E bounds the
+     * rounding of n.C and det; each undecidable case widens the box. */
     double det = A[0] * B[1] - A[1] * B[0];
-    if (det == 0.0) {
-        full_az = 1; rows_top = 1; rows_bot = 1;
+    double n0 = A[1] * B[2] - A[2] * B[1], n1 = A[2] * B[0] - A[0] * B[2];
+    double sc = (n0 * C[0] + n1 * C[1]) + det * C[2];
+    double an = sqrt((A[0] * A[0] + A[1] * A[1]) + A[2] * A[2]);
+    double bn = sqrt((B[0] * B[0] + B[1] * B[1]) + B[2] * B[2]);
+    double nn = sqrt((n0 * n0 + n1 * n1) + det * det);
+    double Rb = (range + an) + bn;
+    double E = 4e-15 * (an * bn);
+    double as = fabs(sc);
+    if (!(as > (1e-9 * Rb) * nn + E * range)) {
+        full_az = 1; rows_top = 1; rows_bot = 1;      /* sensor (nearly) in the square's plane */
+    } else if (as - E * range > Rb * (fabs(det) + E)) {
+        /* the axis meets the plane beyond the square, or never (plane parallel to it) */
+    } else if (!(fabs(det) >= 1e-6 * nn)) {
+        full_az = 1; rows_top = 1; rows_bot = 1;      /* ill-conditioned solve */
     } else {
         double a = (B[0] * C[1] - B[1] * C[0]) / det;
         double b = (A[1] * C[0] - A[0] * C[1]) / det;
-        if (fabs(a) <= 1.0 + 1e-9 && fabs(b) <= 1.0 + 1e-9) {   /* z-axis pierces the square */
+        if (fabs(a) <= 1.0 + 1e-6 && fabs(b) <= 1.0 + 1e-6) {   /* z-axis pierces the square */
             double zp = (C[2] + a * A[2]) + b * B[2];
             full_az = 1;
             if (zp >= 0.0) rows_top = 1;

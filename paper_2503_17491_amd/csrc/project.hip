@@ -63,22 +63,38 @@ struct BoxOut {
     int r0, r1, c[4];
 };
 
-// Exact angular box of the square {C + a A + b B : |a|, |b| <= 1}.
-__device__ BoxOut angular_box(const double A[3], const double B[3], const double C[3], int H, int W,
+// Exact angular box of the square {C + a A + b B : |a|, |b| <= 1}; range = |C|.
+__device__ BoxOut angular_box(const double A[3], const double B[3], const double C[3], double range, int H, int W,
                               const double2 *__restrict__ col, const double2 *__restrict__ rlo,
                               const double2 *__restrict__ rhi, double cm, double sm)
 {
     BoxOut o;
     o.nint = 0;
     bool full_az = false, to_top = false, to_bottom = false;
+    // Does the z-axis meet the square?  With n = A x B (det = n_z) it meets the
+    // plane at height (n.C)/det; all of the square lies within |C| + |A| + |B|
+    // of the sensor.  E bounds the rounding of n.C and det; a case that the
+    // rounding leaves open widens the box.
     double det = A[0] * B[1] - A[1] * B[0];
-    if (det == 0.0) {
-        full_az = to_top = to_bottom = true;
+    double n0 = A[1] * B[2] - A[2] * B[1], n1 = A[2] * B[0] - A[0] * B[2];
+    double sc = (n0 * C[0] + n1 * C[1]) + det * C[2];
+    double an = sqrt((A[0] * A[0] + A[1] * A[1]) + A[2] * A[2]);
+    double bn = sqrt((B[0] * B[0] + B[1] * B[1]) + B[2] * B[2]);
+    double nn = sqrt((n0 * n0 + n1 * n1) + det * det);
+    double Rb = (range + an) + bn;
+    double E = 4e-15 * (an * bn);
+    double as = fabs(sc);
+    if (!(as > (1e-9 * Rb) * nn + E * range)) {
+        full_az = to_top = to_bottom = true;      // sensor (nearly) in the square's plane
+    } else if (as - E * range > Rb * (fabs(det) + E)) {
+        // the axis meets the plane beyond the square, or never
+    } else if (!(fabs(det) >= 1e-6 * nn)) {
+        full_az = to_top = to_bottom = true;      // ill-conditioned solve
     } else {
-        // where (if anywhere) the z-axis crosses the square's plane, in splat units
+        // where the z-axis crosses the square's plane, in splat units
         double a = (B[0] * C[1] - B[1] * C[0]) / det;
         double b = (A[1] * C[0] - A[0] * C[1]) / det;
-        if (fabs(a) <= 1.0 + 1e-9 && fabs(b) <= 1.0 + 1e-9) {
+        if (fabs(a) <= 1.0 + 1e-6 && fabs(b) <= 1.0 + 1e-6) {
             double zp = (C[2] + a * A[2]) + b * B[2];
             full_az = true;
             to_top = zp >= 0.0;
@@ -255,7 +271,7 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     }
     BoxOut bx;
     bx.nint = 0;
-    if (ok) bx = angular_box(A, B, C, H, W, col, rlo, rhi, cm, sm);
+    if (ok) bx = angular_box(A, B, C, range, H, W, col, rlo, rhi, cm, sm);
     int32_t cnt = 0;
     PixBox pb = {-1, -1, -1, -1, -1, -1, (int16_t)blockIdx.y, 0};
     if (bx.nint > 0) {

@@ -152,6 +152,35 @@ def test_box_tightness_aggregate():
     assert touched <= b["K"] <= 1.6 * touched
 
 
+def test_box_tightness_vertical_surfels():
+    """Surfels on vertical faces (box sides, cylinders) have a square whose plane
+    is parallel to the sensor's z axis; their box must stay as tight as any
+    other surfel's, not fall back to the whole image."""
+    s = O.make_sensor(64, 512)
+    sc, _ = synth.structured_scene(3000, 7)
+    T = synth.circle_poses(8, 0)[1]
+    b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s)
+    vertical = np.abs(h_normals(sc)[:, 2]) < 1e-6
+    assert vertical.sum() > 100
+    idx = np.nonzero(vertical)[0][:300]
+    sub = {k: v[idx] for k, v in sc.items()}
+    M = support_masks(sub, T, s)
+    touched_all = 0
+    for n, k in enumerate(idx):
+        rr, cc = np.nonzero(M[n])
+        touched = np.unique((rr // 16) * 32 + cc // 16).size
+        touched_all += touched
+        assert b["counts"][k] <= 2 * touched + 6, (k, int(b["counts"][k]), touched)
+    assert b["counts"][idx].sum() <= 1.6 * touched_all
+
+
+def h_normals(sc):
+    q = sc["quats"].astype(np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)], 1)
+
+
 def test_sorted_lists_match_lexsort():
     s = O.make_sensor(64, 512)
     sc = synth.shell_scene(2000, 1)
