@@ -81,7 +81,7 @@ constexpr int kMaxDigitBits = 8;
 
 // Compositing variant and tile schedule used when the caller asks for the default.
 constexpr int kDefaultVariant = SLR_VARIANT_LDS;
-constexpr int kDefaultSchedule = SLR_SCHEDULE_TILE;
+constexpr int kDefaultSchedule = SLR_SCHEDULE_LONGEST;
 
 // Angular margin (radians) by which the bounding box is widened on every side.
 constexpr double kBoxMargin = 2e-5;
