@@ -78,17 +78,63 @@ __device__ __forceinline__ float dpp_add(float v)
     return v + __int_as_float(s);
 }
 
-// Sum over the 64 lanes of a wave, valid in lane 63 (all lanes must be active).
-__device__ __forceinline__ float wave_sum_lane63(float v)
+template <int CTRL>
+__device__ __forceinline__ float dpp_perm(float v)
 {
-    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
-    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
-    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
-    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
-    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15
-    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
+
+// x + y after lanes 32..63 of x are exchanged with lanes 0..31 of y
+// (v_permlane32_swap): lanes 0..31 hold x's half sums, lanes 32..63 y's.
+__device__ __forceinline__ float fold32(float x, float y)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// x + y after the odd 16-lane rows of x are exchanged with the even rows of y
+// (v_permlane16_swap): rows 0, 2 hold x's row-pair sums, rows 1, 3 y's.
+__device__ __forceinline__ float fold16(float x, float y)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Within every group of 2*BIT lanes: the low half keeps x's pair sums, the high
+// half y's; the partner lane comes from the DPP permutation CTRL (a mirror or
+// quad permutation that maps each half onto the other).
+template <int BIT, int CTRL>
+__device__ __forceinline__ float fold_lanes(float x, float y, int lane)
+{
+    const bool hi = (lane & BIT) != 0;
+    const float s = hi ? y : x, t = hi ? x : y;
+    return s + dpp_perm<CTRL>(t);
+}
+
+// Wave sums of 18 per-lane values by a transposed butterfly: each stage halves
+// the lanes a value spans and packs two values into one register, so the 18
+// sums cost 43 VALU operations instead of six DPP steps per value.  On return
+// lane l holds the sum of value bitrev6(l) for bitrev6(l) < 18 (all 64 lanes
+// must be active).
+__device__ __forceinline__ float wave_sum18(const float (&g)[18], int lane)
+{
+    float z[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) z[m] = fold32(g[2 * m], g[2 * m + 1]);
+    float w[5];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = fold16(z[2 * q], z[2 * q + 1]);
+    w[4] = fold16(z[8], 0.0f);
+    const float u0 = fold_lanes<8, 0x140>(w[0], w[1], lane);  // row_mirror
+    const float u1 = fold_lanes<8, 0x140>(w[2], w[3], lane);
+    const float u2 = w[4] + dpp_perm<0x140>(w[4]);
+    const float v0 = fold_lanes<4, 0x141>(u0, u1, lane);      // row_half_mirror
+    const float v1 = u2 + dpp_perm<0x141>(u2);
+    const float r = fold_lanes<2, 0x4e>(v0, v1, lane);        // quad_perm [2,3,0,1]
+    return r + dpp_perm<0xb1>(r);                             // quad_perm [1,0,3,2]
+}
+
+__device__ __forceinline__ int bitrev6(int l) { return (int)(__builtin_bitreverse32((uint32_t)l) >> 26); }
 
 template <int TW>
 __global__ void __launch_bounds__(256)
@@ -253,8 +299,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
     __shared__ ChatRec schat[kBwdBatch];
-    __shared__ float sred[4][kNg][kBwdBatch];
-    __shared__ int sflag[4][kBwdBatch];
+    __shared__ float sred[kNg][kBwdBatch];   // wave sums of the four waves, added in LDS
+    __shared__ int sflag[kBwdBatch];
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
 
@@ -280,6 +326,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
     const int2 rg = ranges[tile];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int red_val = bitrev6(lane);  // the wave sum this lane holds after wave_sum18
     const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
     const int p = inside ? i * W + j : 0;
     float T = inside ? stT[p] : 1.0f;
@@ -291,6 +338,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
     const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
     if (threadIdx.x == 0) s_last = 0;
+    for (int e = threadIdx.x; e < kNg * kBwdBatch; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
+    for (int e = threadIdx.x; e < kBwdBatch; e += blockDim.x) sflag[e] = 0;
     __syncthreads();
     if (last > 0) atomicMax(&s_last, last);
     __syncthreads();
@@ -322,10 +371,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         __syncthreads();
         for (int k = cnt - 1; k >= 0; --k) {
             const uint32_t rows = srec[k].rows;
-            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) {
-                if (lane == 0) sflag[wid][k] = 0;
-                continue;
-            }
+            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) continue;
             const int pos = b0 + k - rg.x;
             float g[kNg];
 #pragma unroll
@@ -369,33 +415,21 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 g[15] = gn0 * w; g[16] = gn1 * w; g[17] = gn2 * w;
             }
             if (__any(act)) {
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) g[v] = wave_sum_lane63(g[v]);
-                if (lane == 63) {
-#pragma unroll
-                    for (int v = 0; v < kNg; ++v) sred[wid][v][k] = g[v];
-                    sflag[wid][k] = 1;
-                }
-            } else if (lane == 0) {
-                sflag[wid][k] = 0;
+                static_assert(kNg == 18, "wave_sum18 reduces 18 values");
+                const float tot = wave_sum18(g, lane);
+                if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
+                if (lane == 0) sflag[k] = 1;
             }
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int k = threadIdx.x;
-            float s[kNg];
-            bool any = false;
+            if (sflag[k]) {
+                // take the record's sums and leave the slots zeroed for the next batch
+                float s[kNg];
 #pragma unroll
-            for (int v = 0; v < kNg; ++v) s[v] = 0.0f;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                if (sflag[w][k]) {
-                    any = true;
-#pragma unroll
-                    for (int v = 0; v < kNg; ++v) s[v] += sred[w][v][k];
-                }
-            }
-            if (any) {
+                for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
+                sflag[k] = 0;
                 const uint32_t id = pval[b0 + k];
                 const FrameRec fr = frame[id];
                 const RasterRec &rr = srec[k];
