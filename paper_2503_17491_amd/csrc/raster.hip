@@ -71,6 +71,31 @@ __device__ __forceinline__ bool eval_pair(const RasterRec &r, double vx, double 
     return true;
 }
 
+// The same arithmetic as eval_pair without control flow: every quantity is
+// computed and the returned flag says whether the pair contributes, so two
+// pairs can be evaluated side by side; where it returns true, e holds exactly
+// the values eval_pair gives.
+__device__ __forceinline__ bool eval_pair_flat(const RasterRec &r, double vx, double vy, double vz, float near_m,
+                                               PairEval &e)
+{
+    const double a = fma(r.P[2], vz, fma(r.P[1], vy, r.P[0] * vx));
+    const double b = fma(r.Q[2], vz, fma(r.Q[1], vy, r.Q[0] * vx));
+    const double c = fma(r.M[2], vz, fma(r.M[1], vy, r.M[0] * vx));
+    const float af = (float)a, bf = (float)b, cf = (float)c;
+    const float lim = 3.0f * fabsf(cf);
+    const bool sup = fabsf(af) <= lim && fabsf(bf) <= lim && cf != 0.0f;
+    const float rc = __builtin_amdgcn_rcpf(cf);
+    const float t = r.tau * rc;
+    const float sa = af * rc, sb = bf * rc;
+    const float q = fmaf(sa, sa, sb * sb);
+    const float G = __builtin_amdgcn_exp2f(kNegHalfLog2e * q);
+    const float ag = r.opac * G;
+    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G;
+    e.clamped = ag > kAlphaMax;
+    e.alpha = e.clamped ? kAlphaMax : ag;
+    return sup && (t > near_m) && !(ag < kAlphaMin);
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v)
 {
@@ -146,6 +171,7 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[256];
+    __shared__ __align__(4) uint8_t slist[4][256];
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -168,31 +194,78 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
+    const int lane = threadIdx.x & 63;
     for (int b0 = rg.x; b0 < rg.y; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
         const int idx = b0 + threadIdx.x;
         if (idx < rg.y) srec[threadIdx.x] = rec[pval[idx]];
         __syncthreads();
         const int cnt = min(256, rg.y - b0);
-        for (int k = 0; k < cnt; ++k) {
+        // the batch's records whose pixel rows meet this wave's rows, in list order
+        int nact = 0;
+        for (int base = 0; base < cnt; base += 64) {
+            const int k = base + lane;
+            bool meets = false;
+            if (k < cnt) {
+                const uint32_t rows = srec[k].rows;
+                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+            }
+            const uint64_t m = __ballot(meets);
+            if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)k;
+            nact += __popcll(m);
+        }
+        __syncthreads();
+        // two records per step: both evaluations are independent, the blends
+        // then follow in list order
+        for (int q = 0; q < nact; q += 2) {
             if (__all(done)) break;
-            const uint32_t rows = srec[k].rows;
-            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) continue;
-            if (done) continue;
-            ++n_eval;
-            PairEval e;
-            if (!eval_pair(srec[k], vx, vy, vz, near_m, e)) continue;
-            const float tT = T * (1.0f - e.alpha);
-            if (tT < kTMin) { done = true; continue; }
-            const float w = e.alpha * T;
-            D = fmaf(w, e.t, D);
-            N0 = fmaf(w, srec[k].n[0], N0);
-            N1 = fmaf(w, srec[k].n[1], N1);
-            N2 = fmaf(w, srec[k].n[2], N2);
-            O += w;
-            T = tT;
-            last = b0 + k + 1 - rg.x;
-            ++n_con;
+            // q is even: both slots come in one 16-bit read
+            const uint32_t two = *reinterpret_cast<const uint16_t *>(&slist[wid][q]);
+            const int k0 = (int)(two & 0xffu);
+            const bool has1 = q + 1 < nact;
+            const int k1 = has1 ? (int)(two >> 8) : k0;
+            PairEval e0, e1;
+            const bool ok0 = eval_pair_flat(srec[k0], vx, vy, vz, near_m, e0);
+            const bool ok1 = eval_pair_flat(srec[k1], vx, vy, vz, near_m, e1) && has1;
+            if (!done) {
+                ++n_eval;
+                if (ok0) {
+                    const float tT = T * (1.0f - e0.alpha);
+                    if (tT < kTMin) {
+                        done = true;
+                    } else {
+                        const float w = e0.alpha * T;
+                        D = fmaf(w, e0.t, D);
+                        N0 = fmaf(w, srec[k0].n[0], N0);
+                        N1 = fmaf(w, srec[k0].n[1], N1);
+                        N2 = fmaf(w, srec[k0].n[2], N2);
+                        O += w;
+                        T = tT;
+                        last = b0 + k0 + 1 - rg.x;
+                        ++n_con;
+                    }
+                }
+            }
+            if (has1 && !done) {
+                ++n_eval;
+                if (ok1) {
+                    const float tT = T * (1.0f - e1.alpha);
+                    if (tT < kTMin) {
+                        done = true;
+                    } else {
+                        const float w = e1.alpha * T;
+                        D = fmaf(w, e1.t, D);
+                        N0 = fmaf(w, srec[k1].n[0], N0);
+                        N1 = fmaf(w, srec[k1].n[1], N1);
+                        N2 = fmaf(w, srec[k1].n[2], N2);
+                        O += w;
+                        T = tT;
+                        last = b0 + k1 + 1 - rg.x;
+                        ++n_con;
+                    }
+                }
+            }
         }
     }
     if (inside) {
