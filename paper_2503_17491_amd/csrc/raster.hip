@@ -360,7 +360,7 @@ __device__ __forceinline__ void dcross(const double *a, const double *b, double 
 }
 
 template <int TW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
              const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const ChatRec *__restrict__ chat,
@@ -374,6 +374,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     __shared__ ChatRec schat[kBwdBatch];
     __shared__ float sred[kNg][kBwdBatch];   // wave sums of the four waves, added in LDS
     __shared__ int sflag[kBwdBatch];
+    __shared__ uint8_t slist[4][kBwdBatch];
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
 
@@ -417,12 +418,10 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     if (last > 0) atomicMax(&s_last, last);
     __syncthreads();
     const int end = rg.x + s_last;
-
-    double R[9];
+    int wlast = last;  // the wave's largest contributor count
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
-    }
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     // dL/dalpha_k = c_k A_k - B_k / (1 - alpha_k) + K T_final / (1 - alpha_k), with
     // c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
@@ -442,16 +441,31 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             schat[threadIdx.x] = chat[id];
         }
         __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
-            const uint32_t rows = srec[k].rows;
-            if ((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) continue;
+        // the batch's records that meet this wave's rows and lie before its last
+        // contributor, in list order; they are walked in reverse
+        int nact = 0;
+        for (int base = 0; base < cnt; base += 64) {
+            const int kk = base + lane;
+            bool meets = false;
+            if (kk < cnt) {
+                const uint32_t rows = srec[kk].rows;
+                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
+            }
+            const uint64_t m = __ballot(meets);
+            if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)kk;
+            nact += __popcll(m);
+        }
+        __syncthreads();
+        for (int q = nact - 1; q >= 0; --q) {
+            const int k = slist[wid][q];
             const int pos = b0 + k - rg.x;
             float g[kNg];
 #pragma unroll
             for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
             PairEval e;
             n_eval += pos < last ? 1 : 0;
-            bool act = pos < last && eval_pair(srec[k], vx, vy, vz, near_m, e);
+            const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
             if (act) {
                 ++n_con;
                 const float n0 = srec[k].n[0], n1 = srec[k].n[1], n2 = srec[k].n[2];
@@ -534,6 +548,11 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                     pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
                 }
                 if (!pose_only) {
+                    double R[9];
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
+                    }
                     float *a = acc + (size_t)(id - fd.item_off) * kAccStride;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
