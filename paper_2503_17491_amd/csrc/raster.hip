@@ -41,6 +41,22 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -1 / (2 ln 2)
+// A wave with at most this many unfinished pixels walks the rest of its list
+// one pixel at a time with 64 records per step (see k_raster_fwd).
+constexpr int kStragglers = 16;
+
+__device__ __forceinline__ float bcast(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double bcast(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 struct PairEval {
     float sa, sb, t, rc, G, alpha;
@@ -218,8 +234,10 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         __syncthreads();
         // two records per step: both evaluations are independent, the blends
         // then follow in list order
-        for (int q = 0; q < nact; q += 2) {
-            if (__all(done)) break;
+        int q = 0;
+        for (; q < nact; q += 2) {
+            const uint64_t live = __ballot(!done);
+            if (live == 0 || __popcll(live) <= kStragglers) break;
             // q is even: both slots come in one 16-bit read
             const uint32_t two = *reinterpret_cast<const uint16_t *>(&slist[wid][q]);
             const int k0 = (int)(two & 0xffu);
@@ -265,6 +283,55 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                         ++n_con;
                     }
                 }
+            }
+        }
+        // Few unfinished pixels left: each of them in turn takes the wave, whose
+        // lanes evaluate 64 consecutive list entries for that pixel's ray; the
+        // contributing entries are then blended in list order with the same
+        // arithmetic as above, so the result does not depend on the mode.
+        uint64_t live = q < nact ? __ballot(!done) : 0ull;
+        while (live) {
+            const int pl = (int)__builtin_ctzll(live);
+            live &= live - 1;
+            const double pvx = bcast(vx, pl), pvy = bcast(vy, pl), pvz = bcast(vz, pl);
+            float sT = bcast(T, pl), sD = bcast(D, pl), sN0 = bcast(N0, pl), sN1 = bcast(N1, pl),
+                  sN2 = bcast(N2, pl), sO = bcast(O, pl);
+            int sLast = bcast(last, pl), sEval = 0, sCon = 0;
+            bool sDone = false;
+            for (int c = q; c < nact && !sDone; c += 64) {
+                const int e = c + lane;
+                const bool in = e < nact;
+                const int k = slist[wid][in ? e : c];
+                PairEval ev;
+                const bool ok = eval_pair_flat(srec[k], pvx, pvy, pvz, near_m, ev) && in;
+                uint64_t cm = __ballot(ok);
+                int counted = min(64, nact - c);
+                while (cm) {
+                    const int jl = (int)__builtin_ctzll(cm);
+                    cm &= cm - 1;
+                    const float a = bcast(ev.alpha, jl), tj = bcast(ev.t, jl);
+                    const int kj = bcast(k, jl);
+                    const float tT = sT * (1.0f - a);
+                    if (tT < kTMin) {
+                        sDone = true;
+                        counted = jl + 1;
+                        break;
+                    }
+                    const float w = a * sT;
+                    sD = fmaf(w, tj, sD);
+                    sN0 = fmaf(w, srec[kj].n[0], sN0);
+                    sN1 = fmaf(w, srec[kj].n[1], sN1);
+                    sN2 = fmaf(w, srec[kj].n[2], sN2);
+                    sO += w;
+                    sT = tT;
+                    sLast = b0 + kj + 1 - rg.x;
+                    ++sCon;
+                }
+                sEval += counted;
+            }
+            if (lane == pl) {
+                T = sT; D = sD; N0 = sN0; N1 = sN1; N2 = sN2; O = sO;
+                last = sLast; n_eval += sEval; n_con += sCon; done = sDone;
             }
         }
     }

@@ -157,6 +157,23 @@ def test_forward_identical_across_tilings_and_runs(slr):
             np.testing.assert_array_equal(a, b)
 
 
+def test_forward_state_identical_across_variants(slr):
+    """Same tiling, the two compositing kernels (records from LDS, with the
+    few-pixels-left mode, or through the scalar cache): identical per-pixel
+    state and work census, not only identical images."""
+    say("forward variants: per-pixel state and census")
+    sensor = slr.make_sensor(64, 512)
+    for sc in (synth.shell_scene(4000, 2), synth.structured_scene(30000, 3)[0]):
+        views = []
+        for tiling in [(16, 16, 1), (16, 16, 2)]:
+            r, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling, 1 << 20)
+            v = r.views()
+            views.append((D, N, A, v["T_final"].cpu().numpy(), v["n_proc"].cpu().numpy(),
+                          v["census"][:2].cpu().numpy()))
+        for a, b in zip(*views):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_forward_parity_fullsize_sampled(slr):
     """200k surfels on the structured scene at 128x1024 (the fwd+bwd workload)."""
     say("forward structured-200k-128x1024 sampled")
