@@ -127,7 +127,7 @@ def main():
                     help="form whose iter/s is reported as value (both are always timed)")
     ap.add_argument("--no-graph", action="store_true", help="batched form without HIP-graph capture")
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--variant", choices=["default", "lds", "scalar"], default="default",
+    ap.add_argument("--variant", choices=["default", "lds", "scalar", "wave"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
     ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
                     help="order in which the compositing kernels take tiles")
@@ -150,7 +150,8 @@ def main():
     slr.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     th, tw = (int(x) for x in args.tile.split("x"))
-    var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR}[args.variant]
+    var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR,
+           "wave": slr.VARIANT_WAVE}[args.variant]
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     if args.copy_calib:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

@@ -68,7 +68,9 @@ typedef struct slr_sensor {
  * 256; supported shapes: 16x16, 8x32, 32x8, 4x64.  variant selects how the
  * forward compositing kernel reads a tile's surfel records: 0 = library
  * default, 1 = staged through LDS in batches by the whole workgroup, 2 = each
- * wave reads them through the scalar cache (no LDS, no workgroup barrier).
+ * wave reads them through the scalar cache (no LDS, no workgroup barrier),
+ * 3 = one workgroup of one wave per 64-pixel strip of the tile, records read
+ * one per lane and shared through LDS (no workgroup barrier).
  * schedule selects the order in which the compositing kernels take tiles:
  * 0 = library default, 1 = tile-id order, 2 = longest surfel list first
  * (computed on the device after binning).  Every variant and schedule
@@ -81,6 +83,7 @@ typedef struct slr_tiling {
 #define SLR_VARIANT_DEFAULT 0
 #define SLR_VARIANT_LDS 1
 #define SLR_VARIANT_SCALAR 2
+#define SLR_VARIANT_WAVE 3
 #define SLR_SCHEDULE_DEFAULT 0
 #define SLR_SCHEDULE_TILE 1
 #define SLR_SCHEDULE_LONGEST 2

@@ -80,7 +80,7 @@ slr_status check_tiling(const slr_tiling *t)
     const bool ok = (t->tile_h == 16 && t->tile_w == 16) || (t->tile_h == 8 && t->tile_w == 32) ||
                     (t->tile_h == 32 && t->tile_w == 8) || (t->tile_h == 4 && t->tile_w == 64);
     if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
-    if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_SCALAR)
+    if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);

@@ -347,6 +347,177 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
 }
 
+// Forward, one wave per 64-pixel strip of a tile (a tile's strips are
+// independent workgroups: no workgroup barrier, and the strips of a long list
+// run on different compute units).  The list is read in chunks of 64 records,
+// one per lane, with the next chunk's loads in flight while the current one is
+// composited.  While the wave has many unfinished pixels, the chunk's records
+// that meet the strip's rows are compacted into LDS and every lane composites
+// its own pixel against them, two at a time; with few unfinished pixels left,
+// each of them in turn takes the wave and the lanes evaluate their own
+// records for that pixel.  Same arithmetic and order as k_raster_fwd, hence
+// bit-identical results.
+template <int TW>
+__global__ void __launch_bounds__(64)
+k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+               const uint32_t *__restrict__ order,
+               const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+               const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
+               int32_t *__restrict__ census_all, int64_t total_pixels)
+{
+    constexpr int TH = 256 / TW, SR = 64 / TW;   // tile rows, strip rows
+    __shared__ RasterRec sbuf[64];
+    __shared__ uint8_t sidx[64];
+    const int strip = (int)(blockIdx.x & 3u);
+    const int tslot = (int)(blockIdx.x >> 2);
+    const int tile = order ? (int)order[tslot] : tslot;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    float *depth = fd.depth, *normal = fd.normal, *alpha = fd.alpha;
+    float *stT = stT_all + fd.pix_off;
+    int32_t *stN = stN_all + fd.pix_off;
+    int32_t *census = census_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x;
+    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + strip * SR, wr1 = wr0 + SR - 1;
+    float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
+    int last = 0, n_eval = 0, n_con = 0;
+    bool done = !inside;
+    RasterRec nxt;
+    if (rg.x + lane < rg.y) nxt = rec[pval[rg.x + lane]];
+    for (int c = rg.x; c < rg.y; c += 64) {
+        uint64_t live = __ballot(!done);
+        if (live == 0) break;
+        const RasterRec r = nxt;   // list entry c + lane
+        const bool inchunk = c + lane < rg.y;
+        if (c + 64 + lane < rg.y) nxt = rec[pval[c + 64 + lane]];
+        bool meets = false;
+        if (inchunk) {
+            const uint32_t rows = r.rows;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        int q = 0;
+        if (__popcll(live) > kStragglers) {
+            if (meets) { sbuf[rank] = r; sidx[rank] = (uint8_t)lane; }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (; q < nact; q += 2) {
+                live = __ballot(!done);
+                if (live == 0 || __popcll(live) <= kStragglers) break;
+                const bool has1 = q + 1 < nact;
+                const int k0 = q, k1 = has1 ? q + 1 : q;
+                PairEval e0, e1;
+                const bool ok0 = eval_pair_flat(sbuf[k0], vx, vy, vz, near_m, e0);
+                const bool ok1 = eval_pair_flat(sbuf[k1], vx, vy, vz, near_m, e1) && has1;
+                if (!done) {
+                    ++n_eval;
+                    if (ok0) {
+                        const float tT = T * (1.0f - e0.alpha);
+                        if (tT < kTMin) {
+                            done = true;
+                        } else {
+                            const float w = e0.alpha * T;
+                            D = fmaf(w, e0.t, D);
+                            N0 = fmaf(w, sbuf[k0].n[0], N0);
+                            N1 = fmaf(w, sbuf[k0].n[1], N1);
+                            N2 = fmaf(w, sbuf[k0].n[2], N2);
+                            O += w;
+                            T = tT;
+                            last = c + sidx[k0] + 1 - rg.x;
+                            ++n_con;
+                        }
+                    }
+                }
+                if (has1 && !done) {
+                    ++n_eval;
+                    if (ok1) {
+                        const float tT = T * (1.0f - e1.alpha);
+                        if (tT < kTMin) {
+                            done = true;
+                        } else {
+                            const float w = e1.alpha * T;
+                            D = fmaf(w, e1.t, D);
+                            N0 = fmaf(w, sbuf[k1].n[0], N0);
+                            N1 = fmaf(w, sbuf[k1].n[1], N1);
+                            N2 = fmaf(w, sbuf[k1].n[2], N2);
+                            O += w;
+                            T = tT;
+                            last = c + sidx[k1] + 1 - rg.x;
+                            ++n_con;
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // sbuf is rewritten by the next chunk
+        }
+        if (q >= nact) continue;
+        // few unfinished pixels: the chunk's remaining entries (compacted rank >= q)
+        // are evaluated by their own lanes for one pixel at a time
+        const bool rem = meets && rank >= q;
+        live = __ballot(!done);
+        while (live) {
+            const int pl = (int)__builtin_ctzll(live);
+            live &= live - 1;
+            const double pvx = bcast(vx, pl), pvy = bcast(vy, pl), pvz = bcast(vz, pl);
+            float sT = bcast(T, pl), sD = bcast(D, pl), sN0 = bcast(N0, pl), sN1 = bcast(N1, pl),
+                  sN2 = bcast(N2, pl), sO = bcast(O, pl);
+            int sLast = bcast(last, pl), sCon = 0;
+            PairEval ev;
+            const bool ok = eval_pair_flat(r, pvx, pvy, pvz, near_m, ev) && rem;
+            uint64_t cm = __ballot(ok);
+            int counted = nact - q;
+            bool sDone = false;
+            while (cm) {
+                const int jl = (int)__builtin_ctzll(cm);
+                cm &= cm - 1;
+                const float a = bcast(ev.alpha, jl), tj = bcast(ev.t, jl);
+                const float tT = sT * (1.0f - a);
+                if (tT < kTMin) {
+                    sDone = true;
+                    // entries evaluated: those of rank q .. rank(jl)
+                    counted = bcast(rank, jl) - q + 1;
+                    break;
+                }
+                const float w = a * sT;
+                sD = fmaf(w, tj, sD);
+                sN0 = fmaf(w, bcast(r.n[0], jl), sN0);
+                sN1 = fmaf(w, bcast(r.n[1], jl), sN1);
+                sN2 = fmaf(w, bcast(r.n[2], jl), sN2);
+                sO += w;
+                sT = tT;
+                sLast = c + jl + 1 - rg.x;
+                ++sCon;
+            }
+            if (lane == pl) {
+                T = sT; D = sD; N0 = sN0; N1 = sN1; N2 = sN2; O = sO;
+                last = sLast; n_eval += counted; n_con += sCon; done = sDone;
+            }
+        }
+    }
+    if (inside) {
+        const int p = i * W + j;
+        census[p] = n_eval;
+        census[total_pixels + p] = n_con;
+        depth[p] = D;
+        alpha[p] = O;
+        normal[3 * p] = N0; normal[3 * p + 1] = N1; normal[3 * p + 2] = N2;
+        stT[p] = T;
+        stN[p] = last;
+    }
+}
+
 // Forward, scalar-cache variant: every wave walks the tile's list on its own.
 // The record index and the record itself are wave-uniform, so they are read
 // with scalar loads into SGPRs and feed the VALU as scalar operands; no LDS,
@@ -666,8 +837,9 @@ template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>, dim3((unsigned)L.tiles),
-                       dim3(256), 0, stream,
+    const bool wave = L.variant == SLR_VARIANT_WAVE;
+    hipLaunchKernelGGL(wave ? k_raster_fwd_w<TW> : L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>,
+                       dim3((unsigned)(wave ? 4 * L.tiles : L.tiles)), dim3(wave ? 64 : 256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),

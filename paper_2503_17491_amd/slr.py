@@ -29,7 +29,7 @@ class Tiling(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32)]
 
 
-VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR = 0, 1, 2
+VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
 SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST = 0, 1, 2
 
 

@@ -149,7 +149,7 @@ def test_forward_identical_across_tilings_and_runs(slr):
     # (h, w, 2): the forward that reads records through the scalar cache;
     # (h, w, v, 2): tiles taken longest list first
     for tiling in [(16, 16), (8, 32), (32, 8), (4, 64), (16, 16), (16, 16, 2), (8, 32, 2), (4, 64, 2),
-                   (16, 16, 1, 2), (32, 8, 2, 2)]:
+                   (16, 16, 1, 2), (32, 8, 2, 2), (16, 16, 3), (32, 8, 3), (4, 64, 3, 1)]:
         _, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling)
         outs.append((D, N, A))
     for o in outs[1:]:
@@ -165,7 +165,7 @@ def test_forward_state_identical_across_variants(slr):
     sensor = slr.make_sensor(64, 512)
     for sc in (synth.shell_scene(4000, 2), synth.structured_scene(30000, 3)[0]):
         views = []
-        for tiling in [(16, 16, 1), (16, 16, 2)]:
+        for tiling in [(16, 16, 1), (16, 16, 2), (16, 16, 3), (8, 32, 3)]:
             r, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling, 1 << 20)
             v = r.views()
             views.append((D, N, A, v["T_final"].cpu().numpy(), v["n_proc"].cpu().numpy(),
