@@ -597,6 +597,121 @@ __device__ __forceinline__ void dcross(const double *a, const double *b, double 
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Upstream gradients and final transmittance of one pixel.
+struct BwdUpstream {
+    float gd, go, gn0, gn1, gn2, Tfin;
+};
+
+// Reverse-order state of one pixel: T is the transmittance behind the next
+// pair to visit (A_k once it is divided by 1 - alpha_k); Bs the suffix sum of
+// c_i alpha_i A_i over the pairs already visited; the reference values are
+// those of the pixel's last contributor (the first pair met in reverse).
+struct BwdState {
+    float T, Bs, Kref, tref, nr0, nr1, nr2;
+    bool have_ref;
+};
+
+// One contributing pair of a pixel, met in reverse list order (Supp. D):
+// advances the state and writes the pair's 18 partials.
+//   dL/dalpha_k = c_k A_k + (K T_final - B_k) / (1 - alpha_k), with
+//   c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
+//   and K = gD t_ref + gN . n_ref + gO: the reference removes the cancellation of
+//   the unshifted form.  The partials are centred on the surfel centre's
+//   direction ch: da (v - ch), db (v - ch), dc_s v, da, db, (dL/dt / c)(s_a, s_b, 1),
+//   dL/do, dL/dn.
+__device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
+                                         const double *ch, const BwdUpstream &u, double vx, double vy, double vz,
+                                         float (&g)[18])
+{
+    const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+    const float A = st.T * r1;  // transmittance in front of this pair
+    if (!st.have_ref) {
+        st.have_ref = true;
+        st.tref = e.t; st.nr0 = n0; st.nr1 = n1; st.nr2 = n2;
+        st.Kref = u.gd * st.tref + u.gn0 * st.nr0 + u.gn1 * st.nr1 + u.gn2 * st.nr2 + u.go;
+    }
+    const float ck = u.gd * (e.t - st.tref) + u.gn0 * (n0 - st.nr0) + u.gn1 * (n1 - st.nr1) + u.gn2 * (n2 - st.nr2);
+    const float dA = ck * A + (st.Kref * u.Tfin - st.Bs) * r1;
+    const float w = e.alpha * A;
+    st.Bs = fmaf(ck, w, st.Bs);
+    st.T = A;
+    const float gt = u.gd * w;  // dL/d(range)
+    float dsa = 0.0f, dsb = 0.0f, dop = 0.0f;
+    if (!e.clamped) {
+        const float f = -dA * e.alpha;
+        dsa = f * e.sa; dsb = f * e.sb;
+        dop = dA * e.G;
+    }
+    const float da = dsa * e.rc, db = dsb * e.rc;
+    const float dcs = -(dsa * e.sa + dsb * e.sb) * e.rc;
+    const float tt = gt * e.rc;
+    const float ex = (float)(vx - ch[0]), ey = (float)(vy - ch[1]), ez = (float)(vz - ch[2]);
+    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    g[0] = da * ex; g[1] = da * ey; g[2] = da * ez;
+    g[3] = db * ex; g[4] = db * ey; g[5] = db * ez;
+    g[6] = dcs * fvx; g[7] = dcs * fvy; g[8] = dcs * fvz;
+    g[9] = da; g[10] = db;
+    g[11] = tt * e.sa; g[12] = tt * e.sb; g[13] = tt;
+    g[14] = dop;
+    g[15] = u.gn0 * w; g[16] = u.gn1 * w; g[17] = u.gn2 * w;
+}
+
+// A record's pixel sums of the 18 partials -> dL/d(b_alpha, b_beta, b_c, n) in
+// FP64 (dPv = E_a + A_a ch, dQv = E_b + A_b ch; g_alpha = E_b x b_c + b_beta x C_s
+// + T_a M, g_beta = b_c x E_a + C_s x b_alpha + T_b M, g_c = dPv x b_beta +
+// b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (acc not
+// NULL) the world-frame gradients added to the record's accumulator.
+__device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRec &fr, const double *M,
+                                             const double *ch, const double *pose, float *acc, double (&pacc)[6])
+{
+    const double Ea[3] = {s[0], s[1], s[2]}, Eb[3] = {s[3], s[4], s[5]}, Cs[3] = {s[6], s[7], s[8]};
+    const double Aa = s[9], Ab = s[10], Ta = s[11], Tb = s[12], Tc = s[13];
+    double dPv[3], dQv[3];  // sum da v, sum db v
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { dPv[c] = Ea[c] + Aa * ch[c]; dQv[c] = Eb[c] + Ab * ch[c]; }
+    double t1[3], t2[3];
+    double ga[3], gb[3], gc[3];
+    dcross(Eb, fr.bc, t1); dcross(fr.bb, Cs, t2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ga[c] = t1[c] + t2[c] + Ta * M[c];
+    dcross(fr.bc, Ea, t1); dcross(Cs, fr.ba, t2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gb[c] = t1[c] + t2[c] + Tb * M[c];
+    dcross(dPv, fr.bb, t1); dcross(fr.ba, dQv, t2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gc[c] = t1[c] + t2[c] + Tc * M[c];
+    const double gn[3] = {s[15], s[16], s[17]};
+    const double nn[3] = {fr.n[0], fr.n[1], fr.n[2]};
+    // pose: d b / d rho = -I, d b / d phi = [b]_x
+    double c1[3], c2[3], c3[3], c4[3];
+    dcross(gc, fr.bc, c1); dcross(ga, fr.ba, c2); dcross(gb, fr.bb, c3); dcross(gn, nn, c4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        pacc[c] -= gc[c];
+        pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
+    }
+    if (acc) {
+        double R[9];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
+            const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
+            const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
+            const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
+            atomicAdd(acc + c, (float)wa);
+            atomicAdd(acc + 3 + c, (float)wb);
+            atomicAdd(acc + 6 + c, (float)wc);
+            atomicAdd(acc + 9 + c, (float)wn);
+        }
+        atomicAdd(acc + 12, s[14]);
+    }
+}
+
+
 template <int TW>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
@@ -635,7 +750,6 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
-    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
     const int2 rg = ranges[tile];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int red_val = bitrev6(lane);  // the wave sum this lane holds after wave_sum18
@@ -665,8 +779,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     // c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
     // and K = gD t_ref + gN . n_ref + gO: the reference (the last contributor, met
     // first in reverse) removes the cancellation of the unshifted form.
-    float Bs = 0.0f, Kref = 0.0f, tref = 0.0f, nr0 = 0.0f, nr1 = 0.0f, nr2 = 0.0f;
-    bool have_ref = false;
+    BwdState st = {T, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    const BwdUpstream up = {gd, go, gn0, gn1, gn2, Tfin};
     int n_eval = 0, n_con = 0;
 
     for (int b_end = end; b_end > rg.x; b_end -= kBwdBatch) {
@@ -706,38 +820,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
             if (act) {
                 ++n_con;
-                const float n0 = srec[k].n[0], n1 = srec[k].n[1], n2 = srec[k].n[2];
-                const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-                const float A = T * r1;  // transmittance in front of this pair
-                if (!have_ref) {
-                    have_ref = true;
-                    tref = e.t; nr0 = n0; nr1 = n1; nr2 = n2;
-                    Kref = gd * tref + gn0 * nr0 + gn1 * nr1 + gn2 * nr2 + go;
-                }
-                const float ck = gd * (e.t - tref) + gn0 * (n0 - nr0) + gn1 * (n1 - nr1) + gn2 * (n2 - nr2);
-                const float dA = ck * A + (Kref * Tfin - Bs) * r1;
-                const float w = e.alpha * A;
-                Bs = fmaf(ck, w, Bs);
-                T = A;
-                const float gt = gd * w;  // dL/d(range)
-                float dsa = 0.0f, dsb = 0.0f, dop = 0.0f;
-                if (!e.clamped) {
-                    const float f = -dA * e.alpha;
-                    dsa = f * e.sa; dsb = f * e.sb;
-                    dop = dA * e.G;
-                }
-                const float da = dsa * e.rc, db = dsb * e.rc;
-                const float dcs = -(dsa * e.sa + dsb * e.sb) * e.rc;
-                const float tt = gt * e.rc;
-                const float ex = (float)(vx - schat[k].c[0]), ey = (float)(vy - schat[k].c[1]),
-                            ez = (float)(vz - schat[k].c[2]);
-                g[0] = da * ex; g[1] = da * ey; g[2] = da * ez;
-                g[3] = db * ex; g[4] = db * ey; g[5] = db * ez;
-                g[6] = dcs * fvx; g[7] = dcs * fvy; g[8] = dcs * fvz;
-                g[9] = da; g[10] = db;
-                g[11] = tt * e.sa; g[12] = tt * e.sb; g[13] = tt;
-                g[14] = dop;
-                g[15] = gn0 * w; g[16] = gn1 * w; g[17] = gn2 * w;
+                bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k].c, up, vx, vy, vz, g);
             }
             if (__any(act)) {
                 static_assert(kNg == 18, "wave_sum18 reduces 18 values");
@@ -756,55 +839,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
                 sflag[k] = 0;
                 const uint32_t id = pval[b0 + k];
-                const FrameRec fr = frame[id];
-                const RasterRec &rr = srec[k];
-                const double *ch = schat[k].c;
-                const double Ea[3] = {s[0], s[1], s[2]}, Eb[3] = {s[3], s[4], s[5]}, Cs[3] = {s[6], s[7], s[8]};
-                const double Aa = s[9], Ab = s[10], Ta = s[11], Tb = s[12], Tc = s[13];
-                double dPv[3], dQv[3];  // sum da v, sum db v
-#pragma unroll
-                for (int c = 0; c < 3; ++c) { dPv[c] = Ea[c] + Aa * ch[c]; dQv[c] = Eb[c] + Ab * ch[c]; }
-                double t1[3], t2[3];
-                double ga[3], gb[3], gc[3];
-                dcross(Eb, fr.bc, t1); dcross(fr.bb, Cs, t2);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) ga[c] = t1[c] + t2[c] + Ta * rr.M[c];
-                dcross(fr.bc, Ea, t1); dcross(Cs, fr.ba, t2);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gb[c] = t1[c] + t2[c] + Tb * rr.M[c];
-                dcross(dPv, fr.bb, t1); dcross(fr.ba, dQv, t2);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gc[c] = t1[c] + t2[c] + Tc * rr.M[c];
-                const double gn[3] = {s[15], s[16], s[17]};
-                const double nn[3] = {fr.n[0], fr.n[1], fr.n[2]};
-                // pose: d b / d rho = -I, d b / d phi = [b]_x
-                double c1[3], c2[3], c3[3], c4[3];
-                dcross(gc, fr.bc, c1); dcross(ga, fr.ba, c2); dcross(gb, fr.bb, c3); dcross(gn, nn, c4);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    pacc[c] -= gc[c];
-                    pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
-                }
-                if (!pose_only) {
-                    double R[9];
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-                        R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
-                    }
-                    float *a = acc + (size_t)(id - fd.item_off) * kAccStride;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
-                        const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
-                        const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
-                        const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
-                        atomicAdd(a + c, (float)wa);
-                        atomicAdd(a + 3 + c, (float)wb);
-                        atomicAdd(a + 6 + c, (float)wc);
-                        atomicAdd(a + 9 + c, (float)wn);
-                    }
-                    atomicAdd(a + 12, s[14]);
-                }
+                flush_record(s, frame[id], srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
             }
         }
     }
@@ -833,6 +868,211 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
 }
 
+// Backward, one wave per 64-pixel strip (the counterpart of k_raster_fwd_w).
+// The strip's list is walked in reverse, 64 records per chunk (one per lane,
+// the previous chunk's loads in flight), from its last contributor down.
+// Many active pixels: every lane runs its pixel's reverse update against the
+// compacted records and each record's 18 partials are summed over the wave;
+// few active pixels (those whose last contributor lies further along the
+// list): each of them in turn takes the wave, the lanes evaluate their own
+// records for it and the contributing ones are visited in reverse order.  At
+// the end of a chunk every lane flushes its own record's sums.
+template <int TW>
+__global__ void __launch_bounds__(64)
+k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+               const uint32_t *__restrict__ order,
+               const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame,
+               const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+               const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+               const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
+               int pose_only)
+{
+    constexpr int TH = 256 / TW, SR = 64 / TW;
+    __shared__ RasterRec sbuf[64];
+    __shared__ ChatRec schat[64];
+    __shared__ float sred[kNg][64];
+    __shared__ uint8_t slist[64];
+    const int strip = (int)(blockIdx.x & 3u);
+    const int tslot = (int)(blockIdx.x >> 2);
+    const int tile = order ? (int)order[tslot] : tslot;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    int32_t *census = census_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x;
+    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + strip * SR, wr1 = wr0 + SR - 1;
+    const int red_val = bitrev6(lane);
+    const int p = inside ? i * W + j : 0;
+    const int last = inside ? stN[p] : 0;
+    const float T0 = inside ? stT[p] : 1.0f;
+    BwdUpstream up;
+    up.gd = (inside && fd.gD) ? fd.gD[p] : 0.0f;
+    up.go = (inside && fd.gO) ? fd.gO[p] : 0.0f;
+    up.gn0 = (inside && fd.gN) ? fd.gN[3 * p] : 0.0f;
+    up.gn1 = (inside && fd.gN) ? fd.gN[3 * p + 1] : 0.0f;
+    up.gn2 = (inside && fd.gN) ? fd.gN[3 * p + 2] : 0.0f;
+    up.Tfin = T0;
+    BwdState st = {T0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    int wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+    for (int v = 0; v < kNg; ++v) sred[v][lane] = 0.0f;
+    double pacc[6] = {0, 0, 0, 0, 0, 0};
+    int n_eval = 0, n_con = 0;
+    float *acc_base = pose_only ? nullptr : fd.acc;
+    const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
+    int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64;
+    // a record travels as six 16-byte words (the last one ends with the rows
+    // word) and the centre direction as three doubles
+    static_assert(sizeof(RasterRec) == 96 && offsetof(RasterRec, rows) == 92, "record layout");
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 nrec[6];
+    double nch[3];
+    uint32_t nid = 0;
+    if (c >= rg.x && c + lane < end) {
+        nid = pval[c + lane];
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) nrec[f] = src[f];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
+    }
+    for (; c >= rg.x; c -= 64) {
+        const bool inr = c + lane < end;
+        const uint32_t id = nid;
+        bool meets = false;
+        if (inr) {
+            const uint32_t rows = nrec[5].w;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[lane]);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) dst[f] = nrec[f];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) schat[lane].c[f] = nch[f];
+        }
+        if (c - 64 >= rg.x) {   // the previous chunk's records, read while this one is processed
+            nid = pval[c - 64 + lane];
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) nrec[f] = src[f];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (meets) slist[rank] = (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t fmask = 0;   // records of this chunk with partials in sred
+        uint64_t live = __ballot(last > c - rg.x);
+        if (__popcll(live) > kStragglers) {
+            for (int q = nact - 1; q >= 0; --q) {
+                const int k = slist[q];
+                const int pos = c + k - rg.x;
+                float g[kNg];
+#pragma unroll
+                for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                PairEval e;
+                n_eval += pos < last ? 1 : 0;
+                const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
+                if (act) {
+                    ++n_con;
+                    bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k].c, up, vx, vy, vz, g);
+                }
+                if (__any(act)) {
+                    static_assert(kNg == 18, "wave_sum18 reduces 18 values");
+                    const float tot = wave_sum18(g, lane);
+                    if (red_val < kNg) sred[red_val][k] = tot;
+                    fmask |= 1ull << k;
+                }
+            }
+        } else {
+            const int pos_l = c + lane - rg.x;
+            while (live) {
+                const int pl = (int)__builtin_ctzll(live);
+                live &= live - 1;
+                const double pvx = bcast(vx, pl), pvy = bcast(vy, pl), pvz = bcast(vz, pl);
+                const int plast = bcast(last, pl);
+                BwdUpstream pu;
+                pu.gd = bcast(up.gd, pl); pu.go = bcast(up.go, pl); pu.gn0 = bcast(up.gn0, pl);
+                pu.gn1 = bcast(up.gn1, pl); pu.gn2 = bcast(up.gn2, pl); pu.Tfin = bcast(up.Tfin, pl);
+                BwdState ps;
+                ps.T = bcast(st.T, pl); ps.Bs = bcast(st.Bs, pl); ps.Kref = bcast(st.Kref, pl);
+                ps.tref = bcast(st.tref, pl); ps.nr0 = bcast(st.nr0, pl); ps.nr1 = bcast(st.nr1, pl);
+                ps.nr2 = bcast(st.nr2, pl); ps.have_ref = bcast(st.have_ref ? 1 : 0, pl) != 0;
+                const bool cand = meets && pos_l < plast;
+                PairEval ev;
+                const bool ok = eval_pair_flat(sbuf[lane], pvx, pvy, pvz, near_m, ev) && cand;
+                const int pe = __popcll(__ballot(cand));
+                uint64_t cm = __ballot(ok);
+                const int pc = __popcll(cm);
+                while (cm) {
+                    const int jl = 63 - (int)__builtin_clzll(cm);   // reverse list order
+                    cm &= ~(1ull << jl);
+                    PairEval ej;
+                    ej.sa = bcast(ev.sa, jl); ej.sb = bcast(ev.sb, jl); ej.t = bcast(ev.t, jl);
+                    ej.rc = bcast(ev.rc, jl); ej.G = bcast(ev.G, jl); ej.alpha = bcast(ev.alpha, jl);
+                    ej.clamped = bcast(ev.clamped ? 1 : 0, jl) != 0;
+                    float g[kNg];
+                    bwd_pair(ps, ej, sbuf[jl].n[0], sbuf[jl].n[1], sbuf[jl].n[2], schat[jl].c, pu, pvx, pvy, pvz, g);
+                    if (lane == jl) {
+#pragma unroll
+                        for (int v = 0; v < kNg; ++v) sred[v][jl] += g[v];
+                    }
+                    fmask |= 1ull << jl;
+                }
+                if (lane == pl) {
+                    st = ps;
+                    n_eval += pe;
+                    n_con += pc;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((fmask >> lane) & 1ull) {
+            float s[kNg];
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
+            flush_record(s, frame[id], sbuf[lane].M, schat[lane].c, fd.pose,
+                         acc_base ? acc_base + (size_t)(id - fd.item_off) * kAccStride : nullptr, pacc);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (inside) {
+        census[2 * total_pixels + p] = n_eval;
+        census[3 * total_pixels + p] = n_con;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double v = pacc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        pacc[k] = v;
+    }
+    if (lane < 6) {
+        double v = pacc[0];
+#pragma unroll
+        for (int k = 1; k < 6; ++k) v = lane == k ? pacc[k] : v;
+        if (v != 0.0) atomicAdd(fd.d_pose + lane, v);
+    }
+}
+
 template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
@@ -851,7 +1091,9 @@ template <int TW>
 void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+    const bool wave = L.variant == SLR_VARIANT_WAVE;
+    hipLaunchKernelGGL(wave ? k_raster_bwd_w<TW> : k_raster_bwd<TW>, dim3((unsigned)(wave ? 4 * L.tiles : L.tiles)),
+                       dim3(wave ? 64 : 256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),

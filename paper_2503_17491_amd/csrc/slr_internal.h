@@ -80,7 +80,7 @@ constexpr int kSortTile = kSortThreads * kSortItems; // items per block
 constexpr int kMaxDigitBits = 8;
 
 // Compositing variant and tile schedule used when the caller asks for the default.
-constexpr int kDefaultVariant = SLR_VARIANT_LDS;
+constexpr int kDefaultVariant = SLR_VARIANT_WAVE;
 constexpr int kDefaultSchedule = SLR_SCHEDULE_LONGEST;
 
 // Angular margin (radians) by which the bounding box is widened on every side.

@@ -176,6 +176,21 @@ def test_forward_state_identical_across_variants(slr):
                     np.testing.assert_array_equal(a, b)
 
 
+def test_forward_parity_fullsize_sampled(slr):
+    """200k surfels on the structured scene at 128x1024 (the fwd+bwd workload)."""
+    say("forward structured-200k-128x1024 sampled")
+    sc, _ = synth.structured_scene(200000, 2)
+    sensor = slr.make_sensor(128, 1024)
+    r, d, Td, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, (16, 16), 1 << 20)
+    g = np.random.default_rng(0)
+    pix = np.stack([g.integers(0, 128, 600), g.integers(0, 1024, 600)], 1).astype(np.int32)
+    # plus every pixel of one tile at the horizon and one at the seam
+    ii, jj = np.meshgrid(np.arange(48, 64), np.arange(0, 16), indexing="ij")
+    pix = np.concatenate([pix, np.stack([ii.ravel(), jj.ravel()], 1).astype(np.int32)])
+    ref = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), sensor, pix)
+    assert_forward_close(D, N, A, ref, pix)
+
+
 # ---------------------------------------------------------------- backward
 def block_err(g, ref, absum):
     """max over surfels of |g - ref| / max(|ref|, 1e-3 RMS, 1e-2 |absum|) per parameter block;
