@@ -237,12 +237,14 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
 __global__ void __launch_bounds__(256)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
        const int32_t *__restrict__ counts, const PixBox *__restrict__ box, int64_t n, const uint64_t *__restrict__ keff,
-       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
+       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval, uint32_t *__restrict__ rid,
+       uint32_t *__restrict__ estart)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || *keff == 0) return;
     uint32_t id = order[r];
     if (counts[id] == 0) return;
+    estart[id] = offsets[r];
     PixBox b = box[id];
     const FrameDesc &fd = descs[b.frame];
     const int th = fd.th, tw = fd.tw, tiles_x = fd.tiles_x, toff = fd.tile_off;
@@ -255,9 +257,23 @@ k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, 
         if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
     }
     for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
-        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
+        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = o; rid[o] = id; ++o; }
+        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = o; rid[o] = id; ++o; }
     }
+}
+
+// The tile sort carries each pair's emission position E; turn the sorted
+// values into record ids and record where every emitted pair went.
+__global__ void __launch_bounds__(256)
+k_finalize_pairs(uint32_t *__restrict__ sval, const uint32_t *__restrict__ rid, uint32_t *__restrict__ inv,
+                 const uint64_t *__restrict__ keff)
+{
+    const int64_t K = (int64_t)*keff;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= K) return;
+    const uint32_t e = sval[p];
+    sval[p] = rid[e];
+    inv[e] = (uint32_t)p;
 }
 
 __global__ void __launch_bounds__(256)
@@ -394,7 +410,8 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
-                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0);
+                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0,
+                       reinterpret_cast<uint32_t *>(ws + L.rid), reinterpret_cast<uint32_t *>(ws + L.estart));
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)
@@ -407,6 +424,9 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
         done += bits;
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;
+    hipLaunchKernelGGL(k_finalize_pairs, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream,
+                       L.tile_in_1 ? v1 : v0, reinterpret_cast<const uint32_t *>(ws + L.rid),
+                       reinterpret_cast<uint32_t *>(ws + L.inv), keff);
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream, ts, keff, ranges);
     launch_tile_order(L, ws, stream);
 }

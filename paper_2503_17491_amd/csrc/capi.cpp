@@ -296,22 +296,24 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
                       bool pose_only, bool accumulate, hipStream_t s)
 {
     const Layout &L = B.L;
-    // pose gradients are accumulated by FP64 atomics: start from zero
-    slr::launch_fill_u32(ws + L.scratch_pose, 0u, 12 * (int64_t)L.frames, s);
-    if (!pose_only) slr::launch_fill_u32(ws + L.acc, 0u, L.acc_floats, s);
+    // slot flags of the pairs this render produced start cleared
+    if (!pose_only) slr::launch_fill_pairs(L, ws, L.pflag, 1, s);
     {
         StageScope t(5, s);
         slr::launch_raster_bwd(L, ws, pose_only, s);
     }
+    slr::launch_pose_reduce(L, ws, s);
     if (pose_only) return;
     StageScope t(6, s);
     int64_t off = 0;
     for (int32_t k = 0; k < L.sets; ++k) {
         const slr_surfel_grads &g = grads[k];
-        if (g.means)
+        if (g.means) {
+            slr::launch_surfel_reduce(L, ws, k, sets[k].n, off, s);
             slr::launch_surfel_grad(sets[k].quats, sets[k].log_scales, sets[k].logits, sets[k].n,
                                     reinterpret_cast<const float *>(ws + L.acc) + off, g.means, g.quats, g.log_scales,
                                     g.logits, accumulate, s);
+        }
         off += sets[k].n * slr::kAccStride;
     }
 }
@@ -333,13 +335,6 @@ slr_status check_grads(int32_t n_sets, const slr_surfel_grads *grads, bool pose_
         if (nset == 4 && !aligned(g.quats, 16)) return fail(SLR_E_INVALID, "set %d: d_quats must be 16-byte aligned", k);
     }
     return SLR_OK;
-}
-
-// Zero the user pose gradients of every frame that has one.
-void zero_user_pose(int32_t n_frames, const slr_frame *frames, hipStream_t s)
-{
-    for (int32_t f = 0; f < n_frames; ++f)
-        if (frames[f].d_pose) slr::launch_fill_u32(frames[f].d_pose, 0u, 12, s);
 }
 
 }  // namespace
@@ -381,6 +376,12 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
+    L.rid = take(4 * cc);
+    L.inv = take(4 * cc);
+    L.estart = take(4 * nn);
+    L.pflag = take(4 * cc);
+    L.slot = take(sizeof(float) * kSlotFloats * kSlotStrips * (size_t)cc);
+    L.pose_part = take(sizeof(double) * 8 * kSlotStrips * (size_t)(L.tiles > 0 ? L.tiles : 1));
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));
@@ -513,7 +514,6 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
     // rewrite the descriptor with the backward's pointers (outputs are not read)
     std::vector<FrameDesc> d = make_descs(B, surfels, &fr, tiling, ws);
     slr::launch_write_desc(d.data(), 1, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
-    zero_user_pose(1, &fr, s);
     slr_surfel_grads g{d_means, d_quats, d_log_scales, d_logits};
     enqueue_backward(B, surfels, &g, ws, pose_only, accumulate, s);
     HIP_TRY(hipGetLastError());
@@ -583,7 +583,6 @@ slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr
     if ((st = check_grads(n_sets, grads, pose_only)) != SLR_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *ws = reinterpret_cast<char *>(workspace);
-    zero_user_pose(n_frames, frames, s);
     enqueue_backward(B, sets, grads, ws, pose_only, (flags & SLR_ACCUMULATE) != 0, s);
     HIP_TRY(hipGetLastError());
     return SLR_OK;

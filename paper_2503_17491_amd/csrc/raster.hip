@@ -659,10 +659,12 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
 // A record's pixel sums of the 18 partials -> dL/d(b_alpha, b_beta, b_c, n) in
 // FP64 (dPv = E_a + A_a ch, dQv = E_b + A_b ch; g_alpha = E_b x b_c + b_beta x C_s
 // + T_a M, g_beta = b_c x E_a + C_s x b_alpha + T_b M, g_c = dPv x b_beta +
-// b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (acc not
-// NULL) the world-frame gradients added to the record's accumulator.
+// b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (slot not
+// NULL) the 13 world-frame gradients written to the slot (64 bytes) with its
+// flag byte set.
 __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRec &fr, const double *M,
-                                             const double *ch, const double *pose, float *acc, double (&pacc)[6])
+                                             const double *ch, const double *pose, float *slot, uint8_t *flag,
+                                             double (&pacc)[6])
 {
     const double Ea[3] = {s[0], s[1], s[2]}, Eb[3] = {s[3], s[4], s[5]}, Cs[3] = {s[6], s[7], s[8]};
     const double Aa = s[9], Ab = s[10], Ta = s[11], Tb = s[12], Tc = s[13];
@@ -690,24 +692,26 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
         pacc[c] -= gc[c];
         pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
     }
-    if (acc) {
+    if (slot) {
         double R[9];
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
         }
+        float w[16];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
-            const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
-            const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
-            const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
-            atomicAdd(acc + c, (float)wa);
-            atomicAdd(acc + 3 + c, (float)wb);
-            atomicAdd(acc + 6 + c, (float)wc);
-            atomicAdd(acc + 9 + c, (float)wn);
+            w[c] = (float)(R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2]);
+            w[3 + c] = (float)(R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2]);
+            w[6 + c] = (float)(R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2]);
+            w[9 + c] = (float)(R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2]);
         }
-        atomicAdd(acc + 12, s[14]);
+        w[12] = s[14];
+        w[13] = w[14] = w[15] = 0.0f;
+        float4 *d = reinterpret_cast<float4 *>(slot);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+        *flag = 1;
     }
 }
 
@@ -720,6 +724,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
+             float *__restrict__ slots, uint8_t *__restrict__ pflag, double *__restrict__ pose_part,
              int pose_only)
 {
     constexpr int TH = 256 / TW;
@@ -741,8 +746,6 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     int32_t *census = census_all + fd.pix_off;
     const float *gD = fd.gD, *gN = fd.gN, *gO = fd.gO;
     const double *pose = fd.pose;
-    float *acc = fd.acc;
-    double *d_pose = fd.d_pose;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
@@ -839,7 +842,9 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
                 sflag[k] = 0;
                 const uint32_t id = pval[b0 + k];
-                flush_record(s, frame[id], srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
+                const size_t slot = (size_t)(b0 + k) * kSlotStrips;   // this workgroup holds the whole tile
+                flush_record(s, frame[id], srec[k].M, schat[k].c, pose,
+                             pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
             }
         }
     }
@@ -862,9 +867,11 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-        const double v = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] +
-                         s_pose[3][threadIdx.x];
-        if (v != 0.0) atomicAdd(d_pose + threadIdx.x, v);
+        pose_part[8 * (size_t)blockIdx.x + threadIdx.x] =
+            s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
+    }
+    if (threadIdx.x == 6) {
+        pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
     }
 }
 
@@ -885,6 +892,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
+               float *__restrict__ slots, uint8_t *__restrict__ pflag, double *__restrict__ pose_part,
                int pose_only)
 {
     constexpr int TH = 256 / TW, SR = 64 / TW;
@@ -929,7 +937,6 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     for (int v = 0; v < kNg; ++v) sred[v][lane] = 0.0f;
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     int n_eval = 0, n_con = 0;
-    float *acc_base = pose_only ? nullptr : fd.acc;
     const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
     int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64;
     // a record travels as six 16-byte words (the last one ends with the rows
@@ -1047,8 +1054,9 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             float s[kNg];
 #pragma unroll
             for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
+            const size_t slot = (size_t)(c + lane) * kSlotStrips + strip;
             flush_record(s, frame[id], sbuf[lane].M, schat[lane].c, fd.pose,
-                         acc_base ? acc_base + (size_t)(id - fd.item_off) * kAccStride : nullptr, pacc);
+                         pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1069,8 +1077,9 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
         double v = pacc[0];
 #pragma unroll
         for (int k = 1; k < 6; ++k) v = lane == k ? pacc[k] : v;
-        if (v != 0.0) atomicAdd(fd.d_pose + lane, v);
+        pose_part[8 * (size_t)blockIdx.x + lane] = v;
     }
+    if (lane == 6) pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
 }
 
 template <int TW>
@@ -1100,7 +1109,9 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
-                       reinterpret_cast<int32_t *>(ws + L.census), L.pixels, pose_only ? 1 : 0);
+                       reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<float *>(ws + L.slot),
+                       reinterpret_cast<uint8_t *>(ws + L.pflag), reinterpret_cast<double *>(ws + L.pose_part),
+                       pose_only ? 1 : 0);
 }
 
 }  // namespace

@@ -1,6 +1,9 @@
-// surfel_grad.hip -- per-surfel parameter gradients (Supp. D, last block).
+// surfel_grad.hip -- per-surfel parameter gradients (Supp. D, last block), and
+// the gathers that turn the compositing backward's per-(pair, strip) slots and
+// per-workgroup pose partials into per-surfel sums and per-keyframe pose
+// gradients in a fixed order.
 //
-// The compositing backward leaves, per surfel, the world-frame gradients
+// The gather leaves, per surfel, the world-frame gradients
 //   w_a = dL/d(s_a t_a), w_b = dL/d(s_b t_b), w_c = dL/dmu, w_n = dL/dt_n,
 //   g_o = dL/do
 // summed over pixels (and over keyframes that share the surfel).  This kernel
@@ -10,6 +13,87 @@
 
 namespace slr {
 namespace {
+
+// Per surfel of one set: for every keyframe that renders the set, the surfel's
+// record emitted its pairs at positions [estart, estart + count); each pair's
+// written slots (flag byte set) are added in the order keyframe, pair, strip.
+__global__ void __launch_bounds__(256)
+k_surfel_reduce(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
+                const int32_t *__restrict__ counts, const uint32_t *__restrict__ estart,
+                const uint32_t *__restrict__ inv, const uint32_t *__restrict__ pflag, const float *__restrict__ slots,
+                const uint64_t *__restrict__ keff, float *__restrict__ acc)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float a[kAccStride];
+#pragma unroll
+    for (int c = 0; c < kAccStride; ++c) a[c] = 0.0f;
+    const uint64_t K = *keff;   // 0 when the render overflowed: nothing was emitted
+    for (int32_t f = 0; f < nframes && K > 0; ++f) {
+        const FrameDesc &fd = descs[f];
+        if (fd.set != set) continue;
+        const int64_t r = fd.item_off + k;
+        const int32_t cnt = counts[r];
+        if (cnt <= 0) continue;
+        const uint64_t e0 = estart[r];
+        for (int32_t q = 0; q < cnt; ++q) {
+            if (e0 + (uint64_t)q >= K) break;
+            const uint32_t P = inv[e0 + q];
+            if ((uint64_t)P >= K) continue;
+            const uint32_t fl = pflag[P];
+            if (fl == 0) continue;
+#pragma unroll
+            for (int st = 0; st < kSlotStrips; ++st) {
+                if (((fl >> (8 * st)) & 0xffu) == 0) continue;
+                const float4 *sl = reinterpret_cast<const float4 *>(slots + ((size_t)P * kSlotStrips + st) * kSlotFloats);
+                const float4 s0 = sl[0], s1 = sl[1], s2 = sl[2], s3 = sl[3];
+                a[0] += s0.x; a[1] += s0.y; a[2] += s0.z; a[3] += s0.w;
+                a[4] += s1.x; a[5] += s1.y; a[6] += s1.z; a[7] += s1.w;
+                a[8] += s2.x; a[9] += s2.y; a[10] += s2.z; a[11] += s2.w;
+                a[12] += s3.x;
+            }
+        }
+    }
+    float *o = acc + (size_t)k * kAccStride;
+#pragma unroll
+    for (int c = 0; c < kAccStride; ++c) o[c] = a[c];
+}
+
+// Per keyframe: the sum of the compositing workgroups' pose partials (6 values
+// and the keyframe index in a row of 8 doubles), in a fixed order, written to
+// the keyframe's pose gradient.
+__global__ void __launch_bounds__(256)
+k_pose_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts)
+{
+    __shared__ double red[6][256];
+    const int f = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
+        const double *pp = part + 8 * b;
+        if ((int)pp[6] != f) continue;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += pp[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) descs[f].d_pose[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Zero words_per_pair 32-bit words for each of the K pairs of the last render.
+__global__ void __launch_bounds__(256)
+k_fill_pairs(uint32_t *__restrict__ p, const uint64_t *__restrict__ keff, int64_t words_per_pair)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((uint64_t)i < *keff * (uint64_t)words_per_pair) p[i] = 0u;
+}
 
 __global__ void __launch_bounds__(256)
 k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restrict__ lsc,
@@ -78,6 +162,35 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
 }
 
 }  // namespace
+
+void launch_surfel_reduce(const Layout &L, char *ws, int32_t set, int64_t n, int64_t acc_off, hipStream_t stream)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_surfel_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), L.frames, set, n,
+                       reinterpret_cast<const int32_t *>(ws + L.cnt), reinterpret_cast<const uint32_t *>(ws + L.estart),
+                       reinterpret_cast<const uint32_t *>(ws + L.inv), reinterpret_cast<const uint32_t *>(ws + L.pflag),
+                       reinterpret_cast<const float *>(ws + L.slot),
+                       reinterpret_cast<const uint64_t *>(ws + L.misc) + 2, reinterpret_cast<float *>(ws + L.acc) + acc_off);
+}
+
+void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.frames == 0) return;
+    const int64_t nparts = (L.variant == SLR_VARIANT_WAVE ? kSlotStrips : 1) * L.tiles;
+    hipLaunchKernelGGL(k_pose_reduce, dim3((unsigned)L.frames), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.pose_part),
+                       nparts);
+}
+
+void launch_fill_pairs(const Layout &L, char *ws, size_t region, int64_t words_per_pair, hipStream_t stream)
+{
+    if (L.cap == 0 || L.items == 0) return;
+    const int64_t words = L.cap * words_per_pair;
+    hipLaunchKernelGGL(k_fill_pairs, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(ws + region), reinterpret_cast<const uint64_t *>(ws + L.misc) + 2,
+                       words_per_pair);
+}
 
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits,
