@@ -730,8 +730,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
     __shared__ ChatRec schat[kBwdBatch];
-    __shared__ float sred[kNg][kBwdBatch];   // wave sums of the four waves, added in LDS
-    __shared__ int sflag[kBwdBatch];
+    __shared__ float sred[4][kNg][kBwdBatch];   // each wave's sums, added in wave order at the flush
+    __shared__ int sflag[4][kBwdBatch];
     __shared__ uint8_t slist[4][kBwdBatch];
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
@@ -767,8 +767,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
     const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
     if (threadIdx.x == 0) s_last = 0;
-    for (int e = threadIdx.x; e < kNg * kBwdBatch; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
-    for (int e = threadIdx.x; e < kBwdBatch; e += blockDim.x) sflag[e] = 0;
+    for (int e = threadIdx.x; e < 4 * kBwdBatch; e += blockDim.x) (&sflag[0][0])[e] = 0;
     __syncthreads();
     if (last > 0) atomicMax(&s_last, last);
     __syncthreads();
@@ -828,19 +827,24 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             if (__any(act)) {
                 static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                 const float tot = wave_sum18(g, lane);
-                if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
-                if (lane == 0) sflag[k] = 1;
+                if (red_val < kNg) sred[wid][red_val][k] = tot;
+                if (lane == 0) sflag[wid][k] = 1;
             }
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int k = threadIdx.x;
-            if (sflag[k]) {
-                // take the record's sums and leave the slots zeroed for the next batch
+            if (sflag[0][k] | sflag[1][k] | sflag[2][k] | sflag[3][k]) {
                 float s[kNg];
 #pragma unroll
-                for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
-                sflag[k] = 0;
+                for (int v = 0; v < kNg; ++v) s[v] = 0.0f;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if (!sflag[w][k]) continue;
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) s[v] += sred[w][v][k];
+                    sflag[w][k] = 0;
+                }
                 const uint32_t id = pval[b0 + k];
                 const size_t slot = (size_t)(b0 + k) * kSlotStrips;   // this workgroup holds the whole tile
                 flush_record(s, frame[id], srec[k].M, schat[k].c, pose,
