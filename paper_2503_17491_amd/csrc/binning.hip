@@ -92,7 +92,8 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__
 
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-                uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
+                uint32_t *__restrict__ vout, const uint32_t *__restrict__ vin2, uint32_t *__restrict__ vout2,
+                int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
@@ -154,6 +155,8 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
             uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
             kout[pos] = key[i];
             vout[pos] = val[i];
+            // optional second value: its input is the item's position when vin2 is NULL
+            if (vout2) vout2[pos] = vin2 ? vin2[idx] : (uint32_t)idx;
         }
     }
 }
@@ -237,8 +240,7 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
 __global__ void __launch_bounds__(256)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
        const int32_t *__restrict__ counts, const PixBox *__restrict__ box, int64_t n, const uint64_t *__restrict__ keff,
-       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval, uint32_t *__restrict__ rid,
-       uint32_t *__restrict__ estart)
+       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval, uint32_t *__restrict__ estart)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || *keff == 0) return;
@@ -257,23 +259,9 @@ k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, 
         if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
     }
     for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = o; rid[o] = id; ++o; }
-        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = o; rid[o] = id; ++o; }
+        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
+        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
     }
-}
-
-// The tile sort carries each pair's emission position E; turn the sorted
-// values into record ids and record where every emitted pair went.
-__global__ void __launch_bounds__(256)
-k_finalize_pairs(uint32_t *__restrict__ sval, const uint32_t *__restrict__ rid, uint32_t *__restrict__ inv,
-                 const uint64_t *__restrict__ keff)
-{
-    const int64_t K = (int64_t)*keff;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= K) return;
-    const uint32_t e = sval[p];
-    sval[p] = rid[e];
-    inv[e] = (uint32_t)p;
 }
 
 __global__ void __launch_bounds__(256)
@@ -333,15 +321,16 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 
 // One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
 // n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *vin2,
+                uint32_t *vout2, int64_t n_max, const uint64_t *n_dev, int shift, int bits, uint32_t *hist,
+                uint32_t *totals, hipStream_t stream)
 {
     int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
                        nblocks);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
-                       shift, bits, hist, totals, nblocks);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, vin2, vout2,
+                       n_max, n_dev, shift, bits, hist, totals, nblocks);
 }
 
 }  // namespace
@@ -365,8 +354,8 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
         const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
-        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
-                   stream);
+        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, nullptr, nullptr, L.items, nullptr, 8 * p, 8,
+                   hist, totals, stream);
     }
 }
 
@@ -407,11 +396,12 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
     uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
+    uint32_t *e0 = reinterpret_cast<uint32_t *>(ws + L.pe0), *e1 = reinterpret_cast<uint32_t *>(ws + L.pe1);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
                        reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0,
-                       reinterpret_cast<uint32_t *>(ws + L.rid), reinterpret_cast<uint32_t *>(ws + L.estart));
+                       reinterpret_cast<uint32_t *>(ws + L.estart));
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)
@@ -419,14 +409,12 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     for (int p = 0; p < L.tile_passes; ++p) {
         int bits = (L.tile_bits - done + (L.tile_passes - p) - 1) / (L.tile_passes - p);
         const bool even = (p % 2) == 0;
-        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, L.cap, keff, done, bits, hist,
-                   totals, stream);
+        // the second value is the pair's emission position
+        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, p == 0 ? nullptr : (even ? e0 : e1),
+                   even ? e1 : e0, L.cap, keff, done, bits, hist, totals, stream);
         done += bits;
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;
-    hipLaunchKernelGGL(k_finalize_pairs, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream,
-                       L.tile_in_1 ? v1 : v0, reinterpret_cast<const uint32_t *>(ws + L.rid),
-                       reinterpret_cast<uint32_t *>(ws + L.inv), keff);
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream, ts, keff, ranges);
     launch_tile_order(L, ws, stream);
 }

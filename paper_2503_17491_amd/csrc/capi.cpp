@@ -354,7 +354,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
         L.items += set_n[frames[f].set];
     }
     for (int32_t s = 0; s < nsets; ++s) L.acc_floats += set_n[s] * kAccStride;
-    L.tile_bits = ceil_log2(L.tiles > 0 ? L.tiles : 1);
+    // at least one pass: the tile sort also produces each pair's emission position
+    L.tile_bits = ceil_log2(L.tiles > 1 ? L.tiles : 2);
     L.depth_passes = 4;
     L.tile_passes = (L.tile_bits + kMaxDigitBits - 1) / kMaxDigitBits;
     L.depth_in_1 = (L.depth_passes % 2) == 1;
@@ -376,8 +377,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
-    L.rid = take(4 * cc);
-    L.inv = take(4 * cc);
+    L.pe0 = take(4 * cc);
+    L.pe1 = take(4 * cc);
     L.estart = take(4 * nn);
     L.pflag = take(4 * cc);
     L.slot = take(sizeof(float) * kSlotFloats * kSlotStrips * (size_t)cc);

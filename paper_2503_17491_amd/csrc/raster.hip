@@ -724,8 +724,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-             float *__restrict__ slots, uint8_t *__restrict__ pflag, double *__restrict__ pose_part,
-             int pose_only)
+             float *__restrict__ slots, uint8_t *__restrict__ pflag, const uint32_t *__restrict__ pemit,
+             double *__restrict__ pose_part, int pose_only)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
@@ -846,7 +846,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                     sflag[w][k] = 0;
                 }
                 const uint32_t id = pval[b0 + k];
-                const size_t slot = (size_t)(b0 + k) * kSlotStrips;   // this workgroup holds the whole tile
+                const size_t slot = (size_t)pemit[b0 + k] * kSlotStrips;   // this workgroup holds the whole tile
                 flush_record(s, frame[id], srec[k].M, schat[k].c, pose,
                              pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
             }
@@ -896,8 +896,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-               float *__restrict__ slots, uint8_t *__restrict__ pflag, double *__restrict__ pose_part,
-               int pose_only)
+               float *__restrict__ slots, uint8_t *__restrict__ pflag, const uint32_t *__restrict__ pemit,
+               double *__restrict__ pose_part, int pose_only)
 {
     constexpr int TH = 256 / TW, SR = 64 / TW;
     __shared__ RasterRec sbuf[64];
@@ -1058,7 +1058,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             float s[kNg];
 #pragma unroll
             for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
-            const size_t slot = (size_t)(c + lane) * kSlotStrips + strip;
+            const size_t slot = (size_t)pemit[c + lane] * kSlotStrips + strip;
             flush_record(s, frame[id], sbuf[lane].M, schat[lane].c, fd.pose,
                          pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
         }
@@ -1114,8 +1114,9 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<float *>(ws + L.slot),
-                       reinterpret_cast<uint8_t *>(ws + L.pflag), reinterpret_cast<double *>(ws + L.pose_part),
-                       pose_only ? 1 : 0);
+                       reinterpret_cast<uint8_t *>(ws + L.pflag),
+                       reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pe1 : L.pe0)),
+                       reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0);
 }
 
 }  // namespace

@@ -75,7 +75,8 @@ constexpr int kAccStride = 13;
 
 // The backward writes each (pair, strip) contribution to a slot of its own
 // instead of adding it to the surfel's accumulator: kSlotStrips slots of
-// kSlotFloats floats (13 used) per pair, one flag byte per slot.
+// kSlotFloats floats (13 used) per pair, one flag byte per slot, indexed by
+// the pair's emission position (a record's pairs are contiguous there).
 constexpr int kSlotStrips = 4;
 constexpr int kSlotFloats = 16;
 
@@ -99,7 +100,7 @@ struct Layout {
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, rid, inv, estart, pflag, slot, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, pe0, pe1, estart, pflag, slot, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 

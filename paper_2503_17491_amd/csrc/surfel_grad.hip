@@ -15,12 +15,13 @@ namespace slr {
 namespace {
 
 // Per surfel of one set: for every keyframe that renders the set, the surfel's
-// record emitted its pairs at positions [estart, estart + count); each pair's
-// written slots (flag byte set) are added in the order keyframe, pair, strip.
+// record emitted its pairs at positions [estart, estart + count); the written
+// slots of those positions (flag byte set) are added in the order keyframe,
+// pair, strip.
 __global__ void __launch_bounds__(256)
 k_surfel_reduce(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
                 const int32_t *__restrict__ counts, const uint32_t *__restrict__ estart,
-                const uint32_t *__restrict__ inv, const uint32_t *__restrict__ pflag, const float *__restrict__ slots,
+                const uint32_t *__restrict__ pflag, const float *__restrict__ slots,
                 const uint64_t *__restrict__ keff, float *__restrict__ acc)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,9 +38,8 @@ k_surfel_reduce(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t se
         if (cnt <= 0) continue;
         const uint64_t e0 = estart[r];
         for (int32_t q = 0; q < cnt; ++q) {
-            if (e0 + (uint64_t)q >= K) break;
-            const uint32_t P = inv[e0 + q];
-            if ((uint64_t)P >= K) continue;
+            const uint64_t P = e0 + (uint64_t)q;
+            if (P >= K) break;
             const uint32_t fl = pflag[P];
             if (fl == 0) continue;
 #pragma unroll
@@ -169,7 +169,7 @@ void launch_surfel_reduce(const Layout &L, char *ws, int32_t set, int64_t n, int
     hipLaunchKernelGGL(k_surfel_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), L.frames, set, n,
                        reinterpret_cast<const int32_t *>(ws + L.cnt), reinterpret_cast<const uint32_t *>(ws + L.estart),
-                       reinterpret_cast<const uint32_t *>(ws + L.inv), reinterpret_cast<const uint32_t *>(ws + L.pflag),
+                       reinterpret_cast<const uint32_t *>(ws + L.pflag),
                        reinterpret_cast<const float *>(ws + L.slot),
                        reinterpret_cast<const uint64_t *>(ws + L.misc) + 2, reinterpret_cast<float *>(ws + L.acc) + acc_off);
 }
