@@ -197,7 +197,7 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
 
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
-             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
+             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets, uint32_t *__restrict__ rcounts)
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_items[kSortTile];
@@ -225,6 +225,12 @@ k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ or
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) offsets[idx] = s_items[i * kSortThreads + threadIdx.x];
     }
+    // the counts in range order as well (the backward's gather walks records in this order)
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) rcounts[idx] = (uint32_t)counts[order[idx]];
+    }
 }
 
 // Pair-capacity check on the device: the effective pair count is K, or 0 with
@@ -240,13 +246,12 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
 __global__ void __launch_bounds__(256)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
        const int32_t *__restrict__ counts, const PixBox *__restrict__ box, int64_t n, const uint64_t *__restrict__ keff,
-       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval, uint32_t *__restrict__ estart)
+       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || *keff == 0) return;
     uint32_t id = order[r];
     if (counts[id] == 0) return;
-    estart[id] = offsets[r];
     PixBox b = box[id];
     const FrameDesc &fd = descs[b.frame];
     const int th = fd.th, tw = fd.tw, tiles_x = fd.tiles_x, toff = fd.tile_off;
@@ -373,7 +378,7 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs,
-                       reinterpret_cast<uint32_t *>(ws + L.off));
+                       reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.rcnt));
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
@@ -400,8 +405,7 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
-                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0,
-                       reinterpret_cast<uint32_t *>(ws + L.estart));
+                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)

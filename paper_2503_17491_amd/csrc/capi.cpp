@@ -305,6 +305,7 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
     slr::launch_pose_reduce(L, ws, s);
     if (pose_only) return;
     StageScope t(6, s);
+    slr::launch_record_reduce(L, ws, s);
     int64_t off = 0;
     for (int32_t k = 0; k < L.sets; ++k) {
         const slr_surfel_grads &g = grads[k];
@@ -379,7 +380,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
     L.pe0 = take(4 * cc);
     L.pe1 = take(4 * cc);
-    L.estart = take(4 * nn);
+    L.rcnt = take(4 * nn);
+    L.racc = take(sizeof(float) * kAccStride * (size_t)nn);
     L.pflag = take(4 * cc);
     L.slot = take(sizeof(float) * kSlotFloats * kSlotStrips * (size_t)cc);
     L.pose_part = take(sizeof(double) * 8 * kSlotStrips * (size_t)(L.tiles > 0 ? L.tiles : 1));

@@ -100,7 +100,7 @@ struct Layout {
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, pe0, pe1, estart, pflag, slot, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, pe0, pe1, rcnt, racc, pflag, slot, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
@@ -121,6 +121,7 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream);
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream);
+void launch_record_reduce(const Layout &L, char *ws, hipStream_t stream);
 void launch_surfel_reduce(const Layout &L, char *ws, int32_t set, int64_t n, int64_t acc_off, hipStream_t stream);
 void launch_fill_pairs(const Layout &L, char *ws, size_t region, int64_t words_per_pair, hipStream_t stream);
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
