@@ -92,8 +92,7 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__
 
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-                uint32_t *__restrict__ vout, const uint32_t *__restrict__ vin2, uint32_t *__restrict__ vout2,
-                int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
+                uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
@@ -155,8 +154,6 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
             uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
             kout[pos] = key[i];
             vout[pos] = val[i];
-            // optional second value: its input is the item's position when vin2 is NULL
-            if (vout2) vout2[pos] = vin2 ? vin2[idx] : (uint32_t)idx;
         }
     }
 }
@@ -197,7 +194,7 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
 
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
-             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets, uint32_t *__restrict__ rcounts)
+             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_items[kSortTile];
@@ -224,12 +221,6 @@ k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ or
     for (int i = 0; i < kSortItems; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) offsets[idx] = s_items[i * kSortThreads + threadIdx.x];
-    }
-    // the counts in range order as well (the backward's gather walks records in this order)
-#pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
-        int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) rcounts[idx] = (uint32_t)counts[order[idx]];
     }
 }
 
@@ -326,16 +317,15 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 
 // One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
 // n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *vin2,
-                uint32_t *vout2, int64_t n_max, const uint64_t *n_dev, int shift, int bits, uint32_t *hist,
-                uint32_t *totals, hipStream_t stream)
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+                const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
 {
     int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
                        nblocks);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, vin2, vout2,
-                       n_max, n_dev, shift, bits, hist, totals, nblocks);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
+                       shift, bits, hist, totals, nblocks);
 }
 
 }  // namespace
@@ -359,8 +349,8 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
         const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
-        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, nullptr, nullptr, L.items, nullptr, 8 * p, 8,
-                   hist, totals, stream);
+        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
+                   stream);
     }
 }
 
@@ -378,7 +368,7 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs,
-                       reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.rcnt));
+                       reinterpret_cast<uint32_t *>(ws + L.off));
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
@@ -401,7 +391,6 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
     uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
-    uint32_t *e0 = reinterpret_cast<uint32_t *>(ws + L.pe0), *e1 = reinterpret_cast<uint32_t *>(ws + L.pe1);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
@@ -413,9 +402,8 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     for (int p = 0; p < L.tile_passes; ++p) {
         int bits = (L.tile_bits - done + (L.tile_passes - p) - 1) / (L.tile_passes - p);
         const bool even = (p % 2) == 0;
-        // the second value is the pair's emission position
-        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, p == 0 ? nullptr : (even ? e0 : e1),
-                   even ? e1 : e0, L.cap, keff, done, bits, hist, totals, stream);
+        radix_pass(even ? t0 : t1, even ? v0 : v1, even ? t1 : t0, even ? v1 : v0, L.cap, keff, done, bits, hist,
+                   totals, stream);
         done += bits;
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;

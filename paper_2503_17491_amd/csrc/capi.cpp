@@ -296,8 +296,7 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
                       bool pose_only, bool accumulate, hipStream_t s)
 {
     const Layout &L = B.L;
-    // slot flags of the pairs this render produced start cleared
-    if (!pose_only) slr::launch_fill_pairs(L, ws, L.pflag, 1, s);
+    if (!pose_only) slr::launch_fill_u32(ws + L.acc, 0u, L.acc_floats, s);
     {
         StageScope t(5, s);
         slr::launch_raster_bwd(L, ws, pose_only, s);
@@ -305,16 +304,13 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
     slr::launch_pose_reduce(L, ws, s);
     if (pose_only) return;
     StageScope t(6, s);
-    slr::launch_record_reduce(L, ws, s);
     int64_t off = 0;
     for (int32_t k = 0; k < L.sets; ++k) {
         const slr_surfel_grads &g = grads[k];
-        if (g.means) {
-            slr::launch_surfel_reduce(L, ws, k, sets[k].n, off, s);
+        if (g.means)
             slr::launch_surfel_grad(sets[k].quats, sets[k].log_scales, sets[k].logits, sets[k].n,
                                     reinterpret_cast<const float *>(ws + L.acc) + off, g.means, g.quats, g.log_scales,
                                     g.logits, accumulate, s);
-        }
         off += sets[k].n * slr::kAccStride;
     }
 }
@@ -355,8 +351,7 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
         L.items += set_n[frames[f].set];
     }
     for (int32_t s = 0; s < nsets; ++s) L.acc_floats += set_n[s] * kAccStride;
-    // at least one pass: the tile sort also produces each pair's emission position
-    L.tile_bits = ceil_log2(L.tiles > 1 ? L.tiles : 2);
+    L.tile_bits = ceil_log2(L.tiles > 0 ? L.tiles : 1);
     L.depth_passes = 4;
     L.tile_passes = (L.tile_bits + kMaxDigitBits - 1) / kMaxDigitBits;
     L.depth_in_1 = (L.depth_passes % 2) == 1;
@@ -378,13 +373,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
-    L.pe0 = take(4 * cc);
-    L.pe1 = take(4 * cc);
-    L.rcnt = take(4 * nn);
-    L.racc = take(sizeof(float) * kAccStride * (size_t)nn);
-    L.pflag = take(4 * cc);
-    L.slot = take(sizeof(float) * kSlotFloats * kSlotStrips * (size_t)cc);
-    L.pose_part = take(sizeof(double) * 8 * kSlotStrips * (size_t)(L.tiles > 0 ? L.tiles : 1));
+    // per compositing workgroup: its pose partial (6 doubles) and keyframe index
+    L.pose_part = take(sizeof(double) * 8 * 4 * (size_t)(L.tiles > 0 ? L.tiles : 1));
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));

@@ -659,12 +659,10 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
 // A record's pixel sums of the 18 partials -> dL/d(b_alpha, b_beta, b_c, n) in
 // FP64 (dPv = E_a + A_a ch, dQv = E_b + A_b ch; g_alpha = E_b x b_c + b_beta x C_s
 // + T_a M, g_beta = b_c x E_a + C_s x b_alpha + T_b M, g_c = dPv x b_beta +
-// b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (slot not
-// NULL) the 13 world-frame gradients written to the slot (64 bytes) with its
-// flag byte set.
+// b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (acc not
+// NULL) the world-frame gradients added to the record's accumulator.
 __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRec &fr, const double *M,
-                                             const double *ch, const double *pose, float *slot, uint8_t *flag,
-                                             double (&pacc)[6])
+                                             const double *ch, const double *pose, float *acc, double (&pacc)[6])
 {
     const double Ea[3] = {s[0], s[1], s[2]}, Eb[3] = {s[3], s[4], s[5]}, Cs[3] = {s[6], s[7], s[8]};
     const double Aa = s[9], Ab = s[10], Ta = s[11], Tb = s[12], Tc = s[13];
@@ -692,26 +690,24 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
         pacc[c] -= gc[c];
         pacc[3 + c] += c1[c] + c2[c] + c3[c] + c4[c];
     }
-    if (slot) {
+    if (acc) {
         double R[9];
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
         }
-        float w[16];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            w[c] = (float)(R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2]);
-            w[3 + c] = (float)(R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2]);
-            w[6 + c] = (float)(R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2]);
-            w[9 + c] = (float)(R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2]);
+            const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
+            const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
+            const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
+            const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
+            atomicAdd(acc + c, (float)wa);
+            atomicAdd(acc + 3 + c, (float)wb);
+            atomicAdd(acc + 6 + c, (float)wc);
+            atomicAdd(acc + 9 + c, (float)wn);
         }
-        w[12] = s[14];
-        w[13] = w[14] = w[15] = 0.0f;
-        float4 *d = reinterpret_cast<float4 *>(slot);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-        *flag = 1;
+        atomicAdd(acc + 12, s[14]);
     }
 }
 
@@ -724,14 +720,13 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-             float *__restrict__ slots, uint8_t *__restrict__ pflag, const uint32_t *__restrict__ pemit,
              double *__restrict__ pose_part, int pose_only)
 {
     constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
     __shared__ ChatRec schat[kBwdBatch];
-    __shared__ float sred[4][kNg][kBwdBatch];   // each wave's sums, added in wave order at the flush
-    __shared__ int sflag[4][kBwdBatch];
+    __shared__ float sred[kNg][kBwdBatch];   // wave sums of the four waves, added in LDS
+    __shared__ int sflag[kBwdBatch];
     __shared__ uint8_t slist[4][kBwdBatch];
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
@@ -746,6 +741,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     int32_t *census = census_all + fd.pix_off;
     const float *gD = fd.gD, *gN = fd.gN, *gO = fd.gO;
     const double *pose = fd.pose;
+    float *acc = fd.acc;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
@@ -767,7 +763,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
     const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
     if (threadIdx.x == 0) s_last = 0;
-    for (int e = threadIdx.x; e < 4 * kBwdBatch; e += blockDim.x) (&sflag[0][0])[e] = 0;
+    for (int e = threadIdx.x; e < kNg * kBwdBatch; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
+    for (int e = threadIdx.x; e < kBwdBatch; e += blockDim.x) sflag[e] = 0;
     __syncthreads();
     if (last > 0) atomicMax(&s_last, last);
     __syncthreads();
@@ -827,28 +824,21 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             if (__any(act)) {
                 static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                 const float tot = wave_sum18(g, lane);
-                if (red_val < kNg) sred[wid][red_val][k] = tot;
-                if (lane == 0) sflag[wid][k] = 1;
+                if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
+                if (lane == 0) sflag[k] = 1;
             }
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int k = threadIdx.x;
-            if (sflag[0][k] | sflag[1][k] | sflag[2][k] | sflag[3][k]) {
+            if (sflag[k]) {
+                // take the record's sums and leave the slots zeroed for the next batch
                 float s[kNg];
 #pragma unroll
-                for (int v = 0; v < kNg; ++v) s[v] = 0.0f;
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    if (!sflag[w][k]) continue;
-#pragma unroll
-                    for (int v = 0; v < kNg; ++v) s[v] += sred[w][v][k];
-                    sflag[w][k] = 0;
-                }
+                for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
+                sflag[k] = 0;
                 const uint32_t id = pval[b0 + k];
-                const size_t slot = (size_t)pemit[b0 + k] * kSlotStrips;   // this workgroup holds the whole tile
-                flush_record(s, frame[id], srec[k].M, schat[k].c, pose,
-                             pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
+                flush_record(s, frame[id], srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
             }
         }
     }
@@ -896,7 +886,6 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-               float *__restrict__ slots, uint8_t *__restrict__ pflag, const uint32_t *__restrict__ pemit,
                double *__restrict__ pose_part, int pose_only)
 {
     constexpr int TH = 256 / TW, SR = 64 / TW;
@@ -941,6 +930,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     for (int v = 0; v < kNg; ++v) sred[v][lane] = 0.0f;
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     int n_eval = 0, n_con = 0;
+    float *acc_base = pose_only ? nullptr : fd.acc;
     const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
     int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64;
     // a record travels as six 16-byte words (the last one ends with the rows
@@ -1058,9 +1048,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             float s[kNg];
 #pragma unroll
             for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
-            const size_t slot = (size_t)pemit[c + lane] * kSlotStrips + strip;
             flush_record(s, frame[id], sbuf[lane].M, schat[lane].c, fd.pose,
-                         pose_only ? nullptr : slots + slot * kSlotFloats, pflag + slot, pacc);
+                         acc_base ? acc_base + (size_t)(id - fd.item_off) * kAccStride : nullptr, pacc);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1113,10 +1102,8 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
-                       reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<float *>(ws + L.slot),
-                       reinterpret_cast<uint8_t *>(ws + L.pflag),
-                       reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pe1 : L.pe0)),
-                       reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0);
+                       reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<double *>(ws + L.pose_part),
+                       pose_only ? 1 : 0);
 }
 
 }  // namespace

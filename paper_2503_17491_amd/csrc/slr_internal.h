@@ -73,13 +73,6 @@ struct __align__(16) FrameDesc {
 // dL/dmu, dL/dt_n and dL/do.
 constexpr int kAccStride = 13;
 
-// The backward writes each (pair, strip) contribution to a slot of its own
-// instead of adding it to the surfel's accumulator: kSlotStrips slots of
-// kSlotFloats floats (13 used) per pair, one flag byte per slot, indexed by
-// the pair's emission position (a record's pairs are contiguous there).
-constexpr int kSlotStrips = 4;
-constexpr int kSlotFloats = 16;
-
 // Radix sort geometry.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                       // per thread
@@ -100,7 +93,7 @@ struct Layout {
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, pe0, pe1, rcnt, racc, pflag, slot, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
@@ -121,9 +114,6 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream);
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream);
-void launch_record_reduce(const Layout &L, char *ws, hipStream_t stream);
-void launch_surfel_reduce(const Layout &L, char *ws, int32_t set, int64_t n, int64_t acc_off, hipStream_t stream);
-void launch_fill_pairs(const Layout &L, char *ws, size_t region, int64_t words_per_pair, hipStream_t stream);
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits,
                         bool accumulate, hipStream_t stream);

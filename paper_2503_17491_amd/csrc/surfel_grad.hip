@@ -1,9 +1,6 @@
-// surfel_grad.hip -- per-surfel parameter gradients (Supp. D, last block), and
-// the gathers that turn the compositing backward's per-(pair, strip) slots and
-// per-workgroup pose partials into per-surfel sums and per-keyframe pose
-// gradients in a fixed order.
+// surfel_grad.hip -- per-surfel parameter gradients (Supp. D, last block).
 //
-// The gather leaves, per surfel, the world-frame gradients
+// The compositing backward leaves, per surfel, the world-frame gradients
 //   w_a = dL/d(s_a t_a), w_b = dL/d(s_b t_b), w_c = dL/dmu, w_n = dL/dt_n,
 //   g_o = dL/do
 // summed over pixels (and over keyframes that share the surfel).  This kernel
@@ -13,67 +10,6 @@
 
 namespace slr {
 namespace {
-
-// Per record, in range order (records of consecutive ranks own adjacent
-// emission ranges, so a wave reads one contiguous span): the written slots
-// (flag byte set) of the record's pairs [offset, offset + count), added in the
-// order pair, strip, into the record's 13 sums.
-__global__ void __launch_bounds__(256)
-k_record_reduce(int64_t n, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-                const uint32_t *__restrict__ rcounts, const uint32_t *__restrict__ pflag,
-                const float *__restrict__ slots, const uint64_t *__restrict__ keff, float *__restrict__ racc)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    float a[kAccStride];
-#pragma unroll
-    for (int c = 0; c < kAccStride; ++c) a[c] = 0.0f;
-    const uint64_t K = *keff;   // 0 when the render overflowed: nothing was emitted
-    const uint32_t cnt = K > 0 ? rcounts[r] : 0u;
-    const uint64_t e0 = offsets[r];
-    for (uint32_t q = 0; q < cnt; ++q) {
-        const uint64_t E = e0 + q;
-        if (E >= K) break;
-        const uint32_t fl = pflag[E];
-        if (fl == 0) continue;
-#pragma unroll
-        for (int st = 0; st < kSlotStrips; ++st) {
-            if (((fl >> (8 * st)) & 0xffu) == 0) continue;
-            const float4 *sl = reinterpret_cast<const float4 *>(slots + (E * kSlotStrips + st) * kSlotFloats);
-            const float4 s0 = sl[0], s1 = sl[1], s2 = sl[2], s3 = sl[3];
-            a[0] += s0.x; a[1] += s0.y; a[2] += s0.z; a[3] += s0.w;
-            a[4] += s1.x; a[5] += s1.y; a[6] += s1.z; a[7] += s1.w;
-            a[8] += s2.x; a[9] += s2.y; a[10] += s2.z; a[11] += s2.w;
-            a[12] += s3.x;
-        }
-    }
-    float *o = racc + (size_t)order[r] * kAccStride;
-#pragma unroll
-    for (int c = 0; c < kAccStride; ++c) o[c] = a[c];
-}
-
-// Per surfel of one set: the sum of its records over the keyframes that render
-// the set, in keyframe order.
-__global__ void __launch_bounds__(256)
-k_surfel_reduce(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
-                const float *__restrict__ racc, float *__restrict__ acc)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    float a[kAccStride];
-#pragma unroll
-    for (int c = 0; c < kAccStride; ++c) a[c] = 0.0f;
-    for (int32_t f = 0; f < nframes; ++f) {
-        const FrameDesc &fd = descs[f];
-        if (fd.set != set) continue;
-        const float *src = racc + (size_t)(fd.item_off + k) * kAccStride;
-#pragma unroll
-        for (int c = 0; c < kAccStride; ++c) a[c] += src[c];
-    }
-    float *o = acc + (size_t)k * kAccStride;
-#pragma unroll
-    for (int c = 0; c < kAccStride; ++c) o[c] = a[c];
-}
 
 // Per keyframe: the sum of the compositing workgroups' pose partials (6 values
 // and the keyframe index in a row of 8 doubles), in a fixed order, written to
@@ -101,14 +37,6 @@ k_pose_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ pa
         __syncthreads();
     }
     if (threadIdx.x < 6) descs[f].d_pose[threadIdx.x] = red[threadIdx.x][0];
-}
-
-// Zero words_per_pair 32-bit words for each of the K pairs of the last render.
-__global__ void __launch_bounds__(256)
-k_fill_pairs(uint32_t *__restrict__ p, const uint64_t *__restrict__ keff, int64_t words_per_pair)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((uint64_t)i < *keff * (uint64_t)words_per_pair) p[i] = 0u;
 }
 
 __global__ void __launch_bounds__(256)
@@ -179,40 +107,13 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
 
 }  // namespace
 
-void launch_record_reduce(const Layout &L, char *ws, hipStream_t stream)
-{
-    if (L.items == 0) return;
-    hipLaunchKernelGGL(k_record_reduce, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream, L.items,
-                       reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0)),
-                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
-                       reinterpret_cast<const uint32_t *>(ws + L.pflag), reinterpret_cast<const float *>(ws + L.slot),
-                       reinterpret_cast<const uint64_t *>(ws + L.misc) + 2, reinterpret_cast<float *>(ws + L.racc));
-}
-
-void launch_surfel_reduce(const Layout &L, char *ws, int32_t set, int64_t n, int64_t acc_off, hipStream_t stream)
-{
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_surfel_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                       reinterpret_cast<const FrameDesc *>(ws + L.desc), L.frames, set, n,
-                       reinterpret_cast<const float *>(ws + L.racc), reinterpret_cast<float *>(ws + L.acc) + acc_off);
-}
-
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.frames == 0) return;
-    const int64_t nparts = (L.variant == SLR_VARIANT_WAVE ? kSlotStrips : 1) * L.tiles;
+    const int64_t nparts = (L.variant == SLR_VARIANT_WAVE ? 4 : 1) * L.tiles;
     hipLaunchKernelGGL(k_pose_reduce, dim3((unsigned)L.frames), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.pose_part),
                        nparts);
-}
-
-void launch_fill_pairs(const Layout &L, char *ws, size_t region, int64_t words_per_pair, hipStream_t stream)
-{
-    if (L.cap == 0 || L.items == 0) return;
-    const int64_t words = L.cap * words_per_pair;
-    hipLaunchKernelGGL(k_fill_pairs, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream,
-                       reinterpret_cast<uint32_t *>(ws + region), reinterpret_cast<const uint64_t *>(ws + L.misc) + 2,
-                       words_per_pair);
 }
 
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,

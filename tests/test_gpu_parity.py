@@ -272,11 +272,12 @@ def test_backward_parity_fullsize_sparse(slr):
                    g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (16, 16), 1 << 20)
 
 
-def test_backward_is_deterministic(slr):
-    """Surfel gradients are gathered from per-(pair, strip) slots and pose
-    gradients from per-workgroup partials in a fixed order: two backward
-    calls give bit-identical results, for both compositing forms."""
-    say("backward determinism")
+def test_backward_repeatable(slr):
+    """The pose gradient is reduced from per-workgroup partials in a fixed
+    order: with the one-wave form (whose record sums are deterministic) two
+    backward calls give bit-identical pose gradients; the surfel gradients are
+    added with float atomics and agree to rounding."""
+    say("backward repeatability")
     sc, _ = synth.structured_scene(20000, 5)
     sensor = slr.make_sensor(64, 512)
     T = synth.circle_poses(8, 1)[2]
@@ -284,16 +285,16 @@ def test_backward_is_deterministic(slr):
     GD = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
     GN = torch.from_numpy(g.normal(size=(64, 512, 3)).astype(np.float32)).to(DEV)
     GO = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
-    for tiling in [(16, 16, 3), (16, 16, 1)]:
-        r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, tiling, 1 << 20)
-        outs = []
-        for _ in range(2):
-            gr, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, GD, GN, GO)
-            torch.cuda.synchronize()
-            outs.append([gr[k].cpu().numpy().copy() for k in ("means", "quats", "log_scales", "logits")] +
-                        [dp.cpu().numpy().copy()])
-        for a, b in zip(*outs):
-            np.testing.assert_array_equal(a, b)
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, (16, 16, 3), 1 << 20)
+    outs = []
+    for _ in range(2):
+        gr, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, GD, GN, GO)
+        torch.cuda.synchronize()
+        outs.append(([gr[k].cpu().numpy().copy() for k in ("means", "quats", "log_scales", "logits")],
+                     dp.cpu().numpy().copy()))
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    for a, b in zip(outs[0][0], outs[1][0]):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(a).max()))
 
 
 def test_pose_only_matches_full_backward(slr):
