@@ -374,7 +374,7 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
-    L.pose_part = take(sizeof(double) * 8 * 4 * (size_t)(L.tiles > 0 ? L.tiles : 1));
+    L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));

@@ -347,6 +347,19 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
 }
 
+// Strip and tile slot of a one-wave workgroup.  Each run of 32 workgroups
+// covers 8 tile slots x 4 strips, arranged so that the 4 strips of a tile
+// have the same workgroup index modulo 8: workgroups are handed to the 8 XCDs
+// in turn, so a tile's strips share one XCD's L2 for the tile's records.
+// Returns false for the padding workgroups past the last tile.
+__device__ __forceinline__ bool strip_of_block(int64_t ntiles, int &strip, int &tslot)
+{
+    const int j = (int)(blockIdx.x & 31u);
+    strip = j >> 3;
+    tslot = (int)(blockIdx.x >> 5) * 8 + (j & 7);
+    return tslot < ntiles;
+}
+
 // Forward, one wave per 64-pixel strip of a tile (a tile's strips are
 // independent workgroups: no workgroup barrier, and the strips of a long list
 // run on different compute units).  The list is read in chunks of 64 records,
@@ -363,13 +376,13 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const uint32_t *__restrict__ order,
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
-               int32_t *__restrict__ census_all, int64_t total_pixels)
+               int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles)
 {
     constexpr int TH = 256 / TW, SR = 64 / TW;   // tile rows, strip rows
     __shared__ RasterRec sbuf[64];
     __shared__ uint8_t sidx[64];
-    const int strip = (int)(blockIdx.x & 3u);
-    const int tslot = (int)(blockIdx.x >> 2);
+    int strip, tslot;
+    if (!strip_of_block(ntiles, strip, tslot)) return;
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -886,15 +899,18 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-               double *__restrict__ pose_part, int pose_only)
+               double *__restrict__ pose_part, int pose_only, int64_t ntiles)
 {
     constexpr int TH = 256 / TW, SR = 64 / TW;
     __shared__ RasterRec sbuf[64];
     __shared__ ChatRec schat[64];
     __shared__ float sred[kNg][64];
     __shared__ uint8_t slist[64];
-    const int strip = (int)(blockIdx.x & 3u);
-    const int tslot = (int)(blockIdx.x >> 2);
+    int strip, tslot;
+    if (!strip_of_block(ntiles, strip, tslot)) {
+        if (threadIdx.x == 6) pose_part[8 * (size_t)blockIdx.x + 6] = -1.0;   // no keyframe
+        return;
+    }
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -1080,8 +1096,19 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
-    hipLaunchKernelGGL(wave ? k_raster_fwd_w<TW> : L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>,
-                       dim3((unsigned)(wave ? 4 * L.tiles : L.tiles)), dim3(wave ? 64 : 256), 0, stream,
+    if (wave) {
+        hipLaunchKernelGGL(k_raster_fwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+                           reinterpret_cast<const FrameDesc *>(ws + L.desc),
+                           reinterpret_cast<const int32_t *>(ws + L.tile_frame),
+                           L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
+                           reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
+                           reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                           reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
+                           reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles);
+        return;
+    }
+    hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>,
+                       dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),
@@ -1094,11 +1121,22 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
-    hipLaunchKernelGGL(wave ? k_raster_bwd_w<TW> : k_raster_bwd<TW>, dim3((unsigned)(wave ? 4 * L.tiles : L.tiles)),
-                       dim3(wave ? 64 : 256), 0, stream,
+    const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
+    if (wave) {
+        hipLaunchKernelGGL(k_raster_bwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+                           reinterpret_cast<const FrameDesc *>(ws + L.desc),
+                           reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
+                           reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
+                           reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
+                           reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                           reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
+                           reinterpret_cast<int32_t *>(ws + L.census), L.pixels,
+                           reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles);
+        return;
+    }
+    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
-                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
-                       reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
+                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
                        reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),

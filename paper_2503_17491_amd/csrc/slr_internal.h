@@ -79,6 +79,10 @@ constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // items per block
 constexpr int kMaxDigitBits = 8;
 
+// Workgroups of the one-wave compositing forms: 4 strips per tile, tiles in
+// runs of 8 (see strip_of_block).
+inline int64_t wave_blocks(int64_t tiles) { return 32 * ((tiles + 7) / 8); }
+
 // Compositing variant and tile schedule used when the caller asks for the default.
 constexpr int kDefaultVariant = SLR_VARIANT_WAVE;
 constexpr int kDefaultSchedule = SLR_SCHEDULE_LONGEST;
