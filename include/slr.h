@@ -215,6 +215,23 @@ slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n
                               const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                               size_t workspace_bytes, const uint64_t **counters);
 
+/* Adam over the raw surfel parameters (the map refinement of Sec. 3.3.2
+ * optimises them with Adam), PyTorch's single-tensor form:
+ *   m <- m + (1 - beta1) (g - m),  v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - lr / (1 - beta1^step) * m / (sqrt(v) / sqrt(1 - beta2^step) + eps).
+ * Parameters (device, FP32, updated in place) are the surfel arrays of an
+ * slr_surfels set; grads the matching slr_surfel_grads; m and v (device, FP32,
+ * caller-owned, zero before the first step) are [n, 10] per surfel in the
+ * order means, quaternion, log-scales, logit.  step >= 1.  Errors: NULL or
+ * misaligned arrays, step < 1, non-finite or negative hyper-parameters. */
+typedef struct slr_adam_config {
+    float lr_means, lr_quats, lr_log_scales, lr_logits;
+    float beta1, beta2, eps;
+    int32_t step;
+} slr_adam_config;
+slr_status slr_adam_step(int64_t n, float *means, float *quats, float *log_scales, float *logits,
+                         const slr_surfel_grads *grads, float *m, float *v, const slr_adam_config *cfg, void *stream);
+
 /* Range and normal losses of Sec. 3.3.2 (Eqs. loss_range and loss_normal,
  * with rho_d = 1 and N(D) replaced by a given target normal), fused with
  * their gradients:

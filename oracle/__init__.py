@@ -4,3 +4,5 @@ Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` import this package.  The product path never does.
 """
 from .oracle import *  # noqa: F401,F403
+from .adam import adam_step  # noqa: F401
+from .loss import loss_l1_normal  # noqa: F401

@@ -56,7 +56,7 @@ class SurfelGrads(C.Structure):
 
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-           "slr_batch_counters", "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times",
+           "slr_batch_counters", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
            "slr_status_string", "slr_last_error"]
 
 _lib = None
@@ -337,6 +337,25 @@ def loss_l1_normal(D, N, Dt, Nt, w_d, w_n, gD, gN, loss=None):
     P = D.numel()
     _check(lib().slr_loss_l1_normal(P, _ptr(D), _ptr(N), _ptr(Dt), _ptr(Nt), float(w_d), float(w_n), _ptr(gD),
                                     _ptr(gN), _ptr(loss), _stream()), "slr_loss_l1_normal")
+
+
+class AdamConfig(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_quats", C.c_float), ("lr_log_scales", C.c_float),
+                ("lr_logits", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32)]
+
+
+def adam_step(params, grads, m, v, lr, step, betas=(0.9, 0.999), eps=1e-15):
+    """One fused Adam step on a surfel set in place.  params / grads: dicts of
+    means [n,3], quats [n,4], log_scales [n,2], logits [n]; m, v: [n,10] FP32
+    moments (zero before step 1); lr: dict with one rate per group."""
+    n = params["means"].shape[0]
+    g = SurfelGrads(_ptr(grads["means"]), _ptr(grads["quats"]), _ptr(grads["log_scales"]), _ptr(grads["logits"]))
+    cfg = AdamConfig(float(lr["means"]), float(lr["quats"]), float(lr["log_scales"]), float(lr["logits"]),
+                     float(betas[0]), float(betas[1]), float(eps), int(step))
+    _check(lib().slr_adam_step(C.c_int64(n), _ptr(params["means"]), _ptr(params["quats"]),
+                               _ptr(params["log_scales"]), _ptr(params["logits"]), C.byref(g), _ptr(m), _ptr(v),
+                               C.byref(cfg), _stream()), "slr_adam_step")
 
 
 def stage_timer(on):

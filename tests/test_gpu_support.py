@@ -1,0 +1,77 @@
+"""Support kernels through the C ABI against the oracle: the fused range +
+normal loss and the fused Adam step."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+LR = {"means": 1e-3, "quats": 1e-3, "log_scales": 5e-3, "logits": 5e-2}
+
+
+def say(*a):
+    print("[gpu-support]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def slr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_17491_amd import slr as S
+    S.lib()
+    return S
+
+
+@pytest.mark.parametrize("H,W", [(64, 512), (37, 300), (1, 1)])
+def test_loss_matches_oracle(slr, H, W):
+    say("loss", H, W)
+    g = np.random.default_rng(H * W)
+    P = H * W
+    D = g.uniform(0, 30, P).astype(np.float32)
+    Dt = (D + g.normal(0, 0.5, P)).astype(np.float32)
+    Dt[g.uniform(size=P) < 0.2] = 0.0
+    N = g.normal(size=(P, 3)).astype(np.float32)
+    Nt = g.normal(size=(P, 3)).astype(np.float32)
+    Dt[:3] = D[:3]    # exact ties: zero range gradient
+    wd, wn = 1.0 / max(P, 1), 0.5 / max(P, 1)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in dict(D=D, N=N, Dt=Dt, Nt=Nt).items()}
+    gD = torch.empty(P, device=DEV); gN = torch.empty(P, 3, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    slr.loss_l1_normal(t["D"], t["N"], t["Dt"], t["Nt"], wd, wn, gD, gN, loss)
+    torch.cuda.synchronize()
+    L, rD, rN = O.loss_l1_normal(D, N, Dt, Nt, wd, wn)
+    np.testing.assert_array_equal(gD.cpu().numpy(), rD)
+    np.testing.assert_array_equal(gN.cpu().numpy(), rN)
+    assert abs(loss.item() - L) <= 1e-6 * max(abs(L), 1e-30) + 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 1000, 70001])
+def test_adam_matches_oracle(slr, n):
+    say("adam", n)
+    g = np.random.default_rng(n)
+    p = {"means": g.normal(size=(n, 3)), "quats": g.normal(size=(n, 4)), "log_scales": g.normal(size=(n, 2)),
+         "logits": g.normal(size=n)}
+    p = {k: v.astype(np.float32) for k, v in p.items()}
+    dp = {k: torch.from_numpy(v.copy()).to(DEV) for k, v in p.items()}
+    m = torch.zeros(n, 10, device=DEV); v = torch.zeros(n, 10, device=DEV)
+    rm = np.zeros((n, 10)); rv = np.zeros((n, 10))
+    cur = {k: x.astype(np.float64) for k, x in p.items()}
+    for step in range(1, 4):
+        gr = {k: (g.normal(size=x.shape) * 10.0 ** g.uniform(-3, 1, size=x.shape)).astype(np.float32)
+              for k, x in p.items()}
+        slr.adam_step(dp, {k: torch.from_numpy(x).to(DEV) for k, x in gr.items()}, m, v, LR, step, eps=1e-15)
+        cur, rm, rv = O.adam_step(cur, gr, rm, rv, LR, step, eps=1e-15)
+    torch.cuda.synchronize()
+    for k in p:
+        got = dp[k].cpu().numpy().astype(np.float64)
+        # each step moves a parameter by at most ~lr: FP32 rounding of the
+        # parameter plus a relative 1e-5 of the accumulated steps
+        tol = 4 * np.finfo(np.float32).eps * np.abs(cur[k]) + 1e-5 * 3 * LR[k]
+        assert (np.abs(got - cur[k]) <= tol).all(), (k, float(np.abs(got - cur[k]).max()))
+    np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-5, atol=1e-30)
+    np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-5, atol=1e-30)
