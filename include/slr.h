@@ -225,8 +225,8 @@ slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n
  * order means, quaternion, log-scales, logit.  step >= 1.  Errors: NULL or
  * misaligned arrays, step < 1, non-finite or negative hyper-parameters. */
 typedef struct slr_adam_config {
-    float lr_means, lr_quats, lr_log_scales, lr_logits;
-    float beta1, beta2, eps;
+    double lr_means, lr_quats, lr_log_scales, lr_logits;
+    double beta1, beta2, eps;
     int32_t step;
 } slr_adam_config;
 slr_status slr_adam_step(int64_t n, float *means, float *quats, float *log_scales, float *logits,

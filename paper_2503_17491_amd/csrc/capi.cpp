@@ -619,10 +619,10 @@ slr_status slr_adam_step(int64_t n, float *means, float *quats, float *log_scale
     if (n < 0) return fail(SLR_E_INVALID, "negative surfel count");
     if (!cfg || !grads) return fail(SLR_E_INVALID, "config or gradients are NULL");
     if (cfg->step < 1) return fail(SLR_E_INVALID, "Adam step must be >= 1");
-    const float hp[7] = {cfg->lr_means, cfg->lr_quats, cfg->lr_log_scales, cfg->lr_logits, cfg->beta1, cfg->beta2, cfg->eps};
-    for (float x : hp)
-        if (!std::isfinite(x) || x < 0.0f) return fail(SLR_E_INVALID, "Adam hyper-parameters must be finite and >= 0");
-    if (cfg->beta1 >= 1.0f || cfg->beta2 >= 1.0f) return fail(SLR_E_INVALID, "Adam betas must be < 1");
+    const double hp[7] = {cfg->lr_means, cfg->lr_quats, cfg->lr_log_scales, cfg->lr_logits, cfg->beta1, cfg->beta2, cfg->eps};
+    for (double x : hp)
+        if (!std::isfinite(x) || x < 0.0) return fail(SLR_E_INVALID, "Adam hyper-parameters must be finite and >= 0");
+    if (cfg->beta1 >= 1.0 || cfg->beta2 >= 1.0) return fail(SLR_E_INVALID, "Adam betas must be < 1");
     if (n > 0) {
         if (!means || !quats || !log_scales || !logits || !m || !v || !grads->means || !grads->quats ||
             !grads->log_scales || !grads->logits)
@@ -630,13 +630,14 @@ slr_status slr_adam_step(int64_t n, float *means, float *quats, float *log_scale
         if (!aligned(quats, 16) || !aligned(grads->quats, 16))
             return fail(SLR_E_INVALID, "quaternion arrays must be 16-byte aligned");
     }
-    const double bc1 = 1.0 - std::pow((double)cfg->beta1, cfg->step);
-    const double bc2 = 1.0 - std::pow((double)cfg->beta2, cfg->step);
+    const double bc1 = 1.0 - std::pow(cfg->beta1, cfg->step);
+    const double bc2 = 1.0 - std::pow(cfg->beta2, cfg->step);
     const float s[4] = {(float)(cfg->lr_means / bc1), (float)(cfg->lr_quats / bc1), (float)(cfg->lr_log_scales / bc1),
                         (float)(cfg->lr_logits / bc1)};
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     slr::launch_adam(n, means, quats, log_scales, logits, grads->means, grads->quats, grads->log_scales, grads->logits,
-                     m, v, s, cfg->beta1, cfg->beta2, (float)std::sqrt(bc2), cfg->eps, st);
+                     m, v, s, (float)(1.0 - cfg->beta1), (float)cfg->beta2, (float)(1.0 - cfg->beta2),
+                     (float)std::sqrt(bc2), (float)cfg->eps, st);
     HIP_TRY(hipGetLastError());
     return SLR_OK;
 }

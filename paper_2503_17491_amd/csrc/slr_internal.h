@@ -126,7 +126,7 @@ void launch_loss_l1_normal(int64_t pixels, const float *depth, const float *norm
                            hipStream_t stream);
 void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream);
 void launch_adam(int64_t n, float *means, float *quats, float *ls, float *logits, const float *gm, const float *gq,
-                 const float *gl, const float *go, float *m, float *v, const float s[4], float b1, float b2, float c2,
-                 float eps, hipStream_t stream);
+                 const float *gl, const float *go, float *m, float *v, const float s[4], float omb1, float b2,
+                 float omb2, float c2, float eps, hipStream_t stream);
 
 }  // namespace slr

@@ -51,11 +51,12 @@ k_loss_l1_normal(int64_t P, const float *__restrict__ D, const float *__restrict
     }
 }
 
-__device__ __forceinline__ void adam1(float &p, float g, float &m, float &v, float s, float b1, float b2, float c2,
-                                      float eps)
+// omb1 = 1 - b1, omb2 = 1 - b2, both formed in FP64 on the host
+__device__ __forceinline__ void adam1(float &p, float g, float &m, float &v, float s, float omb1, float b2, float omb2,
+                                      float c2, float eps)
 {
-    m = fmaf(1.0f - b1, g - m, m);
-    v = b2 * v + (1.0f - b2) * (g * g);
+    m = fmaf(omb1, g - m, m);
+    v = b2 * v + omb2 * (g * g);
     p = p - s * (m / (sqrtf(v) / c2 + eps));
 }
 
@@ -63,7 +64,7 @@ __global__ void __launch_bounds__(256)
 k_adam(int64_t n, float *__restrict__ means, float *__restrict__ quats, float *__restrict__ ls,
        float *__restrict__ logits, const float *__restrict__ gm, const float *__restrict__ gq,
        const float *__restrict__ gl, const float *__restrict__ go, float *__restrict__ mom, float *__restrict__ vel,
-       float s_mean, float s_quat, float s_ls, float s_logit, float b1, float b2, float c2, float eps)
+       float s_mean, float s_quat, float s_ls, float s_logit, float omb1, float b2, float omb2, float c2, float eps)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -72,17 +73,17 @@ k_adam(int64_t n, float *__restrict__ means, float *__restrict__ quats, float *_
 #pragma unroll
     for (int c = 0; c < 10; ++c) { mm[c] = m[c]; vv[c] = v[c]; }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) adam1(means[3 * k + c], gm[3 * k + c], mm[c], vv[c], s_mean, b1, b2, c2, eps);
+    for (int c = 0; c < 3; ++c) adam1(means[3 * k + c], gm[3 * k + c], mm[c], vv[c], s_mean, omb1, b2, omb2, c2, eps);
     float4 q = *reinterpret_cast<float4 *>(quats + 4 * k);
     const float4 g4 = *reinterpret_cast<const float4 *>(gq + 4 * k);
-    adam1(q.x, g4.x, mm[3], vv[3], s_quat, b1, b2, c2, eps);
-    adam1(q.y, g4.y, mm[4], vv[4], s_quat, b1, b2, c2, eps);
-    adam1(q.z, g4.z, mm[5], vv[5], s_quat, b1, b2, c2, eps);
-    adam1(q.w, g4.w, mm[6], vv[6], s_quat, b1, b2, c2, eps);
+    adam1(q.x, g4.x, mm[3], vv[3], s_quat, omb1, b2, omb2, c2, eps);
+    adam1(q.y, g4.y, mm[4], vv[4], s_quat, omb1, b2, omb2, c2, eps);
+    adam1(q.z, g4.z, mm[5], vv[5], s_quat, omb1, b2, omb2, c2, eps);
+    adam1(q.w, g4.w, mm[6], vv[6], s_quat, omb1, b2, omb2, c2, eps);
     *reinterpret_cast<float4 *>(quats + 4 * k) = q;
-    adam1(ls[2 * k], gl[2 * k], mm[7], vv[7], s_ls, b1, b2, c2, eps);
-    adam1(ls[2 * k + 1], gl[2 * k + 1], mm[8], vv[8], s_ls, b1, b2, c2, eps);
-    adam1(logits[k], go[k], mm[9], vv[9], s_logit, b1, b2, c2, eps);
+    adam1(ls[2 * k], gl[2 * k], mm[7], vv[7], s_ls, omb1, b2, omb2, c2, eps);
+    adam1(ls[2 * k + 1], gl[2 * k + 1], mm[8], vv[8], s_ls, omb1, b2, omb2, c2, eps);
+    adam1(logits[k], go[k], mm[9], vv[9], s_logit, omb1, b2, omb2, c2, eps);
 #pragma unroll
     for (int c = 0; c < 10; ++c) { m[c] = mm[c]; v[c] = vv[c]; }
 }
@@ -90,12 +91,12 @@ k_adam(int64_t n, float *__restrict__ means, float *__restrict__ quats, float *_
 }  // namespace
 
 void launch_adam(int64_t n, float *means, float *quats, float *ls, float *logits, const float *gm, const float *gq,
-                 const float *gl, const float *go, float *m, float *v, const float s[4], float b1, float b2, float c2,
-                 float eps, hipStream_t stream)
+                 const float *gl, const float *go, float *m, float *v, const float s[4], float omb1, float b2,
+                 float omb2, float c2, float eps, hipStream_t stream)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, means, quats, ls, logits, gm,
-                       gq, gl, go, m, v, s[0], s[1], s[2], s[3], b1, b2, c2, eps);
+                       gq, gl, go, m, v, s[0], s[1], s[2], s[3], omb1, b2, omb2, c2, eps);
 }
 
 void launch_loss_l1_normal(int64_t P, const float *D, const float *N, const float *Dt, const float *Nt, float wd,

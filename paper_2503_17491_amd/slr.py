@@ -340,8 +340,8 @@ def loss_l1_normal(D, N, Dt, Nt, w_d, w_n, gD, gN, loss=None):
 
 
 class AdamConfig(C.Structure):
-    _fields_ = [("lr_means", C.c_float), ("lr_quats", C.c_float), ("lr_log_scales", C.c_float),
-                ("lr_logits", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+    _fields_ = [("lr_means", C.c_double), ("lr_quats", C.c_double), ("lr_log_scales", C.c_double),
+                ("lr_logits", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("step", C.c_int32)]
 
 
