@@ -61,9 +61,11 @@ def test_adam_matches_oracle(slr, n):
     m = torch.zeros(n, 10, device=DEV); v = torch.zeros(n, 10, device=DEV)
     rm = np.zeros((n, 10)); rv = np.zeros((n, 10))
     cur = {k: x.astype(np.float64) for k, x in p.items()}
+    gsum = np.zeros((n, 10))   # sum over steps of |g|: scale of the FP32 error of m
     for step in range(1, 4):
         gr = {k: (g.normal(size=x.shape) * 10.0 ** g.uniform(-3, 1, size=x.shape)).astype(np.float32)
               for k, x in p.items()}
+        gsum += np.abs(np.concatenate([gr[k].reshape(n, -1) for k in ("means", "quats", "log_scales", "logits")], 1))
         slr.adam_step(dp, {k: torch.from_numpy(x).to(DEV) for k, x in gr.items()}, m, v, LR, step, eps=1e-15)
         cur, rm, rv = O.adam_step(cur, gr, rm, rv, LR, step, eps=1e-15)
     torch.cuda.synchronize()
@@ -73,5 +75,8 @@ def test_adam_matches_oracle(slr, n):
         # parameter plus a relative 1e-5 of the accumulated steps
         tol = 4 * np.finfo(np.float32).eps * np.abs(cur[k]) + 1e-5 * 3 * LR[k]
         assert (np.abs(got - cur[k]) <= tol).all(), (k, float(np.abs(got - cur[k]).max()))
-    np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-5, atol=1e-30)
+    # m = m + (1 - b1)(g - m) may cancel: bound its error by FP32 rounding of the gradients it summed
+    dm = np.abs(m.cpu().numpy() - rm)
+    assert (dm <= 1e-5 * np.abs(rm) + 8 * np.finfo(np.float32).eps * gsum).all(), float(dm.max())
+    # v sums squares: no cancellation
     np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-5, atol=1e-30)
