@@ -151,7 +151,8 @@ def main():
     ap.add_argument("--form", choices=["batched", "plain"], default="batched",
                     help="form whose iter/s is reported as value (both are always timed)")
     ap.add_argument("--no-graph", action="store_true", help="batched form without HIP-graph capture")
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto",
+                    help="HxW tile shape, or auto: the autotuner picks shape, form and schedule (untimed)")
     ap.add_argument("--variant", choices=["default", "lds", "scalar", "wave"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
     ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
@@ -174,10 +175,12 @@ def main():
     from paper_2503_17491_amd import slr, synth, targets
     slr.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    th, tw = (int(x) for x in args.tile.split("x"))
     var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR,
            "wave": slr.VARIANT_WAVE}[args.variant]
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
+    th = tw = None
+    if args.tile != "auto":
+        th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -186,6 +189,17 @@ def main():
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
     sc, d, sensor, kfs = build_workload(torch, slr, synth, targets)
+    br = None
+    tune_ms = None
+    if th is None:
+        # the autotuner times every candidate tiling on this batch (outside the timed region)
+        br = make_batch(torch, slr, d, sensor, kfs, slr.TUNE_CANDIDATES[0])
+        for u in br.up:
+            for t in u:
+                t.fill_(1.0)
+        tune_ms = br.autotune()
+        th, tw, var, sch = br.tiling
+        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/v{c[2]}": round(v, 3) for c, v in tune_ms.items()})
     rend = [slr.Renderer(sensor, (th, tw, var, sch), capacity=4 << 20) for _ in kfs]
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
@@ -218,7 +232,8 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
-    br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch))
+    if br is None:
+        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch))
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -289,7 +304,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
-                   "form": args.form, "graph": graph is not None, "tile": args.tile, "variant": args.variant, "schedule": args.schedule, "keyframes": N_KF,
+                   "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
+                   "schedule": {0: "default", 1: "tile", 2: "longest"}[sch], "autotuned": tune_ms is not None,
+                   "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},

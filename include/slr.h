@@ -208,6 +208,22 @@ slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr
                               int32_t n_frames, const slr_frame *frames, const slr_tiling *tiling,
                               int64_t pair_capacity, void *workspace, size_t workspace_bytes, uint32_t flags,
                               void *stream);
+/* Tile autotuner (the tile shape, compositing form and schedule of a batch):
+ * for each of the n_candidates tilings, renders and back-propagates the batch
+ * once untimed and reps times timed (HIP events on stream; the call
+ * synchronises), and writes the median ms per candidate to ms (host,
+ * [n_candidates]; -1 for a candidate whose pairs overflowed pair_capacity) and
+ * the fastest candidate's index to *best (host).  The workspace must hold the
+ * largest candidate (slr_batch_workspace_size of each); outputs, upstream
+ * gradients and grads are used as in slr_batch_render / slr_batch_backward and
+ * are left holding the last candidate's results.  Errors: any invalid
+ * candidate (nothing is launched then), SLR_E_CAPACITY if every candidate
+ * overflowed. */
+slr_status slr_batch_autotune(int32_t n_sets, const slr_surfels *sets, const slr_surfel_grads *grads,
+                              int32_t n_frames, const slr_frame *frames, const slr_tiling *candidates,
+                              int32_t n_candidates, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                              int32_t reps, double *ms, int32_t *best, void *stream);
+
 /* Device address of three uint64 words in the workspace: the pair count K
  * of the last render, the overflow word (K when K > pair_capacity, else 0)
  * and the pair count actually binned. */

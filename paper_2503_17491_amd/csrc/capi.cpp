@@ -4,6 +4,7 @@
 // of one frame plus a host read-back of the pair count.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -577,6 +578,77 @@ slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *ws = reinterpret_cast<char *>(workspace);
     enqueue_backward(B, sets, grads, ws, pose_only, (flags & SLR_ACCUMULATE) != 0, s);
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_batch_autotune(int32_t n_sets, const slr_surfels *sets, const slr_surfel_grads *grads,
+                              int32_t n_frames, const slr_frame *frames, const slr_tiling *candidates,
+                              int32_t n_candidates, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                              int32_t reps, double *ms, int32_t *best, void *stream)
+{
+    if (!candidates || n_candidates < 1) return fail(SLR_E_INVALID, "no candidate tilings");
+    if (!ms || !best) return fail(SLR_E_INVALID, "ms and best must be host pointers");
+    if (reps < 1) return fail(SLR_E_INVALID, "reps must be >= 1");
+    // validate every candidate first: nothing is launched for an invalid set
+    std::vector<Batch> bs(n_candidates);
+    for (int32_t c = 0; c < n_candidates; ++c) {
+        slr_status st = check_batch(n_sets, sets, n_frames, frames, &candidates[c], pair_capacity, &bs[c]);
+        if (st != SLR_OK) return st;
+        if ((st = check_ws(bs[c].L, workspace, workspace_bytes)) != SLR_OK) return st;
+        if ((st = check_grads(n_sets, grads, false)) != SLR_OK) return st;
+        for (int32_t f = 0; f < n_frames; ++f)
+            if (!frames[f].depth || !frames[f].normal || !frames[f].alpha)
+                return fail(SLR_E_INVALID, "frame %d: output pointer is NULL", f);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SLR_E_HIP, "hipEventCreate failed");
+    }
+    slr_status res = SLR_OK;
+    double best_ms = 0.0;
+    *best = -1;
+    for (int32_t c = 0; c < n_candidates && res == SLR_OK; ++c) {
+        const Batch &B = bs[c];
+        if ((res = upload_tables(B, frames, ws, s)) != SLR_OK) break;
+        std::vector<FrameDesc> d = make_descs(B, sets, frames, &candidates[c], ws);
+        slr::launch_write_desc(d.data(), n_frames, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
+        slr::launch_tile_frame(B.L, ws, s);
+        // one untimed step, then the median of reps timed steps (render + backward)
+        std::vector<float> t;
+        for (int32_t r = -1; r < reps; ++r) {
+            if (r >= 0 && hipEventRecord(e0, s) != hipSuccess) { res = fail(SLR_E_HIP, "hipEventRecord failed"); break; }
+            enqueue_render_front(B, ws, s);
+            enqueue_render_back(B, ws, s);
+            enqueue_backward(B, sets, grads, ws, false, false, s);
+            if (r < 0) continue;
+            float x = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&x, e0, e1) != hipSuccess) {
+                res = fail(SLR_E_HIP, "timing failed");
+                break;
+            }
+            t.push_back(x);
+        }
+        if (res != SLR_OK) break;
+        // a candidate whose pairs overflowed the capacity did not render: not eligible
+        uint64_t over = 0;
+        if (hipMemcpy(&over, ws + B.L.misc + 8, sizeof(over), hipMemcpyDeviceToHost) != hipSuccess) {
+            res = fail(SLR_E_HIP, "hipMemcpy failed");
+            break;
+        }
+        std::sort(t.begin(), t.end());
+        ms[c] = over ? -1.0 : (double)t[t.size() / 2];
+        if (!over && (*best < 0 || ms[c] < best_ms)) { *best = c; best_ms = ms[c]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res != SLR_OK) return res;
+    if (*best < 0) return fail(SLR_E_CAPACITY, "every candidate overflowed the pair capacity");
     HIP_TRY(hipGetLastError());
     return SLR_OK;
 }

@@ -56,7 +56,7 @@ class SurfelGrads(C.Structure):
 
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-           "slr_batch_counters", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
+           "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
            "slr_status_string", "slr_last_error"]
 
 _lib = None
@@ -251,6 +251,13 @@ class Renderer:
                     tiles_y=int(v.tiles_y), K=K)
 
 
+# Candidate tilings of the autotuner: (tile_h, tile_w, variant, schedule).
+TUNE_CANDIDATES = [(16, 16, VARIANT_WAVE, SCHEDULE_LONGEST), (8, 32, VARIANT_WAVE, SCHEDULE_LONGEST),
+                   (32, 8, VARIANT_WAVE, SCHEDULE_LONGEST), (4, 64, VARIANT_WAVE, SCHEDULE_LONGEST),
+                   (16, 16, VARIANT_LDS, SCHEDULE_LONGEST), (32, 8, VARIANT_LDS, SCHEDULE_LONGEST)]
+_tuned = {}   # image-size class -> tiling chosen by the autotuner
+
+
 class BatchRenderer:
     """Batched form: many frames (each its own pose, sensor and image size;
     frames may share a surfel set) rendered and differentiated by one set of
@@ -263,9 +270,14 @@ class BatchRenderer:
     """
 
     def __init__(self, sets, frames, tiling=(16, 16), capacity=1 << 22, device="cuda"):
+        """tiling: (tile_h, tile_w[, variant[, schedule]]) or "auto" (the
+        autotuner's choice for this image-size class, tuned on first use)."""
         self.sets = sets
         self.frames = frames
-        self.tiling = tuple(tiling)
+        self._key = (tuple((int(f["sensor"]["height"]), int(f["sensor"]["width"])) for f in frames),
+                     tuple(int(st["means"].shape[0]) for st in sets))
+        auto = isinstance(tiling, str) and tiling == "auto"
+        self.tiling = _tuned.get(self._key, TUNE_CANDIDATES[0]) if auto else tuple(tiling)
         self.capacity = int(capacity)
         self.device = device
         self.out, self.up, self.dpose = [], [], []
@@ -291,6 +303,33 @@ class BatchRenderer:
             for f, o, u, dp in zip(frames, self.out, self.up, self.dpose)])
         self.ws = None
         self.prepare()
+        if auto and self._key not in _tuned:
+            self.autotune()
+
+    def autotune(self, candidates=None, reps=3):
+        """Time render + backward of this batch for each candidate tiling (median
+        of reps, after one untimed step) and keep the fastest.  Returns
+        {tiling: ms} (-1 where the pairs overflowed the capacity)."""
+        cands = [tuple(c) + (0,) * (4 - len(c)) for c in (candidates or TUNE_CANDIDATES)]
+        arr = (Tiling * len(cands))(*[Tiling(*c) for c in cands])
+        need = 0
+        for c in cands:
+            b = C.c_size_t(0)
+            t = Tiling(*c)
+            _check(lib().slr_batch_workspace_size(len(self.sets), self._c_sets, len(self.frames), self._c_frames,
+                                                  C.byref(t), self.capacity, C.byref(b)), "slr_batch_workspace_size")
+            need = max(need, b.value)
+        if self.ws.numel() < need:
+            self.ws = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+        ms = (C.c_double * len(cands))()
+        best = C.c_int32(-1)
+        _check(lib().slr_batch_autotune(len(self.sets), self._c_sets, self._c_grads, len(self.frames), self._c_frames,
+                                        arr, len(cands), self.capacity, _ptr(self.ws), self.ws.numel(), int(reps), ms,
+                                        C.byref(best), _stream()), "slr_batch_autotune")
+        self.tiling = cands[best.value]
+        _tuned[self._key] = self.tiling
+        self.prepare()
+        return {c: ms[k] for k, c in enumerate(cands)}
 
     def _args(self):
         t = Tiling(*self.tiling)
