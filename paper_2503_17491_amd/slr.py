@@ -81,7 +81,9 @@ def lib():
         L.slr_batch_render.argtypes = BATCH + [P]
         L.slr_batch_backward.argtypes = [I32, P, P, I32, P, P, I64, P, C.c_size_t, C.c_uint32, P]
         L.slr_batch_counters.argtypes = BATCH + [P]
+        L.slr_batch_autotune.argtypes = [I32, P, P, I32, P, P, I32, I64, P, C.c_size_t, I32, P, P, P]
         L.slr_loss_l1_normal.argtypes = [I64, P, P, P, P, C.c_float, C.c_float, P, P, P, P]
+        L.slr_adam_step.argtypes = [I64, P, P, P, P, P, P, P, P, P]
         L.slr_stage_timer_enable.argtypes = [I32]
         L.slr_stage_times.argtypes = [P, P]
         L.slr_status_string.argtypes = [I32]
@@ -89,7 +91,8 @@ def lib():
         L.slr_last_error.restype = C.c_char_p
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-                  "slr_batch_counters", "slr_loss_l1_normal", "slr_stage_timer_enable", "slr_stage_times"):
+                  "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
+                  "slr_stage_timer_enable", "slr_stage_times"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -392,7 +395,7 @@ def adam_step(params, grads, m, v, lr, step, betas=(0.9, 0.999), eps=1e-15):
     g = SurfelGrads(_ptr(grads["means"]), _ptr(grads["quats"]), _ptr(grads["log_scales"]), _ptr(grads["logits"]))
     cfg = AdamConfig(float(lr["means"]), float(lr["quats"]), float(lr["log_scales"]), float(lr["logits"]),
                      float(betas[0]), float(betas[1]), float(eps), int(step))
-    _check(lib().slr_adam_step(C.c_int64(n), _ptr(params["means"]), _ptr(params["quats"]),
+    _check(lib().slr_adam_step(n, _ptr(params["means"]), _ptr(params["quats"]),
                                _ptr(params["log_scales"]), _ptr(params["logits"]), C.byref(g), _ptr(m), _ptr(v),
                                C.byref(cfg), _stream()), "slr_adam_step")
 

@@ -167,3 +167,24 @@ def test_graph_capture_replays_match_eager(slr):
             assert d <= 1e-4 * ref_g[k].abs().max().item(), (rep, k)
         for p, r in zip(br.dpose, ref_p):
             np.testing.assert_allclose(p.cpu().numpy(), r.cpu().numpy(), rtol=1e-6, atol=1e-9)
+
+
+def test_autotune_picks_a_candidate(slr):
+    say("autotune")
+    sets, frames, _, br = make_batch(slr, (16, 16))
+    upstream(br, 3)
+    cands = [(16, 16, 3, 2), (8, 32, 3, 2), (16, 16, 1, 2)]
+    ms = br.autotune(cands, reps=2)
+    assert set(ms) == set(cands) and all(v > 0 for v in ms.values())
+    assert br.tiling == min(ms, key=ms.get)
+    br.render()
+    torch.cuda.synchronize()
+    ref = slr.BatchRenderer(sets, frames, br.tiling, 4 << 20)
+    ref.render()
+    torch.cuda.synchronize()
+    for a, b in zip(br.out, ref.out):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    # an invalid candidate is refused before anything runs
+    with pytest.raises(slr.SlrError):
+        br.autotune([(16, 16, 3, 2), (12, 12, 3, 2)])
