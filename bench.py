@@ -179,6 +179,7 @@ def main():
            "wave": slr.VARIANT_WAVE}[args.variant]
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     th = tw = None
+    bvar = 0
     if args.tile != "auto":
         th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:
@@ -198,9 +199,9 @@ def main():
             for t in u:
                 t.fill_(1.0)
         tune_ms = br.autotune()
-        th, tw, var, sch = br.tiling
-        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/v{c[2]}": round(v, 3) for c, v in tune_ms.items()})
-    rend = [slr.Renderer(sensor, (th, tw, var, sch), capacity=4 << 20) for _ in kfs]
+        th, tw, var, sch, bvar = br.tiling
+        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}": round(v, 3) for c, v in tune_ms.items()})
+    rend = [slr.Renderer(sensor, (th, tw, var, sch, bvar), capacity=4 << 20) for _ in kfs]
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
@@ -233,7 +234,7 @@ def main():
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
     if br is None:
-        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch))
+        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch, bvar))
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -305,7 +306,8 @@ def main():
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
-                   "schedule": {0: "default", 1: "tile", 2: "longest"}[sch], "autotuned": tune_ms is not None,
+                   "schedule": {0: "default", 1: "tile", 2: "longest"}[sch],
+                   "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar], "autotuned": tune_ms is not None,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,

@@ -73,12 +73,16 @@ typedef struct slr_sensor {
  * one per lane and shared through LDS (no workgroup barrier).
  * schedule selects the order in which the compositing kernels take tiles:
  * 0 = library default, 1 = tile-id order, 2 = longest surfel list first
- * (computed on the device after binning).  Every variant and schedule
- * produces bit-identical forward outputs. */
+ * (computed on the device after binning).  bwd_variant selects the form of
+ * the compositing backward: 0 = the same as variant (the library default if
+ * that is 0), 1 = one workgroup per tile (records staged through LDS, one
+ * flush per tile and record), 3 = one wave per 64-pixel strip.  Every variant
+ * and schedule produces bit-identical forward outputs. */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
     int32_t variant;
     int32_t schedule;
+    int32_t bwd_variant;
 } slr_tiling;
 #define SLR_VARIANT_DEFAULT 0
 #define SLR_VARIANT_LDS 1

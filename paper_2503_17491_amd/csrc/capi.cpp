@@ -83,6 +83,8 @@ slr_status check_tiling(const slr_tiling *t)
     if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
     if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
+    if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE)
+        return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
     return SLR_OK;
@@ -201,6 +203,9 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
     if (items >= (int64_t(1) << 31)) return fail(SLR_E_INVALID, "batch has %lld records, limit 2^31", (long long)items);
     b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w);
     b->L.variant = tiling->variant == SLR_VARIANT_DEFAULT ? slr::kDefaultVariant : tiling->variant;
+    // the backward form: as asked, else the forward's (the scalar-cache forward pairs with the workgroup backward)
+    b->L.bwd_variant = tiling->bwd_variant != SLR_VARIANT_DEFAULT ? tiling->bwd_variant
+                       : (b->L.variant == SLR_VARIANT_WAVE ? SLR_VARIANT_WAVE : SLR_VARIANT_LDS);
     b->L.schedule = tiling->schedule == SLR_SCHEDULE_DEFAULT ? slr::kDefaultSchedule : tiling->schedule;
     if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");
     return SLR_OK;

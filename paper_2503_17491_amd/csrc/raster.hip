@@ -1120,7 +1120,7 @@ template <int TW>
 void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    const bool wave = L.variant == SLR_VARIANT_WAVE;
+    const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (wave) {
         hipLaunchKernelGGL(k_raster_bwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,

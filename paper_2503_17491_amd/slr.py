@@ -26,7 +26,8 @@ class Sensor(C.Structure):
 
 
 class Tiling(C.Structure):
-    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32)]
+    _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32),
+                ("bwd_variant", C.c_int32)]
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
@@ -254,10 +255,10 @@ class Renderer:
                     tiles_y=int(v.tiles_y), K=K)
 
 
-# Candidate tilings of the autotuner: (tile_h, tile_w, variant, schedule).
-TUNE_CANDIDATES = [(16, 16, VARIANT_WAVE, SCHEDULE_LONGEST), (8, 32, VARIANT_WAVE, SCHEDULE_LONGEST),
-                   (32, 8, VARIANT_WAVE, SCHEDULE_LONGEST), (4, 64, VARIANT_WAVE, SCHEDULE_LONGEST),
-                   (16, 16, VARIANT_LDS, SCHEDULE_LONGEST), (32, 8, VARIANT_LDS, SCHEDULE_LONGEST)]
+# Candidate tilings of the autotuner: (tile_h, tile_w, forward variant,
+# schedule, backward variant).
+TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((16, 16), (8, 32), (32, 8))
+                   for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
 
 
@@ -313,7 +314,7 @@ class BatchRenderer:
         """Time render + backward of this batch for each candidate tiling (median
         of reps, after one untimed step) and keep the fastest.  Returns
         {tiling: ms} (-1 where the pairs overflowed the capacity)."""
-        cands = [tuple(c) + (0,) * (4 - len(c)) for c in (candidates or TUNE_CANDIDATES)]
+        cands = [tuple(c) + (0,) * (5 - len(c)) for c in (candidates or TUNE_CANDIDATES)]
         arr = (Tiling * len(cands))(*[Tiling(*c) for c in cands])
         need = 0
         for c in cands:

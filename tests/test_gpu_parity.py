@@ -268,8 +268,10 @@ def test_backward_parity_fullsize_sparse(slr):
     pix = np.unique(np.stack([g.integers(0, 128, 500), g.integers(0, 1024, 500)], 1).astype(np.int32), axis=0)
     pix = clean_pixels(sc, np.eye(4), sensor, pix)
     P = pix.shape[0]
+    # one-wave forward with the workgroup backward, 32x8 tiles
     check_backward(slr, sc, np.eye(4), sensor, pix, g.normal(size=P).astype(np.float32),
-                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (16, 16), 1 << 20)
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (32, 8, 3, 2, 1),
+                   1 << 20)
 
 
 def test_backward_repeatable(slr):
