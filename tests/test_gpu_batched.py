@@ -173,7 +173,7 @@ def test_autotune_picks_a_candidate(slr):
     say("autotune")
     sets, frames, _, br = make_batch(slr, (16, 16))
     upstream(br, 3)
-    cands = [(16, 16, 3, 2), (8, 32, 3, 2), (16, 16, 1, 2)]
+    cands = [(16, 16, 3, 2, 3), (8, 32, 3, 2, 1), (16, 16, 1, 2, 1)]
     ms = br.autotune(cands, reps=2)
     assert set(ms) == set(cands) and all(v > 0 for v in ms.values())
     assert br.tiling == min(ms, key=ms.get)
@@ -187,4 +187,4 @@ def test_autotune_picks_a_candidate(slr):
             assert torch.equal(x, y)
     # an invalid candidate is refused before anything runs
     with pytest.raises(slr.SlrError):
-        br.autotune([(16, 16, 3, 2), (12, 12, 3, 2)])
+        br.autotune([(16, 16, 3, 2, 3), (12, 12, 3, 2, 3)])
