@@ -155,6 +155,8 @@ def main():
                     help="HxW tile shape, or auto: the autotuner picks shape, form and schedule (untimed)")
     ap.add_argument("--variant", choices=["default", "lds", "scalar", "wave"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
+    ap.add_argument("--bwd-variant", choices=["default", "lds", "wave"], default="default",
+                    help="backward compositing kernel: one workgroup per tile, or one wave per strip")
     ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
                     help="order in which the compositing kernels take tiles")
     ap.add_argument("--only", choices=["both", "batched"], default="both",
@@ -179,7 +181,7 @@ def main():
            "wave": slr.VARIANT_WAVE}[args.variant]
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     th = tw = None
-    bvar = 0
+    bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
     if args.tile != "auto":
         th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:

@@ -93,7 +93,9 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                 uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
-                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks)
+                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks,
+                const int32_t *__restrict__ cnt_in, const PixBox *__restrict__ box_in, uint32_t *__restrict__ cnt_out,
+                PixBox *__restrict__ box_out)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
     __shared__ uint32_t s_base[256];
@@ -154,14 +156,18 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
             uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
             kout[pos] = key[i];
             vout[pos] = val[i];
+            // optionally the record's tile count and box follow it into sorted order
+            if (cnt_out) {
+                cnt_out[pos] = (uint32_t)cnt_in[val[i]];
+                box_out[pos] = box_in[val[i]];
+            }
         }
     }
 }
 
 // ---- scan of tile counts in range order ----
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_reduce(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
-              uint32_t *__restrict__ blocksum)
+k_scan_reduce(const uint32_t *__restrict__ rcounts, int64_t n, uint32_t *__restrict__ blocksum)
 {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -169,7 +175,7 @@ k_scan_reduce(const int32_t *__restrict__ counts, const uint32_t *__restrict__ o
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) acc += (uint32_t)counts[order[idx]];
+        if (idx < n) acc += rcounts[idx];
     }
     uint32_t tot;
     block_exscan(acc, s_wave, &tot);
@@ -193,8 +199,8 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ order, int64_t n,
-             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
+k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n, const uint32_t *__restrict__ blocksum,
+             uint32_t *__restrict__ offsets)
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_items[kSortTile];
@@ -202,7 +208,7 @@ k_scan_apply(const int32_t *__restrict__ counts, const uint32_t *__restrict__ or
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        s_items[i * kSortThreads + threadIdx.x] = idx < n ? (uint32_t)counts[order[idx]] : 0u;
+        s_items[i * kSortThreads + threadIdx.x] = idx < n ? rcounts[idx] : 0u;
     }
     __syncthreads();
     // each thread scans a contiguous run of kSortItems
@@ -236,14 +242,14 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
 // One thread per record in range order: write its global tile indices and its index.
 __global__ void __launch_bounds__(256)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-       const int32_t *__restrict__ counts, const PixBox *__restrict__ box, int64_t n, const uint64_t *__restrict__ keff,
+       const uint32_t *__restrict__ rcounts, const PixBox *__restrict__ rbox, int64_t n, const uint64_t *__restrict__ keff,
        uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || *keff == 0) return;
-    uint32_t id = order[r];
-    if (counts[id] == 0) return;
-    PixBox b = box[id];
+    if (rcounts[r] == 0) return;
+    const uint32_t id = order[r];
+    PixBox b = rbox[r];
     const FrameDesc &fd = descs[b.frame];
     const int th = fd.th, tw = fd.tw, tiles_x = fd.tiles_x, toff = fd.tile_off;
     uint32_t o = offsets[r];
@@ -318,14 +324,16 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 // One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
 // n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream)
+                const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream,
+                const int32_t *cnt_in = nullptr, const PixBox *box_in = nullptr, uint32_t *cnt_out = nullptr,
+                PixBox *box_out = nullptr)
 {
     int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
                        nblocks);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
-                       shift, bits, hist, totals, nblocks);
+                       shift, bits, hist, totals, nblocks, cnt_in, box_in, cnt_out, box_out);
 }
 
 }  // namespace
@@ -349,8 +357,12 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
         const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
+        const bool last = p == L.depth_passes - 1;
         radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
-                   stream);
+                   stream, last ? reinterpret_cast<const int32_t *>(ws + L.cnt) : nullptr,
+                   last ? reinterpret_cast<const PixBox *>(ws + L.box) : nullptr,
+                   last ? reinterpret_cast<uint32_t *>(ws + L.rcnt) : nullptr,
+                   last ? reinterpret_cast<PixBox *>(ws + L.rbox) : nullptr);
     }
 }
 
@@ -361,13 +373,12 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
         launch_fill_u32(misc, 0u, 6, stream);
         return;
     }
-    const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
-    const int32_t *counts = reinterpret_cast<const int32_t *>(ws + L.cnt);
+    const uint32_t *rcounts = reinterpret_cast<const uint32_t *>(ws + L.rcnt);   // in range order
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
     int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, bs);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, counts, order, L.items, bs,
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, bs,
                        reinterpret_cast<uint32_t *>(ws + L.off));
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
@@ -393,8 +404,8 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
-                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const int32_t *>(ws + L.cnt),
-                       reinterpret_cast<const PixBox *>(ws + L.box), L.items, keff, t0, v0);
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
+                       reinterpret_cast<const PixBox *>(ws + L.rbox), L.items, keff, t0, v0);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)

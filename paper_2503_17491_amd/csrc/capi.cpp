@@ -379,6 +379,9 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
+    // tile counts and boxes of the records in range order (written by the range sort's last pass)
+    L.rcnt = take(4 * nn);
+    L.rbox = take(sizeof(PixBox) * nn);
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
     L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
     L.ranges = take(8 * (size_t)L.tiles);

@@ -97,7 +97,7 @@ struct Layout {
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
