@@ -65,7 +65,8 @@ typedef struct slr_sensor {
 } slr_sensor;
 
 /* Tile shape of the binning (Sec. 3.2.1 uses 16x16).  tile_h * tile_w must be
- * 256; supported shapes: 16x16, 8x32, 32x8, 4x64.  variant selects how the
+ * 256; supported shapes: 16x16, 8x32, 32x8, 4x64; a frame may have at most
+ * 65535 tiles.  variant selects how the
  * forward compositing kernel reads a tile's surfel records: 0 = library
  * default, 1 = staged through LDS in batches by the whole workgroup, 2 = each
  * wave reads them through the scalar cache (no LDS, no workgroup barrier),

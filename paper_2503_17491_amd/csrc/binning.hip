@@ -94,8 +94,7 @@ __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                 uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals, int nblocks,
-                const int32_t *__restrict__ cnt_in, const PixBox *__restrict__ box_in, uint32_t *__restrict__ cnt_out,
-                PixBox *__restrict__ box_out)
+                const PixBox *__restrict__ box_in, uint32_t *__restrict__ cnt_out, PixBox *__restrict__ box_out)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
     __shared__ uint32_t s_base[256];
@@ -156,10 +155,11 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
             uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
             kout[pos] = key[i];
             vout[pos] = val[i];
-            // optionally the record's tile count and box follow it into sorted order
-            if (cnt_out) {
-                cnt_out[pos] = (uint32_t)cnt_in[val[i]];
-                box_out[pos] = box_in[val[i]];
+            // optionally the record's box (with its tile count) follows it into sorted order
+            if (box_out) {
+                const PixBox b = box_in[val[i]];
+                box_out[pos] = b;
+                cnt_out[pos] = b.cnt;
             }
         }
     }
@@ -325,15 +325,14 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 // n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream,
-                const int32_t *cnt_in = nullptr, const PixBox *box_in = nullptr, uint32_t *cnt_out = nullptr,
-                PixBox *box_out = nullptr)
+                const PixBox *box_in = nullptr, uint32_t *cnt_out = nullptr, PixBox *box_out = nullptr)
 {
     int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
                        nblocks);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
-                       shift, bits, hist, totals, nblocks, cnt_in, box_in, cnt_out, box_out);
+                       shift, bits, hist, totals, nblocks, box_in, cnt_out, box_out);
 }
 
 }  // namespace
@@ -359,8 +358,7 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
         const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
         const bool last = p == L.depth_passes - 1;
         radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
-                   stream, last ? reinterpret_cast<const int32_t *>(ws + L.cnt) : nullptr,
-                   last ? reinterpret_cast<const PixBox *>(ws + L.box) : nullptr,
+                   stream, last ? reinterpret_cast<const PixBox *>(ws + L.box) : nullptr,
                    last ? reinterpret_cast<uint32_t *>(ws + L.rcnt) : nullptr,
                    last ? reinterpret_cast<PixBox *>(ws + L.rbox) : nullptr);
     }

@@ -196,6 +196,9 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
         if ((st = check_sensor(&fr.sensor)) != SLR_OK) return st;
         if (!fr.pose_cw || !aligned(fr.pose_cw, 8))
             return fail(SLR_E_INVALID, "frame %d: pose must be a non-NULL, 8-byte aligned device pointer", f);
+        const int64_t ftiles = (int64_t)((fr.sensor.height + tiling->tile_h - 1) / tiling->tile_h) *
+                               ((fr.sensor.width + tiling->tile_w - 1) / tiling->tile_w);
+        if (ftiles > 65535) return fail(SLR_E_INVALID, "frame %d has %lld tiles, limit 65535", f, (long long)ftiles);
         b->geom[f] = FrameGeom{fr.sensor.height, fr.sensor.width, fr.set};
         items += sets[fr.set].n;
         if (sets[fr.set].n > b->max_n) b->max_n = sets[fr.set].n;

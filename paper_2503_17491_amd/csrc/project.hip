@@ -291,6 +291,7 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
         pb.c2 = (int16_t)(bx.nint == 2 ? bx.c[2] : -1); pb.c3 = (int16_t)(bx.nint == 2 ? bx.c[3] : -1);
     }
     counts[it] = cnt;
+    pb.cnt = (uint16_t)cnt;
     box[it] = pb;
     if (cnt == 0) {
         keys[it] = 0xFFFFFFFFu;

@@ -48,9 +48,10 @@ struct ChatRec {
 };
 
 // Pixel box: rows [r0, r1], columns [c0, c1] and optionally [c2, c3]; frame
-// index of the record.
+// index of the record and its tile count (a frame has at most 65535 tiles).
 struct __align__(16) PixBox {
-    int16_t r0, r1, c0, c1, c2, c3, frame, pad;
+    int16_t r0, r1, c0, c1, c2, c3, frame;
+    uint16_t cnt;
 };
 
 // Per-frame descriptor (device memory).
