@@ -97,9 +97,10 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
                 const PixBox *__restrict__ box_in, uint32_t *__restrict__ cnt_out, PixBox *__restrict__ box_out)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
-    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_base[256], s_start[256], s_gbase[256];
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_key[kSortTile], s_val[kSortTile];
     const int nb = 1 << bits;
     const uint32_t mask = (uint32_t)nb - 1u;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -136,31 +137,52 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit: exclusive prefix over the waves of this block
-    for (int d = threadIdx.x; d < nb; d += kSortThreads) {
+    // per digit (one per thread): the waves' offsets within the block's group of
+    // that digit, the group's size, then the groups' starts in the block
+    uint32_t dcount = 0;
+    if ((int)threadIdx.x < nb) {
         uint32_t off = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
-            uint32_t c = s_cnt[w][d];
-            s_cnt[w][d] = off;
+            const uint32_t c = s_cnt[w][threadIdx.x];
+            s_cnt[w][threadIdx.x] = off;
             off += c;
+        }
+        dcount = off;
+    }
+    uint32_t tot;
+    const uint32_t dstart = block_exscan(dcount, s_wave, &tot);
+    if ((int)threadIdx.x < nb) {
+        s_start[threadIdx.x] = dstart;
+        s_gbase[threadIdx.x] = s_base[threadIdx.x] + hist[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    }
+    __syncthreads();
+    // the block's items in LDS in digit order (stable: wave, then item order)
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)i * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (key[i] >> shift) & mask;
+            const uint32_t lp = s_start[d] + s_cnt[wid][d] + rank[i];
+            s_key[lp] = key[i];
+            s_val[lp] = val[i];
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        int64_t idx = base + (int64_t)i * 64 + lane;
-        if (idx < n) {
-            uint32_t d = (key[i] >> shift) & mask;
-            uint32_t pos = s_base[d] + hist[(int64_t)d * nblocks + blockIdx.x] + s_cnt[wid][d] + rank[i];
-            kout[pos] = key[i];
-            vout[pos] = val[i];
-            // optionally the record's box (with its tile count) follows it into sorted order
-            if (box_out) {
-                const PixBox b = box_in[val[i]];
-                box_out[pos] = b;
-                cnt_out[pos] = b.cnt;
-            }
+    // each digit's run goes out to consecutive addresses from consecutive threads
+    const int64_t b0 = (int64_t)blockIdx.x * kSortTile;
+    const int nvalid = (int)min((int64_t)kSortTile, n - b0);
+    for (int j = threadIdx.x; j < nvalid; j += kSortThreads) {
+        const uint32_t k = s_key[j], v = s_val[j];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = s_gbase[d] + ((uint32_t)j - s_start[d]);
+        kout[pos] = k;
+        vout[pos] = v;
+        // optionally the record's box (with its tile count) follows it into sorted order
+        if (box_out) {
+            const PixBox bx = box_in[v];
+            box_out[pos] = bx;
+            cnt_out[pos] = bx.cnt;
         }
     }
 }
