@@ -155,7 +155,7 @@ def main():
                     help="HxW tile shape, or auto: the autotuner picks shape, form and schedule (untimed)")
     ap.add_argument("--variant", choices=["default", "lds", "scalar", "wave"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
-    ap.add_argument("--bwd-variant", choices=["default", "lds", "wave", "tile"], default="default",
+    ap.add_argument("--bwd-variant", choices=["default", "lds", "wave"], default="default",
                     help="backward compositing kernel: one workgroup per tile, or one wave per strip")
     ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
                     help="order in which the compositing kernels take tiles")
@@ -181,7 +181,7 @@ def main():
            "wave": slr.VARIANT_WAVE}[args.variant]
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     th = tw = None
-    bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE, "tile": slr.VARIANT_WAVE_TILE}[args.bwd_variant]
+    bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
     if args.tile != "auto":
         th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:
@@ -309,7 +309,7 @@ def main():
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
                    "schedule": {0: "default", 1: "tile", 2: "longest"}[sch],
-                   "bwd_variant": {0: "default", 1: "lds", 3: "wave", 4: "tile"}[bvar], "autotuned": tune_ms is not None,
+                   "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar], "autotuned": tune_ms is not None,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,

@@ -77,9 +77,7 @@ typedef struct slr_sensor {
  * (computed on the device after binning).  bwd_variant selects the form of
  * the compositing backward: 0 = the same as variant (the library default if
  * that is 0), 1 = one workgroup per tile (records staged through LDS, one
- * flush per tile and record), 3 = one wave per 64-pixel strip, 4 = one
- * workgroup per tile whose four waves work their strips independently and
- * share the tile's records and flushes.  Every variant
+ * flush per tile and record), 3 = one wave per 64-pixel strip.  Every variant
  * and schedule produces bit-identical forward outputs. */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
@@ -91,7 +89,6 @@ typedef struct slr_tiling {
 #define SLR_VARIANT_LDS 1
 #define SLR_VARIANT_SCALAR 2
 #define SLR_VARIANT_WAVE 3
-#define SLR_VARIANT_WAVE_TILE 4 /* backward only */
 #define SLR_SCHEDULE_DEFAULT 0
 #define SLR_SCHEDULE_TILE 1
 #define SLR_SCHEDULE_LONGEST 2

@@ -83,9 +83,8 @@ slr_status check_tiling(const slr_tiling *t)
     if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
     if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
-    if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE &&
-        t->bwd_variant != SLR_VARIANT_WAVE_TILE)
-        return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1, 3 or 4)", t->bwd_variant);
+    if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE)
+        return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
     return SLR_OK;

@@ -1091,229 +1091,6 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     if (lane == 6) pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
 }
 
-// Backward, one workgroup per tile whose four waves each work their own strip
-// as k_raster_bwd_w does (own compaction, own few-pixels mode), but share the
-// tile's records: wave 0 stages each chunk of 64 records in LDS with the
-// next chunk's loads in flight, the waves write their per-record sums to rows
-// of their own, and after the chunk the records are flushed once per tile
-// (the rows added in wave order) by threads spread over the four waves.
-template <int TW>
-__global__ void __launch_bounds__(256, 3)  // 3 waves per SIMD: at most 168 VGPRs
-k_raster_bwd_t(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
-               const uint32_t *__restrict__ order,
-               const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame,
-               const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
-               const double2 *__restrict__ tables, const float *__restrict__ stT_all,
-               const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-               double *__restrict__ pose_part, int pose_only)
-{
-    constexpr int TH = 256 / TW, SR = 64 / TW;
-    __shared__ RasterRec sbuf[64];
-    __shared__ ChatRec schat[64];
-    __shared__ uint32_t sid[64];
-    __shared__ float sred[4][kNg][64];
-    __shared__ uint8_t slist[4][64];
-    __shared__ uint64_t smask[4];
-    __shared__ int s_tlast;
-    __shared__ double s_pose[4][6];
-    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    const FrameDesc &fd = descs[tile_frame[tile]];
-    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
-    const float near_m = (float)fd.near_m;
-    const double2 *col = tables + fd.tab_off, *rowc = col + W;
-    const float *stT = stT_all + fd.pix_off;
-    const int32_t *stN = stN_all + fd.pix_off;
-    int32_t *census = census_all + fd.pix_off;
-    const int ltile = tile - fd.tile_off;
-    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;   // wave = strip
-    const int i = ty * TH + wid * SR + lane / TW, j = tx * TW + lane % TW;
-    const bool inside = (i < H) && (j < W);
-    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
-    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
-    const int2 rg = ranges[tile];
-    const int wr0 = ty * TH + wid * SR, wr1 = wr0 + SR - 1;
-    const int red_val = bitrev6(lane);
-    const int p = inside ? i * W + j : 0;
-    const int last = inside ? stN[p] : 0;
-    const float T0 = inside ? stT[p] : 1.0f;
-    BwdUpstream up;
-    up.gd = (inside && fd.gD) ? fd.gD[p] : 0.0f;
-    up.go = (inside && fd.gO) ? fd.gO[p] : 0.0f;
-    up.gn0 = (inside && fd.gN) ? fd.gN[3 * p] : 0.0f;
-    up.gn1 = (inside && fd.gN) ? fd.gN[3 * p + 1] : 0.0f;
-    up.gn2 = (inside && fd.gN) ? fd.gN[3 * p + 2] : 0.0f;
-    up.Tfin = T0;
-    BwdState st = {T0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
-    int wlast = last;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
-    if (threadIdx.x == 0) s_tlast = 0;
-    for (int e = threadIdx.x; e < 4 * kNg * 64; e += blockDim.x) (&sred[0][0][0])[e] = 0.0f;
-    __syncthreads();
-    if (lane == 0) atomicMax(&s_tlast, wlast);
-    __syncthreads();
-    const int tlast = s_tlast;
-    double pacc[6] = {0, 0, 0, 0, 0, 0};
-    int n_eval = 0, n_con = 0;
-    const int end = rg.x + tlast;    // the tile's entries at or beyond end precede no contributor
-    const int wend = rg.x + wlast;   // this strip's
-    int c = tlast > 0 ? rg.x + ((tlast - 1) & ~63) : rg.x - 64;
-    static_assert(sizeof(RasterRec) == 96 && offsetof(RasterRec, rows) == 92, "record layout");
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    u32x4 nrec[6];
-    double nch[3];
-    uint32_t nid = 0;
-    if (wid == 0 && c >= rg.x && c + lane < end) {
-        nid = pval[c + lane];
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) nrec[f] = src[f];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
-    }
-    for (; c >= rg.x; c -= 64) {
-        if (wid == 0) {
-            if (c + lane < end) {
-                u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[lane]);
-#pragma unroll
-                for (int f = 0; f < 6; ++f) dst[f] = nrec[f];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) schat[lane].c[f] = nch[f];
-                sid[lane] = nid;
-            }
-            if (c - 64 >= rg.x) {   // the previous chunk's records, read while this one is processed
-                nid = pval[c - 64 + lane];
-                const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
-#pragma unroll
-                for (int f = 0; f < 6; ++f) nrec[f] = src[f];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
-            }
-        }
-        __syncthreads();
-        bool meets = false;
-        if (c + lane < wend) {
-            const uint32_t rows = sbuf[lane].rows;
-            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
-        }
-        const uint64_t m = __ballot(meets);
-        const int nact = __popcll(m);
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (meets) slist[wid][rank] = (uint8_t)lane;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        uint64_t fmask = 0;   // records of this chunk with partials in this wave's row
-        uint64_t live = __ballot(last > c - rg.x);
-        if (__popcll(live) > kStragglers) {
-            for (int q = nact - 1; q >= 0; --q) {
-                const int k = slist[wid][q];
-                const int pos = c + k - rg.x;
-                float g[kNg];
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
-                PairEval e;
-                n_eval += pos < last ? 1 : 0;
-                const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
-                if (act) {
-                    ++n_con;
-                    bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k].c, up, vx, vy, vz, g);
-                }
-                if (__any(act)) {
-                    const float tot = wave_sum18(g, lane);
-                    if (red_val < kNg) sred[wid][red_val][k] = tot;
-                    fmask |= 1ull << k;
-                }
-            }
-        } else {
-            const int pos_l = c + lane - rg.x;
-            while (live) {
-                const int pl = (int)__builtin_ctzll(live);
-                live &= live - 1;
-                const double pvx = bcast(vx, pl), pvy = bcast(vy, pl), pvz = bcast(vz, pl);
-                const int plast = bcast(last, pl);
-                BwdUpstream pu;
-                pu.gd = bcast(up.gd, pl); pu.go = bcast(up.go, pl); pu.gn0 = bcast(up.gn0, pl);
-                pu.gn1 = bcast(up.gn1, pl); pu.gn2 = bcast(up.gn2, pl); pu.Tfin = bcast(up.Tfin, pl);
-                BwdState ps;
-                ps.T = bcast(st.T, pl); ps.Bs = bcast(st.Bs, pl); ps.Kref = bcast(st.Kref, pl);
-                ps.tref = bcast(st.tref, pl); ps.nr0 = bcast(st.nr0, pl); ps.nr1 = bcast(st.nr1, pl);
-                ps.nr2 = bcast(st.nr2, pl); ps.have_ref = bcast(st.have_ref ? 1 : 0, pl) != 0;
-                const bool cand = meets && pos_l < plast;
-                PairEval ev;
-                const bool ok = eval_pair_flat(sbuf[lane], pvx, pvy, pvz, near_m, ev) && cand;
-                const int pe = __popcll(__ballot(cand));
-                uint64_t cm = __ballot(ok);
-                const int pc = __popcll(cm);
-                while (cm) {
-                    const int jl = 63 - (int)__builtin_clzll(cm);   // reverse list order
-                    cm &= ~(1ull << jl);
-                    PairEval ej;
-                    ej.sa = bcast(ev.sa, jl); ej.sb = bcast(ev.sb, jl); ej.t = bcast(ev.t, jl);
-                    ej.rc = bcast(ev.rc, jl); ej.G = bcast(ev.G, jl); ej.alpha = bcast(ev.alpha, jl);
-                    ej.clamped = bcast(ev.clamped ? 1 : 0, jl) != 0;
-                    float g[kNg];
-                    bwd_pair(ps, ej, sbuf[jl].n[0], sbuf[jl].n[1], sbuf[jl].n[2], schat[jl].c, pu, pvx, pvy, pvz, g);
-                    if (lane == jl) {
-#pragma unroll
-                        for (int v = 0; v < kNg; ++v) sred[wid][v][jl] += g[v];
-                    }
-                    fmask |= 1ull << jl;
-                }
-                if (lane == pl) {
-                    st = ps;
-                    n_eval += pe;
-                    n_con += pc;
-                }
-            }
-        }
-        if (lane == 0) smask[wid] = fmask;
-        __syncthreads();
-        // one flush per (tile, record); record k by thread 4k
-        if ((threadIdx.x & 3u) == 0) {
-            const int k = (int)(threadIdx.x >> 2);
-            const uint64_t f0 = smask[0], f1 = smask[1], f2 = smask[2], f3 = smask[3];
-            if (((f0 | f1 | f2 | f3) >> k) & 1ull) {
-                float sm[kNg];
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) sm[v] = 0.0f;
-                const uint64_t fw[4] = {f0, f1, f2, f3};
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    if (!((fw[w] >> k) & 1ull)) continue;
-#pragma unroll
-                    for (int v = 0; v < kNg; ++v) { sm[v] += sred[w][v][k]; sred[w][v][k] = 0.0f; }
-                }
-                const uint32_t id = sid[k];
-                flush_record(sm, frame[id], sbuf[k].M, schat[k].c, fd.pose,
-                             pose_only ? nullptr : fd.acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
-            }
-        }
-        __syncthreads();   // the next chunk reuses the buffers
-    }
-    if (inside) {
-        census[2 * total_pixels + p] = n_eval;
-        census[3 * total_pixels + p] = n_con;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        double v = pacc[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        pacc[k] = v;
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s_pose[wid][k] = pacc[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < 6)
-        pose_part[8 * (size_t)blockIdx.x + threadIdx.x] =
-            s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
-    if (threadIdx.x == 6) pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
-}
-
 template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
@@ -1345,18 +1122,6 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
-    if (L.bwd_variant == SLR_VARIANT_WAVE_TILE) {
-        hipLaunchKernelGGL(k_raster_bwd_t<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
-                           reinterpret_cast<const FrameDesc *>(ws + L.desc),
-                           reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
-                           reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                           reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
-                           reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
-                           reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
-                           reinterpret_cast<int32_t *>(ws + L.census), L.pixels,
-                           reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0);
-        return;
-    }
     if (wave) {
         hipLaunchKernelGGL(k_raster_bwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),

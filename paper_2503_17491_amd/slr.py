@@ -30,7 +30,7 @@ class Tiling(C.Structure):
                 ("bwd_variant", C.c_int32)]
 
 
-VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE, VARIANT_WAVE_TILE = 0, 1, 2, 3, 4
+VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
 SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST = 0, 1, 2
 
 
@@ -258,7 +258,7 @@ class Renderer:
 # Candidate tilings of the autotuner: (tile_h, tile_w, forward variant,
 # schedule, backward variant).
 TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((16, 16), (8, 32), (32, 8))
-                   for bv in (VARIANT_WAVE_TILE, VARIANT_WAVE, VARIANT_LDS)]
+                   for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
 
 

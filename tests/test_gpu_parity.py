@@ -249,8 +249,7 @@ def test_backward_parity_shell_full_image(slr):
 
 
 def test_backward_parity_structured_posed(slr):
-    say("backward structured-20k-posed-64x512 all pixels, 8x32 tiles, scalar forward, longest-first, "
-        "workgroup-of-strips backward")
+    say("backward structured-20k-posed-64x512 all pixels, 8x32 tiles, scalar forward, longest-first")
     sc, _ = synth.structured_scene(20000, 5)
     sensor = slr.make_sensor(64, 512)
     T = synth.circle_poses(8, 1)[2]
@@ -258,7 +257,7 @@ def test_backward_parity_structured_posed(slr):
     g = np.random.default_rng(2)
     P = pix.shape[0]
     check_backward(slr, sc, T, sensor, pix, g.normal(size=P).astype(np.float32),
-                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (8, 32, 2, 2, 4))
+                   g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), (8, 32, 2, 2))
 
 
 def test_backward_parity_fullsize_sparse(slr):
@@ -288,17 +287,16 @@ def test_backward_repeatable(slr):
     GD = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
     GN = torch.from_numpy(g.normal(size=(64, 512, 3)).astype(np.float32)).to(DEV)
     GO = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
-    for tiling in [(16, 16, 3), (16, 16, 3, 2, 4)]:
-        r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, tiling, 1 << 20)
-        outs = []
-        for _ in range(2):
-            gr, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, GD, GN, GO)
-            torch.cuda.synchronize()
-            outs.append(([gr[k].cpu().numpy().copy() for k in ("means", "quats", "log_scales", "logits")],
-                         dp.cpu().numpy().copy()))
-        np.testing.assert_array_equal(outs[0][1], outs[1][1])
-        for a, b in zip(outs[0][0], outs[1][0]):
-            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(a).max()))
+    r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, (16, 16, 3), 1 << 20)
+    outs = []
+    for _ in range(2):
+        gr, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, GD, GN, GO)
+        torch.cuda.synchronize()
+        outs.append(([gr[k].cpu().numpy().copy() for k in ("means", "quats", "log_scales", "logits")],
+                     dp.cpu().numpy().copy()))
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    for a, b in zip(outs[0][0], outs[1][0]):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(a).max()))
 
 
 def test_pose_only_matches_full_backward(slr):
