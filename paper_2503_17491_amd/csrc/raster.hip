@@ -824,17 +824,18 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         for (int q = nact - 1; q >= 0; --q) {
             const int k = slist[wid][q];
             const int pos = b0 + k - rg.x;
-            float g[kNg];
-#pragma unroll
-            for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
             PairEval e;
             n_eval += pos < last ? 1 : 0;
             const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
-            if (act) {
-                ++n_con;
-                bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k].c, up, vx, vy, vz, g);
-            }
+            // about half of the walked entries meet no lane: they skip the partials
             if (__any(act)) {
+                float g[kNg];
+#pragma unroll
+                for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                if (act) {
+                    ++n_con;
+                    bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k].c, up, vx, vy, vz, g);
+                }
                 static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                 const float tot = wave_sum18(g, lane);
                 if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
@@ -998,17 +999,17 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             for (int q = nact - 1; q >= 0; --q) {
                 const int k = slist[q];
                 const int pos = c + k - rg.x;
-                float g[kNg];
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
                 PairEval e;
                 n_eval += pos < last ? 1 : 0;
                 const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
-                if (act) {
-                    ++n_con;
-                    bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k].c, up, vx, vy, vz, g);
-                }
                 if (__any(act)) {
+                    float g[kNg];
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                    if (act) {
+                        ++n_con;
+                        bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k].c, up, vx, vy, vz, g);
+                    }
                     static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                     const float tot = wave_sum18(g, lane);
                     if (red_val < kNg) sred[red_val][k] = tot;
