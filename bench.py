@@ -88,10 +88,11 @@ def batched_step(slr, br, kfs, loss):
     br.backward()
 
 
-def counted_traffic(kernel):
+def counted_traffic(kernel, tiling):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when the
-    compositing source has changed since the counters were taken."""
+    compositing source has changed since the counters were taken or the
+    summary was measured with another tiling (tile, forward and backward form)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_8x128x1024_1M.txt")
     src = os.path.join(ROOT, "paper_2503_17491_amd", "csrc", "raster.hip")
@@ -106,6 +107,8 @@ def counted_traffic(kernel):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if fields.get("raster.hip sha256") != sha or "traffic bytes per launch" not in fields:
+        return None
+    if fields.get("tiling") != tiling:
         return None
     return int(float(fields["traffic bytes per launch"]))
 
@@ -287,8 +290,10 @@ def main():
     else:
         dom, flops, ms = "raster_fwd", fwd_flops, fwd_ms
     achieved = flops / (ms * 1e-3) / 1e12
+    vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
+    tiling_name = f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}"
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": counted_traffic(dom),
+            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": counted_traffic(dom, tiling_name),
             "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
     stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
     if args.form == "plain" and plain_iters is None:
