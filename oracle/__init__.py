@@ -6,3 +6,4 @@ Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 from .oracle import *  # noqa: F401,F403
 from .adam import adam_step  # noqa: F401
 from .loss import loss_l1_normal  # noqa: F401
+from .gn import huber, pose_gn, pose_jacobian  # noqa: F401
