@@ -10,7 +10,8 @@ loss and gradients, backward (compositing backward, per-surfel gradients
 summed over the keyframes, pose gradient per keyframe).  Inputs are resident
 in HBM before the timed region.
 
-Prints one JSON line (see the design doc for every field's definition).
+Prints one JSON line: the metric, per-stage times, the roofline of the dominant
+compositing kernel and the FP64 oracle's CPU baseline.
 """
 import argparse
 import json
@@ -27,7 +28,7 @@ N_SURFELS = 1_000_000
 N_KF = 8
 H, W = 128, 1024
 
-# Algorithmic FLOPs (FMA = 2) per unit of compositing work; see the design doc.
+# Algorithmic FLOPs (FMA = 2) per unit of compositing work.
 FWD_EVAL_FLOPS = 18      # 3 three-term FP64 dot products + support bound, reciprocal, range
 FWD_CONTRIB_FLOPS = 20   # Gaussian, alpha, blending of range, normal and opacity
 BWD_EVAL_FLOPS = 18
@@ -171,8 +172,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; the multi-GPU design is described in DESIGN.md "
-              "(keyframe sharding and a gradient all-reduce) and is not implemented", file=sys.stderr)
+        print("bench.py runs on one GPU only: sharding keyframes over several GPUs (with an all-reduce of the "
+              "surfel gradients) is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -158,6 +158,28 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
                         const float *dL_dalpha, float *d_means, float *d_quats, float *d_log_scales,
                         float *d_logits, double *d_pose, uint32_t flags, void *stream);
 
+/* Pose-only Gauss-Newton normal equations of the range image (Sec. 3.3.1:
+ * the keyframe pose is updated as T_wc <- T_wc exp(delta), delta = (rho; phi)
+ * in se(3), by Gauss-Newton on Huber-robust residuals).  Reads the workspace
+ * left by a successful slr_render with the same surfels, pose, sensor and
+ * tiling.  With r = D - D_t per pixel, J = dD/d delta at delta = 0 (computed
+ * in the reverse traversal of the compositing lists), m the pixel weight and
+ * w(r) the Huber IRLS weight (1 for |r| <= huber_k, huber_k / |r| beyond;
+ * huber_k <= 0: plain least squares, w = 1):
+ *   H = sum m w J J^T,  g = sum m w r J,  cost = sum m rho(r)
+ * (rho: r^2/2, or huber_k (|r| - huber_k/2) beyond the threshold); g is the
+ * gradient of the cost and the Gauss-Newton step solves H delta = -g.
+ * Inputs (device, FP32, [H,W]): depth = the range image that slr_render wrote,
+ * target = D_t, weight = m (nullable: all ones; 0 drops a pixel, e.g. where
+ * the target has no return).  Output (device FP64, overwritten, 43 values):
+ * H row-major [0..35], g [36..41], cost [42].  Sums are taken in a fixed
+ * order (bit-reproducible).  Errors: NULL depth, target or normal_eq, NaN
+ * huber_k, and the same checks as slr_backward. */
+slr_status slr_pose_gn(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
+                       const slr_tiling *tiling, void *workspace, size_t workspace_bytes, int64_t pair_capacity,
+                       const float *depth, const float *target, const float *weight, double huber_k,
+                       double *normal_eq, void *stream);
+
 /* Device pointers into a workspace filled by slr_render (for inspection and
  * tests). */
 slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n,
@@ -269,9 +291,9 @@ slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *n
  * synchronises them and returns the accumulated milliseconds and launch
  * counts per stage (then resets).  Stages: 0 projection, 1 range sort,
  * 2 count scan, 3 emit + tile sort + ranges, 4 forward compositing,
- * 5 backward compositing, 6 per-surfel gradients, 7 loss.  ms and counts
- * are host arrays of SLR_NUM_STAGES entries. */
-#define SLR_NUM_STAGES 8
+ * 5 backward compositing, 6 per-surfel gradients, 7 loss, 8 Gauss-Newton
+ * compositing.  ms and counts are host arrays of SLR_NUM_STAGES entries. */
+#define SLR_NUM_STAGES 9
 slr_status slr_stage_timer_enable(int32_t on);
 slr_status slr_stage_times(double *ms, int64_t *counts);
 

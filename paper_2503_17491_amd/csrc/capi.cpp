@@ -387,6 +387,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.rbox = take(sizeof(PixBox) * nn);
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
     L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
+    // per Gauss-Newton workgroup (one per tile): its partial normal equations
+    L.gn_part = take(sizeof(double) * kGnRow * (size_t)L.tiles);
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));
@@ -521,6 +523,36 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
     slr::launch_write_desc(d.data(), 1, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
     slr_surfel_grads g{d_means, d_quats, d_log_scales, d_logits};
     enqueue_backward(B, surfels, &g, ws, pose_only, accumulate, s);
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_pose_gn(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
+                       const slr_tiling *tiling, void *workspace, size_t workspace_bytes, int64_t pair_capacity,
+                       const float *depth, const float *target, const float *weight, double huber_k,
+                       double *normal_eq, void *stream)
+{
+    slr_frame fr;
+    Batch B;
+    slr_status st = plain_batch(surfels, pose_cw, sensor, tiling, pair_capacity, &fr, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    if (!depth || !target || !normal_eq) return fail(SLR_E_INVALID, "depth, target and normal_eq must be set");
+    if (std::isnan(huber_k)) return fail(SLR_E_INVALID, "huber_k is NaN");
+    fr.depth = const_cast<float *>(depth);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    std::vector<FrameDesc> d = make_descs(B, surfels, &fr, tiling, ws);
+    d[0].gn_target = target;
+    d[0].gn_weight = weight;
+    d[0].gn = normal_eq;
+    d[0].huber_k = huber_k;
+    slr::launch_write_desc(d.data(), 1, reinterpret_cast<FrameDesc *>(ws + B.L.desc), s);
+    {
+        StageScope t(8, s);
+        slr::launch_raster_gn(B.L, ws, s);
+    }
+    slr::launch_gn_reduce(B.L, ws, s);
     HIP_TRY(hipGetLastError());
     return SLR_OK;
 }

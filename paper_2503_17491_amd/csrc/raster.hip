@@ -632,9 +632,15 @@ struct BwdState {
 //   the unshifted form.  The partials are centred on the surfel centre's
 //   direction ch: da (v - ch), db (v - ch), dc_s v, da, db, (dL/dt / c)(s_a, s_b, 1),
 //   dL/do, dL/dn.
-__device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
-                                         const double *ch, const BwdUpstream &u, double vx, double vy, double vz,
-                                         float (&g)[18])
+// The scalar part of one reverse step: advances the state and returns
+// da = dL/da, db = dL/db (a = P.v, b = Q.v), dcs = the c = M.v part of the
+// s_hat path, tt = (dL/dt) / c, dop = dL/do and the pair's weight w = alpha A.
+struct BwdScalars {
+    float da, db, dcs, tt, dop, w;
+};
+
+__device__ __forceinline__ BwdScalars bwd_step(BwdState &st, const PairEval &e, float n0, float n1, float n2,
+                                               const BwdUpstream &u)
 {
     const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
     const float A = st.T * r1;  // transmittance in front of this pair
@@ -658,6 +664,15 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
     const float da = dsa * e.rc, db = dsb * e.rc;
     const float dcs = -(dsa * e.sa + dsb * e.sb) * e.rc;
     const float tt = gt * e.rc;
+    return {da, db, dcs, tt, dop, w};
+}
+
+__device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
+                                         const double *ch, const BwdUpstream &u, double vx, double vy, double vz,
+                                         float (&g)[18])
+{
+    const BwdScalars q = bwd_step(st, e, n0, n1, n2, u);
+    const float da = q.da, db = q.db, dcs = q.dcs, tt = q.tt, dop = q.dop, w = q.w;
     const float ex = (float)(vx - ch[0]), ey = (float)(vy - ch[1]), ez = (float)(vz - ch[2]);
     const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
     g[0] = da * ex; g[1] = da * ey; g[2] = da * ez;
@@ -1092,6 +1107,172 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     if (lane == 6) pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
 }
 
+// Pose-only Gauss-Newton normal equations (Sec. 3.3.1, T_wc <- T_wc exp(delta)).
+// The reverse traversal of the backward with a unit upstream range gradient
+// gives every contributing pair's dD/d(s_hat, t) (bwd_step).  Moving the
+// sensor by rho moves the ray origin to rho, turning it by phi turns the ray
+// to v + phi x v; with a = P.v, b = Q.v, c = M.v and the origin o, s_hat =
+// (v.((o - b_c) x b_beta), v.(b_alpha x (o - b_c))) / c and t = (tau - M.o) / c,
+// so per pair
+//   dD/drho += da (b_beta x v) + db (v x b_alpha) - tt M
+//   dD/dphi += v x (da P + db Q + (dcs - tt t) M)
+// summed in registers per pixel (FP32).  Each pixel then adds m w J J^T,
+// m w r J and m rho(r) (r = D - D_target, w the Huber IRLS weight, m the
+// caller's weight) in FP64; the workgroup's sums go to a row of their own,
+// summed per keyframe in a fixed order by k_gn_reduce.
+template <int TW>
+__global__ void __launch_bounds__(256)
+k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+            const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
+            const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+            const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+            const int32_t *__restrict__ stN_all, double *__restrict__ gn_part)
+{
+    constexpr int TH = 256 / TW;
+    __shared__ RasterRec srec[kBwdBatch];
+    __shared__ float sab[kBwdBatch][6];   // b_alpha, b_beta in FP32
+    __shared__ uint8_t slist[4][kBwdBatch];
+    __shared__ int s_last;
+    __shared__ double s_red[4][kGnVals];
+
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = ty * TH + ly, j = tx * TW + lx;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    const int2 rg = ranges[tile];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int p = inside ? i * W + j : 0;
+    const float Tfin = inside ? stT[p] : 1.0f;
+    const int last = inside ? stN[p] : 0;
+    if (threadIdx.x == 0) s_last = 0;
+    __syncthreads();
+    if (last > 0) atomicMax(&s_last, last);
+    __syncthreads();
+    const int end = rg.x + s_last;
+    int wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+
+    BwdState st = {Tfin, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    const BwdUpstream up = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, Tfin};   // dL/dD = 1
+    float J[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int b_end = end; b_end > rg.x; b_end -= kBwdBatch) {
+        const int b0 = max(rg.x, b_end - kBwdBatch);
+        const int cnt = b_end - b0;
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const uint32_t id = pval[b0 + threadIdx.x];
+            srec[threadIdx.x] = rec[id];
+            const FrameRec &fr = frame[id];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sab[threadIdx.x][c] = (float)fr.ba[c];
+                sab[threadIdx.x][3 + c] = (float)fr.bb[c];
+            }
+        }
+        __syncthreads();
+        int nact = 0;
+        for (int base = 0; base < cnt; base += 64) {
+            const int kk = base + lane;
+            bool meets = false;
+            if (kk < cnt) {
+                const uint32_t rows = srec[kk].rows;
+                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
+            }
+            const uint64_t m = __ballot(meets);
+            if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)kk;
+            nact += __popcll(m);
+        }
+        __syncthreads();
+        for (int q = nact - 1; q >= 0; --q) {
+            const int k = slist[wid][q];
+            const int pos = b0 + k - rg.x;
+            PairEval e;
+            const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
+            if (act) {
+                const RasterRec &r = srec[k];
+                const BwdScalars s = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up);
+                const float ax = sab[k][0], ay = sab[k][1], az = sab[k][2];
+                const float bx = sab[k][3], by = sab[k][4], bz = sab[k][5];
+                const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
+                J[0] += s.da * (by * fvz - bz * fvy) + s.db * (fvy * az - fvz * ay) - s.tt * Mx;
+                J[1] += s.da * (bz * fvx - bx * fvz) + s.db * (fvz * ax - fvx * az) - s.tt * My;
+                J[2] += s.da * (bx * fvy - by * fvx) + s.db * (fvx * ay - fvy * ax) - s.tt * Mz;
+                const float km = s.dcs - s.tt * e.t;
+                const float gx = s.da * (float)r.P[0] + s.db * (float)r.Q[0] + km * Mx;
+                const float gy = s.da * (float)r.P[1] + s.db * (float)r.Q[1] + km * My;
+                const float gz = s.da * (float)r.P[2] + s.db * (float)r.Q[2] + km * Mz;
+                J[3] += fvy * gz - fvz * gy;
+                J[4] += fvz * gx - fvx * gz;
+                J[5] += fvx * gy - fvy * gx;
+            }
+        }
+    }
+
+    // this pixel's terms, then wave sums (FP64 butterflies) and the four waves in order
+    double Jd[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Jd[c] = J[c];
+    double wgt = 0.0, wr = 0.0, cost = 0.0;
+    if (inside) {
+        const float m = fd.gn_weight ? fd.gn_weight[p] : 1.0f;
+        if (m != 0.0f) {
+            const double r = (double)fd.depth[p] - (double)fd.gn_target[p];
+            const double k = fd.huber_k, a = fabs(r);
+            const bool lin = k > 0.0 && a > k;
+            wgt = (double)m * (lin ? k / a : 1.0);
+            wr = wgt * r;
+            cost = (double)m * (lin ? k * (a - 0.5 * k) : 0.5 * r * r);
+        }
+    }
+    int c = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+#pragma unroll
+        for (int b = a; b < 6; ++b) {
+            double v = wgt * Jd[a] * Jd[b];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) s_red[wid][c] = v;
+            ++c;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        double v = wr * Jd[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) s_red[wid][21 + a] = v;
+    }
+    {
+        double v = cost;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) s_red[wid][27] = v;
+    }
+    __syncthreads();
+    double *row = gn_part + (size_t)kGnRow * blockIdx.x;
+    if (threadIdx.x < kGnVals) {
+        const int t = threadIdx.x;
+        row[t] = ((s_red[0][t] + s_red[1][t]) + s_red[2][t]) + s_red[3][t];
+    }
+    if (threadIdx.x == kGnVals) row[kGnVals] = (double)tile_frame[tile];
+}
+
 template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
@@ -1145,6 +1326,19 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        pose_only ? 1 : 0);
 }
 
+template <int TW>
+void gn_launch(const Layout &L, char *ws, hipStream_t stream)
+{
+    const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
+    hipLaunchKernelGGL(k_raster_gn<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
+                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
+                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                       reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
+                       reinterpret_cast<double *>(ws + L.gn_part));
+}
+
 }  // namespace
 
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream)
@@ -1166,6 +1360,17 @@ void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t st
     case 32: bwd_launch<32>(L, ws, pose_only, stream); break;
     case 8: bwd_launch<8>(L, ws, pose_only, stream); break;
     default: bwd_launch<64>(L, ws, pose_only, stream); break;
+    }
+}
+
+void launch_raster_gn(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.tiles == 0) return;
+    switch (L.tw) {
+    case 16: gn_launch<16>(L, ws, stream); break;
+    case 32: gn_launch<32>(L, ws, stream); break;
+    case 8: gn_launch<8>(L, ws, stream); break;
+    default: gn_launch<64>(L, ws, stream); break;
     }
 }
 

@@ -62,6 +62,9 @@ struct __align__(16) FrameDesc {
     const float *gD, *gN, *gO;                           // upstream gradients (nullable)
     double *d_pose;                                      // [6] pose gradient (never NULL)
     float *acc;                                          // the set's gradient accumulator
+    const float *gn_target, *gn_weight;                  // Gauss-Newton target range, weight (nullable)
+    double *gn;                                          // [43] Gauss-Newton output: H (6x6), g, cost
+    double huber_k;                                      // Huber threshold (<= 0: least squares)
     int64_t n;                                           // surfels in the set
     int64_t item_off;                                    // first record index
     int64_t pix_off;                                     // first pixel of the per-pixel state
@@ -98,7 +101,7 @@ struct Layout {
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
-    size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
@@ -119,6 +122,13 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream);
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream);
+void launch_raster_gn(const Layout &L, char *ws, hipStream_t stream);
+void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream);
+
+// Gauss-Newton partial row of one compositing workgroup: the 21 upper-triangle
+// entries of H (row-major), the 6 of g, the cost, and the keyframe index.
+constexpr int kGnVals = 28;
+constexpr int kGnRow = 32;
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits,
                         bool accumulate, hipStream_t stream);

@@ -39,6 +39,47 @@ k_pose_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ pa
     if (threadIdx.x < 6) descs[f].d_pose[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Per keyframe: the sum of the Gauss-Newton workgroups' rows (kGnVals values
+// and the keyframe index) in a fixed order, written out as H (6x6, both
+// triangles), g (6) and the cost.  Frames without an output pointer are skipped.
+__global__ void __launch_bounds__(128)
+k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts)
+{
+    __shared__ double red[kGnVals][128];
+    const int f = blockIdx.x;
+    double *out = descs[f].gn;
+    if (!out) return;
+    double v[kGnVals];
+#pragma unroll
+    for (int c = 0; c < kGnVals; ++c) v[c] = 0.0;
+    for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
+        const double *pp = part + (size_t)kGnRow * b;
+        if ((int)pp[kGnVals] != f) continue;
+#pragma unroll
+        for (int c = 0; c < kGnVals; ++c) v[c] += pp[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kGnVals; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = 64; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < kGnVals; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const int t = threadIdx.x;
+    if (t < 36) {
+        const int a = t / 6, b = t % 6;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        out[t] = red[6 * lo - (lo * (lo - 1)) / 2 + (hi - lo)][0];   // row-major upper triangle
+    } else if (t < 42) {
+        out[t] = red[21 + (t - 36)][0];
+    } else if (t == 42) {
+        out[42] = red[27][0];
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restrict__ lsc,
               const float *__restrict__ logits, const float *__restrict__ acc, float *__restrict__ d_means,
@@ -114,6 +155,14 @@ void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_pose_reduce, dim3((unsigned)L.frames), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.pose_part),
                        nparts);
+}
+
+void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.frames == 0) return;
+    hipLaunchKernelGGL(k_gn_reduce, dim3((unsigned)L.frames), dim3(128), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.gn_part),
+                       L.tiles);
 }
 
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(HERE, "libslr.so")
 SLR_OK, SLR_E_INVALID, SLR_E_CAPACITY, SLR_E_HIP, SLR_E_UNSUPPORTED = 0, -1, -2, -3, -4
 SLR_POSE_ONLY = 1
 SLR_ACCUMULATE = 2
-NUM_STAGES = 8
-STAGES = ["project", "range_sort", "count_scan", "emit_tile_sort", "raster_fwd", "raster_bwd", "surfel_grad", "loss"]
+NUM_STAGES = 9
+STAGES = ["project", "range_sort", "count_scan", "emit_tile_sort", "raster_fwd", "raster_bwd", "surfel_grad", "loss",
+          "pose_gn"]
 
 
 class Sensor(C.Structure):
@@ -58,7 +59,7 @@ class SurfelGrads(C.Structure):
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
            "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
-           "slr_status_string", "slr_last_error"]
+           "slr_pose_gn", "slr_status_string", "slr_last_error"]
 
 _lib = None
 
@@ -76,6 +77,7 @@ def lib():
         L.slr_render.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P]
         L.slr_backward.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
         L.slr_workspace_views.argtypes = [P, P, I64, I64, P, C.c_size_t, P]
+        L.slr_pose_gn.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, D, P, P]
         BATCH = [I32, P, I32, P, P, I64, P, C.c_size_t]
         L.slr_batch_workspace_size.argtypes = [I32, P, I32, P, P, I64, P]
         L.slr_batch_prepare.argtypes = BATCH + [P]
@@ -93,7 +95,7 @@ def lib():
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
                   "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
-                  "slr_stage_timer_enable", "slr_stage_times"):
+                  "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -228,6 +230,22 @@ class Renderer:
                                 _ptr(dpose), flags, _stream())
         _check(st, "slr_backward")
         return g, dpose
+
+    def pose_gn(self, means, quats, log_scales, logits, T_cw, depth, target, weight=None, huber_k=0.0, out=None):
+        """Pose-only Gauss-Newton normal equations of the last render
+        (slr_pose_gn): returns (H [6,6], g [6], cost []) as FP64 CUDA tensors
+        (views of one 43-value buffer; `out` reuses a given buffer)."""
+        sf = _surfels(means, quats, log_scales, logits)
+        _pose(T_cw)
+        for name, a in (("depth", depth), ("target", target), ("weight", weight)):
+            if a is not None and (a.dtype != torch.float32 or not a.is_contiguous()):
+                raise ValueError(f"{name} must be contiguous float32")
+        buf = out if out is not None else torch.empty(43, dtype=torch.float64, device=means.device)
+        s, t = _sensor(self.sensor), Tiling(*self.tiling)
+        _check(lib().slr_pose_gn(C.byref(sf), _ptr(T_cw), C.byref(s), C.byref(t), _ptr(self.ws), self.ws.numel(),
+                                 self.capacity, _ptr(depth), _ptr(target), _ptr(weight), float(huber_k), _ptr(buf),
+                                 _stream()), "slr_pose_gn")
+        return buf[:36].view(6, 6), buf[36:42], buf[42]
 
     def views(self):
         """Copies of the binning results and per-pixel state of the last render."""

@@ -115,3 +115,27 @@ def test_backward_rejects_inconsistent_gradient_outputs():
     st = L.slr_backward(C.byref(sf), C.c_void_p(pose.ctypes.data), C.byref(s), C.byref(t), C.c_void_p(wp),
                         big.size - 256, 100, None, None, None, None, None, None, None, gp, 8, None)
     assert st == slr.SLR_E_INVALID
+
+
+def test_pose_gn_rejects_bad_arguments_without_gpu():
+    L = slr.lib()
+    s, t, buf = _args()
+    arr = np.zeros(64, np.float32)
+    p = C.c_void_p(arr.ctypes.data)
+    sf = slr.Surfels(4, p, p, p, p)
+    pose = np.zeros(16)
+    pp = C.c_void_p(pose.ctypes.data)
+    img = np.zeros(64 * 512, np.float32)
+    ip = C.c_void_p(img.ctypes.data)
+    out = np.zeros(43)
+    op = C.c_void_p(out.ctypes.data)
+    big = np.zeros(1 << 24, np.uint8)
+    wp = C.c_void_p(big.ctypes.data + (-big.ctypes.data) % 256)
+    n = big.size - 256
+    for depth, target, o, k in ((None, ip, op, 0.0), (ip, None, op, 0.0), (ip, ip, None, 0.0),
+                                (ip, ip, op, float("nan"))):
+        st = L.slr_pose_gn(C.byref(sf), pp, C.byref(s), C.byref(t), wp, n, 100, depth, target, None, k, o, None)
+        assert st == slr.SLR_E_INVALID
+    # a workspace too small for the plain form is refused too
+    st = L.slr_pose_gn(C.byref(sf), pp, C.byref(s), C.byref(t), wp, 1024, 100, ip, ip, None, 0.0, op, None)
+    assert st == slr.SLR_E_INVALID

@@ -1,0 +1,199 @@
+"""GPU parity of the pose-only Gauss-Newton normal equations (slr_pose_gn,
+Sec. 3.3.1) through the C ABI.
+
+* Against the FP64 oracle (H, g, cost) on a room of overlapping surfels seen
+  from a perturbed pose, ragged image (40x136), every tile shape, least
+  squares and Huber, random per-pixel weights; pixels inside the oracle's
+  guard band get weight 0 on both sides.  H and g at 2e-3 of their largest
+  entry / their norm (per-pixel Jacobians are summed in FP32 per pair, then
+  in FP64), the cost at 1e-4.
+* At the benchmark's size (1M surfels, 128x1024, the analytic target): H is
+  symmetric positive semidefinite, the cost equals the plain sum over pixels,
+  and g equals the pose gradient that slr_backward computes for the upstream
+  range gradient m r (the same quantity by another route) to 1e-3.
+* Gauss-Newton iterations through the GPU converge to the target's pose.
+* Repeatability (bit-identical calls), an empty map, zero weights.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_17491_amd import synth
+from tests import helpers as h
+from tests.test_oracle_gn import pose_error, room_scene
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+EXCL = O.FLAG_SUPPORT | O.FLAG_NEAR | O.FLAG_AMIN | O.FLAG_TSTOP
+
+
+def say(*a):
+    print("[gpu-gn]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def slr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_17491_amd import slr as S
+    S.lib()
+    return S
+
+
+def room_dict():
+    mu, q, ls, lg = room_scene()
+    return dict(means=mu.astype(np.float32), quats=q.astype(np.float32), log_scales=ls.astype(np.float32),
+                logits=lg.astype(np.float32))
+
+
+def to_dev(sc):
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in sc.items()}
+
+
+def pose_dev(T):
+    return torch.from_numpy(np.ascontiguousarray(T, dtype=np.float64)).to(DEV)
+
+
+def gpu_gn(S, sc, T, sensor, target, weight, huber_k, tiling):
+    r = S.Renderer(sensor, tiling, 1 << 18)
+    d = to_dev(sc)
+    Td = pose_dev(T)
+    D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+    tg = torch.from_numpy(np.ascontiguousarray(target, np.float32)).to(DEV)
+    wt = None if weight is None else torch.from_numpy(np.ascontiguousarray(weight, np.float32)).to(DEV)
+    Hm, g, c = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, wt, huber_k)
+    torch.cuda.synchronize()
+    return Hm.cpu().numpy(), g.cpu().numpy(), float(c.cpu()), D
+
+
+_ORACLE = {}
+
+
+def room_case(huber_k):
+    """Scene, sensor, poses, target and weights of the parity case, and the
+    oracle's normal equations (computed once per Huber threshold)."""
+    if huber_k in _ORACLE:
+        return _ORACLE[huber_k]
+    sc = room_dict()
+    sensor = O.make_sensor(40, 136)
+    T_true = np.eye(4)
+    T = h.perturb_cw(T_true, np.array([0.08, -0.06, 0.03, 0.01, -0.012, 0.015]))
+    tgt = O.render_image(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T_true, sensor)
+    cur = O.render_image(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor)
+    g = np.random.default_rng(5)
+    weight = (tgt["alpha"] > 0.5) & ((cur["flags"] & EXCL) == 0)
+    weight = weight * g.uniform(0.5, 1.5, weight.shape)
+    target = tgt["depth"].astype(np.float32).astype(np.float64)
+    ref = O.pose_gn(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, target,
+                    weight.astype(np.float32).astype(np.float64), huber_k)
+    _ORACLE[huber_k] = (sc, sensor, T, target, weight, ref)
+    return _ORACLE[huber_k]
+
+
+@pytest.mark.parametrize("huber_k", [0.0, 0.03])
+@pytest.mark.parametrize("tiling", [(16, 16), (32, 8, 3, 2, 1), (8, 32), (4, 64)])
+def test_pose_gn_matches_oracle(slr, huber_k, tiling):
+    sc, sensor, T, target, weight, ref = room_case(huber_k)
+    say("room 40x136", "huber", huber_k, "tiling", tiling)
+    Hm, g, c, _ = gpu_gn(slr, sc, T, sensor, target, weight, huber_k, tiling)
+    if huber_k > 0:
+        rr = np.abs(ref["residual"])[weight > 0]
+        assert (rr > huber_k).sum() > 20 and (rr <= huber_k).sum() > 20
+    np.testing.assert_array_equal(Hm, Hm.T)
+    assert np.abs(Hm - ref["H"]).max() <= 2e-3 * np.abs(ref["H"]).max(), (Hm, ref["H"])
+    assert np.linalg.norm(g - ref["g"]) <= 2e-3 * np.linalg.norm(ref["g"]), (g, ref["g"])
+    assert abs(c - ref["cost"]) <= 1e-4 * ref["cost"], (c, ref["cost"])
+
+
+def test_pose_gn_repeatable_and_degenerate(slr):
+    sc, sensor, T, target, weight, ref = room_case(0.0)
+    say("repeatable, zero weight, empty map")
+    r = slr.Renderer(sensor, (16, 16), 1 << 18)
+    d = to_dev(sc)
+    Td = pose_dev(T)
+    D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+    tg = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    wt = torch.from_numpy(weight.astype(np.float32)).to(DEV)
+    a = [t.clone() for t in r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, wt)]
+    b = [t.clone() for t in r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, wt)]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    z = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, torch.zeros_like(wt))
+    for x in z:
+        assert not x.cpu().numpy().any()
+    # an empty map renders nothing: J = 0, the cost is the weighted sum over the targets
+    empty = {k: v[:0] for k, v in sc.items()}
+    e = slr.Renderer(sensor, (16, 16), 1 << 10)
+    de = to_dev(empty)
+    De, _, _ = e.forward(de["means"], de["quats"], de["log_scales"], de["logits"], Td)
+    He, ge, ce = e.pose_gn(de["means"], de["quats"], de["log_scales"], de["logits"], Td, De, tg, wt, 0.0)
+    assert not He.cpu().numpy().any() and not ge.cpu().numpy().any()
+    want = float((0.5 * weight * target ** 2).sum())
+    assert abs(float(ce.cpu()) - want) <= 1e-6 * want
+
+
+def test_pose_gn_fullsize_properties(slr):
+    """The benchmark's map and image size: 1M structured-scene surfels, 128x1024."""
+    from paper_2503_17491_amd import targets
+    sc, prims = synth.structured_scene(1_000_000, 0)
+    T = synth.circle_poses(8, 0)[0]
+    sensor = slr.make_sensor(128, 1024)
+    Dt, _ = targets.raycast(prims, sensor, T, seed=100)
+    for tiling, k in (((32, 8, 3, 2, 1), 0.0), ((16, 16, 3, 2, 3), 0.05)):
+        say("fullsize 1M 128x1024", tiling, "huber", k)
+        r = slr.Renderer(sensor, tiling, 4 << 20)
+        d = to_dev(sc)
+        Td = pose_dev(T)
+        D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+        tg = torch.from_numpy(Dt).to(DEV)
+        m = (tg > 0).float()
+        Hm, g, c = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, m, k)
+        Hn, gn, cn = Hm.cpu().numpy(), g.cpu().numpy(), float(c.cpu())
+        np.testing.assert_array_equal(Hn, Hn.T)
+        assert np.linalg.eigvalsh(Hn).min() >= -1e-9 * np.abs(Hn).max()
+        res = (D.double() - tg.double())
+        a = res.abs()
+        if k > 0:
+            rho = torch.where(a <= k, 0.5 * res * res, k * (a - 0.5 * k))
+            w = torch.where(a <= k, torch.ones_like(a), k / a)
+        else:
+            rho, w = 0.5 * res * res, torch.ones_like(a)
+        want = float((m.double() * rho).sum().cpu())
+        assert abs(cn - want) <= 1e-9 * abs(want), (cn, want)
+        # g is the pose gradient of the cost: the backward with dL/dD = m w r gives it too
+        up = (m.double() * w * res).float().contiguous()
+        _, dpose = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, up, None, None,
+                              pose_only=True)
+        dp = dpose.cpu().numpy()
+        assert np.linalg.norm(gn - dp) <= 1e-3 * np.linalg.norm(dp), (gn, dp)
+        del r
+        torch.cuda.empty_cache()
+
+
+def test_gauss_newton_iterations_converge(slr):
+    sc = room_dict()
+    sensor = slr.make_sensor(32, 256)
+    T_true = np.eye(4)
+    tgt = O.render_image(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T_true, sensor)
+    target = torch.from_numpy(tgt["depth"].astype(np.float32)).to(DEV)
+    weight = torch.from_numpy((tgt["alpha"] > 0.5).astype(np.float32)).to(DEV)
+    T = h.perturb_cw(T_true, np.array([0.1, -0.08, 0.05, 0.02, -0.015, 0.025]))
+    r = slr.Renderer(sensor, (16, 16), 1 << 18)
+    d = to_dev(sc)
+    errs = [pose_error(T, T_true)]
+    for it in range(5):
+        Td = pose_dev(T)
+        D, _, _ = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+        Hm, g, c = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, target, weight, 0.0)
+        delta = -np.linalg.solve(Hm.cpu().numpy(), g.cpu().numpy())
+        T = h.perturb_cw(T, delta)
+        errs.append(pose_error(T, T_true))
+        say("GN iteration", it, "cost", float(c.cpu()), "error", errs[-1])
+    for a, b in zip(errs[:3], errs[1:4]):  # every early step at least halves both errors
+        assert b[0] < 0.5 * a[0] and b[1] < 0.5 * a[1], errs
+    assert errs[-1][0] < 1e-4 and errs[-1][1] < 1e-5, errs
