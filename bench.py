@@ -33,6 +33,7 @@ FWD_EVAL_FLOPS = 18      # 3 three-term FP64 dot products + support bound, recip
 FWD_CONTRIB_FLOPS = 20   # Gaussian, alpha, blending of range, normal and opacity
 BWD_EVAL_FLOPS = 18
 BWD_CONTRIB_FLOPS = 70   # recompute alpha, transmittance recovery, dL/dalpha, 14 partials
+GN_CONTRIB_FLOPS = 96    # recompute alpha, reverse step with a unit range gradient, 6-vector Jacobian update
 PEAK_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), unpacked FP32 / FP64
 PEAK_HBM_GBS = 8000.0
 
@@ -114,6 +115,47 @@ def counted_traffic(kernel, tiling):
     return int(float(fields["traffic bytes per launch"]))
 
 
+def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
+    """Pose-only Gauss-Newton iterations on keyframe 0 (plain form): render at
+    the pose, then the normal equations against the keyframe's target (least
+    squares, weight 1 where the target has a return).  The 6x6 solve is the
+    caller's and is not timed.  The kernel walks the pairs the backward walks,
+    so its algorithmic FLOP come from keyframe 0's backward census."""
+    r = slr.Renderer(sensor, tiling, capacity=4 << 20)
+    m = (kf["Dt"] > 0).float()
+    buf = torch.empty(43, dtype=torch.float64, device="cuda")
+    a5 = (d["means"], d["quats"], d["log_scales"], d["logits"], kf["T"])
+
+    def one():
+        D, _, _ = r.forward(*a5)
+        r.pose_gn(*a5, D, kf["Dt"], m, 0.0, out=buf)
+
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    slr.stage_timer(True)
+    slr.stage_times()
+    n = max(3, steps // 2)
+    for _ in range(n):
+        one()
+    st = slr.stage_times()
+    slr.stage_timer(False)
+    ms = st["pose_gn"][0] / max(st["pose_gn"][1], 1)
+    flops = BWD_EVAL_FLOPS * census0[2] + GN_CONTRIB_FLOPS * census0[3]
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"workload": "keyframe 0 of the map, 128x1024: render + Gauss-Newton normal equations per iteration",
+            "iter_s": round(steps / dt, 3), "kernel": "raster_gn", "kernel_ms": round(ms, 4),
+            "render_ms": round(sum(st[k][0] for k in ("project", "range_sort", "count_scan", "emit_tile_sort",
+                                                       "raster_fwd")) / n, 4),
+            "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_TFLOPS, 4), "flops_per_launch": int(flops)}
+
+
 def cpu_baseline(sc, sensor, kfs, budget_s):
     """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
     import numpy as np
@@ -168,6 +210,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device-to-device copy first (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gn", action="store_true", help="skip the pose-only Gauss-Newton measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -231,9 +274,11 @@ def main():
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
         torch.cuda.synchronize()
     ef = cf = eb = cb = 0
+    census0 = None
     for r in rend:  # compositing work census (identical in both forms)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
         ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
+        census0 = c if census0 is None else census0
     pairs = int(sum(r.K for r in rend))
     del rend
     torch.cuda.empty_cache()
@@ -302,6 +347,11 @@ def main():
     value = batched_iters if args.form == "batched" else plain_iters
     dt = batched_dt if args.form == "batched" else plain_dt
 
+    gn = None
+    if not args.no_gn:
+        gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar), args.steps, census0)
+        log("pose-only Gauss-Newton:", gn)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -320,7 +370,7 @@ def main():
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
-        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms,
+        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn,
     }
     print(json.dumps(out), flush=True)
 

@@ -158,7 +158,7 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
                         const float *dL_dalpha, float *d_means, float *d_quats, float *d_log_scales,
                         float *d_logits, double *d_pose, uint32_t flags, void *stream);
 
-/* Pose-only Gauss-Newton normal equations of the range image (Sec. 3.3.1:
+/* Pose-only Gauss-Newton normal equations of the range image (Sec. 3.3.3:
  * the keyframe pose is updated as T_wc <- T_wc exp(delta), delta = (rho; phi)
  * in se(3), by Gauss-Newton on Huber-robust residuals).  Reads the workspace
  * left by a successful slr_render with the same surfels, pose, sensor and

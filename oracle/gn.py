@@ -1,7 +1,7 @@
 """Pose-only Gauss-Newton normal equations of a rendered range image (FP64
 oracle; test infrastructure only -- the product path never imports it).
 
-Sec. 3.3.1 (frame-to-model registration): the keyframe pose is updated as
+Sec. 3.3.3 (frame-to-model registration): the keyframe pose is updated as
 T_k^w <- T_k^w exp(delta), delta = (rho; phi) in se(3), by a second-order
 Gauss-Newton method on Huber-robust range residuals.  For the rendered range
 image D(u) of the map at the pose and a target range image D_t(u), with a

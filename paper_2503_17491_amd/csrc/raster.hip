@@ -1107,7 +1107,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     if (lane == 6) pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
 }
 
-// Pose-only Gauss-Newton normal equations (Sec. 3.3.1, T_wc <- T_wc exp(delta)).
+// Pose-only Gauss-Newton normal equations (Sec. 3.3.3, T_wc <- T_wc exp(delta)).
 // The reverse traversal of the backward with a unit upstream range gradient
 // gives every contributing pair's dD/d(s_hat, t) (bwd_step).  Moving the
 // sensor by rho moves the ray origin to rho, turning it by phi turns the ray

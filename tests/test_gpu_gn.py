@@ -1,5 +1,5 @@
 """GPU parity of the pose-only Gauss-Newton normal equations (slr_pose_gn,
-Sec. 3.3.1) through the C ABI.
+Sec. 3.3.3) through the C ABI.
 
 * Against the FP64 oracle (H, g, cost) on a room of overlapping surfels seen
   from a perturbed pose, ragged image (40x136), every tile shape, least

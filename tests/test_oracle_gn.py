@@ -1,4 +1,4 @@
-"""Pins of the oracle's pose-only Gauss-Newton normal equations (Sec. 3.3.1).
+"""Pins of the oracle's pose-only Gauss-Newton normal equations (Sec. 3.3.3).
 
 * The Huber weight against the loss's closed form (value continuity at the
   threshold, w(r) r = rho'(r) by finite differences, least squares for k <= 0).
