@@ -7,3 +7,5 @@ from .oracle import *  # noqa: F401,F403
 from .adam import adam_step  # noqa: F401
 from .loss import loss_l1_normal  # noqa: F401
 from .gn import huber, pose_gn, pose_jacobian  # noqa: F401
+from . import photo  # noqa: F401
+from .photo import photo_gn  # noqa: F401
