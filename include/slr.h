@@ -180,6 +180,30 @@ slr_status slr_pose_gn(const slr_surfels *surfels, const double *pose_cw, const 
                        const float *depth, const float *target, const float *weight, double huber_k,
                        double *normal_eq, void *stream);
 
+/* Photometric registration normal equations (Sec. 3.3.3): every pixel u of
+ * the rendered range image `depth` is back-projected with its range along
+ * its pixel-centre ray, p = D(u) v(u), moved by T into the query sensor's
+ * frame, q = T p, and projected back, u' = phi(q); the query range image is
+ * read at u' by bilinear interpolation of its pixel centres, and
+ *   r = |q| - D_q(u')   (= D(u) - D_q(u') at T = I, the printed residual).
+ * T (device FP64 [4,4], row-major) maps the render's sensor frame to the
+ * query's; the query pose is updated as T_wq <- T_wq exp(delta), i.e.
+ * T <- exp(-delta^) T, and with J = dr/d delta, m the weight (nullable: ones)
+ * and w the Huber IRLS weight (huber_k as in slr_pose_gn):
+ *   H = sum m w J J^T,  g = sum m w r J,  cost = sum m rho(r).
+ * A pixel takes part when D(u) > 0, m != 0, u' lies inside the grid of query
+ * pixel centres (column in [0, W-1), row in [0, H-1)) and the four query
+ * pixels around u' are > 0 (have a return).  Both images share `sensor`
+ * (device FP32 [H,W]).  Output (device FP64, overwritten, 44 values): H
+ * row-major [0..35], g [36..41], cost [42], number of pixels taken [43].
+ * Workspace: device, 256-byte aligned, slr_photo_workspace_size bytes, no
+ * state kept between calls.  Errors: NULL depth, query, pose_qm, normal_eq or
+ * workspace, a workspace too small, NaN huber_k, an invalid sensor. */
+slr_status slr_photo_workspace_size(const slr_sensor *sensor, size_t *bytes);
+slr_status slr_photo_gn(const slr_sensor *sensor, const float *depth, const float *query, const float *weight,
+                        const double *pose_qm, double huber_k, void *workspace, size_t workspace_bytes,
+                        double *normal_eq, void *stream);
+
 /* Device pointers into a workspace filled by slr_render (for inspection and
  * tests). */
 slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n,
@@ -292,8 +316,9 @@ slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *n
  * counts per stage (then resets).  Stages: 0 projection, 1 range sort,
  * 2 count scan, 3 emit + tile sort + ranges, 4 forward compositing,
  * 5 backward compositing, 6 per-surfel gradients, 7 loss, 8 Gauss-Newton
- * compositing.  ms and counts are host arrays of SLR_NUM_STAGES entries. */
-#define SLR_NUM_STAGES 9
+ * compositing, 9 photometric registration.  ms and counts are host arrays
+ * of SLR_NUM_STAGES entries. */
+#define SLR_NUM_STAGES 10
 slr_status slr_stage_timer_enable(int32_t on);
 slr_status slr_stage_times(double *ms, int64_t *counts);
 

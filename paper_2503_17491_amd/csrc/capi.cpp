@@ -557,6 +557,37 @@ slr_status slr_pose_gn(const slr_surfels *surfels, const double *pose_cw, const 
     return SLR_OK;
 }
 
+slr_status slr_photo_workspace_size(const slr_sensor *sensor, size_t *bytes)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (!bytes) return fail(SLR_E_INVALID, "bytes is NULL");
+    *bytes = slr::photo_workspace_bytes(sensor->height, sensor->width);
+    return SLR_OK;
+}
+
+slr_status slr_photo_gn(const slr_sensor *sensor, const float *depth, const float *query, const float *weight,
+                        const double *pose_qm, double huber_k, void *workspace, size_t workspace_bytes,
+                        double *normal_eq, void *stream)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (!depth || !query || !pose_qm || !normal_eq)
+        return fail(SLR_E_INVALID, "depth, query, pose_qm and normal_eq must be set");
+    if (std::isnan(huber_k)) return fail(SLR_E_INVALID, "huber_k is NaN");
+    const size_t need = slr::photo_workspace_bytes(sensor->height, sensor->width);
+    if (!workspace || !aligned(workspace, 256)) return fail(SLR_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < need) return fail(SLR_E_INVALID, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        StageScope t(9, s);
+        slr::launch_photo_gn(sensor->height, sensor->width, sensor->fu, sensor->cu, sensor->fv, sensor->cv, huber_k,
+                             depth, query, weight, pose_qm, reinterpret_cast<double *>(workspace), normal_eq, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
 // ---------------------------------------------------------------- batched form
 slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int32_t n_frames,
                                     const slr_frame *frames, const slr_tiling *tiling, int64_t pair_capacity,

@@ -136,6 +136,10 @@ void launch_loss_l1_normal(int64_t pixels, const float *depth, const float *norm
                            const float *tn, float wd, float wn, float *gD, float *gN, double *loss,
                            hipStream_t stream);
 void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream);
+size_t photo_workspace_bytes(int32_t H, int32_t W);
+void launch_photo_gn(int32_t H, int32_t W, double fu, double cu, double fv, double cv, double huber_k,
+                     const float *depth, const float *query, const float *weight, const double *T, double *part,
+                     double *out, hipStream_t stream);
 void launch_adam(int64_t n, float *means, float *quats, float *ls, float *logits, const float *gm, const float *gq,
                  const float *gl, const float *go, float *m, float *v, const float s[4], float omb1, float b2,
                  float omb2, float c2, float eps, hipStream_t stream);

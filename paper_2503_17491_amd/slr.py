@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(HERE, "libslr.so")
 SLR_OK, SLR_E_INVALID, SLR_E_CAPACITY, SLR_E_HIP, SLR_E_UNSUPPORTED = 0, -1, -2, -3, -4
 SLR_POSE_ONLY = 1
 SLR_ACCUMULATE = 2
-NUM_STAGES = 9
+NUM_STAGES = 10
 STAGES = ["project", "range_sort", "count_scan", "emit_tile_sort", "raster_fwd", "raster_bwd", "surfel_grad", "loss",
-          "pose_gn"]
+          "pose_gn", "photo_gn"]
 
 
 class Sensor(C.Structure):
@@ -59,7 +59,7 @@ class SurfelGrads(C.Structure):
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
            "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
-           "slr_pose_gn", "slr_status_string", "slr_last_error"]
+           "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_status_string", "slr_last_error"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def lib():
         L.slr_backward.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, P, P, P, P, P, C.c_uint32, P]
         L.slr_workspace_views.argtypes = [P, P, I64, I64, P, C.c_size_t, P]
         L.slr_pose_gn.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, D, P, P]
+        L.slr_photo_workspace_size.argtypes = [P, P]
+        L.slr_photo_gn.argtypes = [P, P, P, P, P, D, P, C.c_size_t, P, P]
         BATCH = [I32, P, I32, P, P, I64, P, C.c_size_t]
         L.slr_batch_workspace_size.argtypes = [I32, P, I32, P, P, I64, P]
         L.slr_batch_prepare.argtypes = BATCH + [P]
@@ -95,7 +97,8 @@ def lib():
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
                   "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
-                  "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn"):
+                  "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
+                  "slr_photo_gn"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -404,6 +407,31 @@ class AdamConfig(C.Structure):
     _fields_ = [("lr_means", C.c_double), ("lr_quats", C.c_double), ("lr_log_scales", C.c_double),
                 ("lr_logits", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("step", C.c_int32)]
+
+
+def photo_workspace_size(sensor):
+    s = _sensor(sensor)
+    n = C.c_size_t(0)
+    _check(lib().slr_photo_workspace_size(C.byref(s), C.byref(n)), "slr_photo_workspace_size")
+    return int(n.value)
+
+
+def photo_gn(sensor, depth, query, pose_qm, weight=None, huber_k=0.0, ws=None, out=None):
+    """Photometric registration normal equations (slr_photo_gn): returns
+    (H [6,6], g [6], cost [], count []) as FP64 CUDA tensors (views of one
+    44-value buffer).  depth, query, weight: contiguous FP32 [H,W] CUDA
+    tensors; pose_qm: FP64 [4,4] CUDA tensor (render frame -> query frame)."""
+    for name, a in (("depth", depth), ("query", query), ("weight", weight)):
+        if a is not None and (a.dtype != torch.float32 or not a.is_contiguous()):
+            raise ValueError(f"{name} must be contiguous float32")
+    _pose(pose_qm)
+    if ws is None:
+        ws = torch.empty(photo_workspace_size(sensor), dtype=torch.uint8, device=depth.device)
+    buf = out if out is not None else torch.empty(44, dtype=torch.float64, device=depth.device)
+    s = _sensor(sensor)
+    _check(lib().slr_photo_gn(C.byref(s), _ptr(depth), _ptr(query), _ptr(weight), _ptr(pose_qm), float(huber_k),
+                              _ptr(ws), ws.numel(), _ptr(buf), _stream()), "slr_photo_gn")
+    return buf[:36].view(6, 6), buf[36:42], buf[42], buf[43]
 
 
 def adam_step(params, grads, m, v, lr, step, betas=(0.9, 0.999), eps=1e-15):

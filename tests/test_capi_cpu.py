@@ -139,3 +139,26 @@ def test_pose_gn_rejects_bad_arguments_without_gpu():
     # a workspace too small for the plain form is refused too
     st = L.slr_pose_gn(C.byref(sf), pp, C.byref(s), C.byref(t), wp, 1024, 100, ip, ip, None, 0.0, op, None)
     assert st == slr.SLR_E_INVALID
+
+
+def test_photo_gn_rejects_bad_arguments_without_gpu():
+    L = slr.lib()
+    s = slr._sensor(slr.make_sensor(64, 512))
+    img = np.zeros(64 * 512, np.float32)
+    ip = C.c_void_p(img.ctypes.data)
+    T = np.eye(4)
+    tp = C.c_void_p(T.ctypes.data)
+    out = np.zeros(44)
+    op = C.c_void_p(out.ctypes.data)
+    need = slr.photo_workspace_size(slr.make_sensor(64, 512))
+    assert need >= 8 * 29 * (64 * 512 // 256)
+    big = np.zeros(need + 512, np.uint8)
+    wp = C.c_void_p(big.ctypes.data + (-big.ctypes.data) % 256)
+    for d, q, t, o, k in ((None, ip, tp, op, 0.0), (ip, None, tp, op, 0.0), (ip, ip, None, op, 0.0),
+                          (ip, ip, tp, None, 0.0), (ip, ip, tp, op, float("nan"))):
+        st = L.slr_photo_gn(C.byref(s), d, q, None, t, k, wp, need, o, None)
+        assert st == slr.SLR_E_INVALID
+    st = L.slr_photo_gn(C.byref(s), ip, ip, None, tp, 0.0, wp, need - 8, op, None)
+    assert st == slr.SLR_E_INVALID and b"needs" in L.slr_last_error()
+    st = L.slr_photo_gn(C.byref(s), ip, ip, None, tp, 0.0, None, need, op, None)
+    assert st == slr.SLR_E_INVALID
