@@ -156,6 +156,30 @@ def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
             "frac": round(ach / PEAK_TFLOPS, 4), "flops_per_launch": int(flops)}
 
 
+def measure_photo(torch, slr, sensor, kf, depth, steps):
+    """Photometric registration normal equations on one 128x1024 frame: the
+    rendered range of keyframe 0 against the keyframe's ray-cast scan, the
+    identity as the render-to-query transform."""
+    T = torch.eye(4, dtype=torch.float64, device="cuda")
+    ws = torch.empty(slr.photo_workspace_size(sensor), dtype=torch.uint8, device="cuda")
+    buf = torch.empty(44, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        slr.photo_gn(sensor, depth, kf["Dt"], T, None, 0.1, ws=ws, out=buf)
+    torch.cuda.synchronize()
+    slr.stage_timer(True)
+    slr.stage_times()
+    for _ in range(steps):
+        slr.photo_gn(sensor, depth, kf["Dt"], T, None, 0.1, ws=ws, out=buf)
+    st = slr.stage_times()
+    slr.stage_timer(False)
+    ms = st["photo_gn"][0] / max(st["photo_gn"][1], 1)
+    px = depth.numel()
+    return {"workload": "rendered range of keyframe 0 against its ray-cast scan, 128x1024, Huber 0.1 m",
+            "kernel_ms": round(ms, 4), "pixels_per_s": round(px / (ms * 1e-3), 1),
+            "pixels_taken": int(buf[43].item()),
+            "bound": "latency: 8 B of images per pixel, ~1 MB per launch"}
+
+
 def cpu_baseline(sc, sensor, kfs, budget_s):
     """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
     import numpy as np
@@ -347,10 +371,12 @@ def main():
     value = batched_iters if args.form == "batched" else plain_iters
     dt = batched_dt if args.form == "batched" else plain_dt
 
-    gn = None
+    gn = photo = None
     if not args.no_gn:
         gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar), args.steps, census0)
         log("pose-only Gauss-Newton:", gn)
+        photo = measure_photo(torch, slr, sensor, kfs[0], br.out[0][0], args.steps)
+        log("photometric registration:", photo)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -370,7 +396,7 @@ def main():
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
-        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn,
+        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn, "photo_gn": photo,
     }
     print(json.dumps(out), flush=True)
 
