@@ -9,3 +9,4 @@ from .loss import loss_l1_normal  # noqa: F401
 from .gn import huber, pose_gn, pose_jacobian  # noqa: F401
 from . import photo  # noqa: F401
 from .photo import photo_gn  # noqa: F401
+from . import mapping  # noqa: F401
