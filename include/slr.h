@@ -310,6 +310,46 @@ slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *n
                               const float *target_normal, float w_d, float w_n, float *dL_ddepth,
                               float *dL_dnormal, double *loss, void *stream);
 
+/* Range image of a point cloud (Sec. 3.1, Eq. spherical-projection): each
+ * point (device FP32 [n,3], sensor frame) goes to (u, v) = K psi(p) and lands
+ * in the pixel whose cell contains it, (i, j) = (floor(v), floor(u)) (pixel
+ * centres at (j + 1/2, i + 1/2)); the pixel keeps the nearest return, the
+ * range rounded once to FP32 from sqrt((x^2 + y^2) + z^2) in FP64; pixels
+ * without a point get 0 (the valid mask of Sec. 3.3.1 is range > 0).  Points
+ * with a non-finite coordinate, zero range or outside the image are dropped.
+ * range: device FP32 [H,W], overwritten.  The result does not depend on the
+ * order of the points. */
+slr_status slr_cloud_to_range(const slr_sensor *sensor, int64_t n, const float *points, float *range,
+                              void *stream);
+
+/* Surface normals from the gradients of a range image (the N(D) of L_n,
+ * Sec. 3.3.2): pixels are back-projected along their centre rays, dx and dy
+ * are the central differences of the left/right and upper/lower neighbours,
+ * N = dx x dy / |dx x dy| turned to face the sensor.  Zero on the border rows
+ * and columns and where any of the five pixels has no return (range <= 0).
+ * range: device FP32 [H,W]; normals: device FP32 [H,W,3], overwritten. */
+slr_status slr_range_normals(const slr_sensor *sensor, const float *range, float *normals, void *stream);
+
+/* Refinement losses of Sec. 3.3.2 on the valid pixels M_v = D_t > 0, fused
+ * with their gradients (rho_d = 1):
+ *   L = w_d sum |D - D_t| + w_n sum_{N_t != 0} (1 - N . N_t)
+ *       + w_o sum -log max(O, 1e-6)
+ * N_t is taken as given (e.g. slr_range_normals of a range image); its pixels
+ * without a normal (all zero) are left out of L_n.  Writes dL/dD, dL/dN,
+ * dL/dO (device FP32 [P], [P,3], [P], overwritten; dL/dO = -w_o/O where
+ * O > 1e-6, else 0) and adds L to *loss (device FP64, nullable). */
+slr_status slr_loss_map(int64_t pixels, const float *depth, const float *normal, const float *alpha,
+                        const float *target_depth, const float *target_normal, float w_d, float w_n, float w_o,
+                        float *dL_ddepth, float *dL_dnormal, float *dL_dalpha, double *loss, void *stream);
+
+/* Scale regulariser of Sec. 3.3.2 with its sign corrected (the printed
+ * tau_s - max(s) would reward growth): L_s = w_s sum max(0, max(s_a, s_b) -
+ * tau_s), s = exp(log-scales) (device FP32 [n,2]).  Adds dL/d(log-scales) to
+ * d_log_scales (device FP32 [n,2]; only the larger scale's entry, s_a on a
+ * tie) and L to *loss (device FP64, nullable). */
+slr_status slr_scale_reg(int64_t n, const float *log_scales, double tau_s, double w_s, float *d_log_scales,
+                         double *loss, void *stream);
+
 /* Stage timers: when enabled, the library records HIP events on the
  * caller's stream around each stage it launches; slr_stage_times()
  * synchronises them and returns the accumulated milliseconds and launch

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libslr.so")
 ARCH = os.environ.get("SLR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["project.hip", "binning.hip", "raster.hip", "surfel_grad.hip", "support.hip", "photo.hip"]
+HIP_SOURCES = ["project.hip", "binning.hip", "raster.hip", "surfel_grad.hip", "support.hip", "photo.hip", "mapping.hip"]
 CXX_SOURCES = ["capi.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

@@ -588,6 +588,60 @@ slr_status slr_photo_gn(const slr_sensor *sensor, const float *depth, const floa
     return SLR_OK;
 }
 
+slr_status slr_cloud_to_range(const slr_sensor *sensor, int64_t n, const float *points, float *range, void *stream)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (n < 0) return fail(SLR_E_INVALID, "negative point count");
+    if ((n > 0 && !points) || !range) return fail(SLR_E_INVALID, "points and range must be set");
+    slr::launch_cloud_to_range(sensor->height, sensor->width, sensor->fu, sensor->cu, sensor->fv, sensor->cv, n,
+                               points, range, reinterpret_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_range_normals(const slr_sensor *sensor, const float *range, float *normals, void *stream)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (!range || !normals) return fail(SLR_E_INVALID, "range and normals must be set");
+    slr::launch_range_normals(sensor->height, sensor->width, sensor->fu, sensor->cu, sensor->fv, sensor->cv, range,
+                              normals, reinterpret_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_loss_map(int64_t pixels, const float *depth, const float *normal, const float *alpha,
+                        const float *target_depth, const float *target_normal, float w_d, float w_n, float w_o,
+                        float *dL_ddepth, float *dL_dnormal, float *dL_dalpha, double *loss, void *stream)
+{
+    if (pixels < 0) return fail(SLR_E_INVALID, "negative pixel count");
+    if (pixels > 0 && (!depth || !normal || !alpha || !target_depth || !target_normal || !dL_ddepth || !dL_dnormal ||
+                       !dL_dalpha))
+        return fail(SLR_E_INVALID, "loss buffer is NULL");
+    if (!std::isfinite(w_d) || !std::isfinite(w_n) || !std::isfinite(w_o))
+        return fail(SLR_E_INVALID, "loss weights must be finite");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        StageScope t(7, s);
+        slr::launch_loss_map(pixels, depth, normal, alpha, target_depth, target_normal, w_d, w_n, w_o, dL_ddepth,
+                             dL_dnormal, dL_dalpha, loss, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
+slr_status slr_scale_reg(int64_t n, const float *log_scales, double tau_s, double w_s, float *d_log_scales,
+                         double *loss, void *stream)
+{
+    if (n < 0) return fail(SLR_E_INVALID, "negative surfel count");
+    if (n > 0 && (!log_scales || !d_log_scales)) return fail(SLR_E_INVALID, "log_scales and d_log_scales must be set");
+    if (!std::isfinite(tau_s) || !std::isfinite(w_s)) return fail(SLR_E_INVALID, "tau_s and w_s must be finite");
+    slr::launch_scale_reg(n, log_scales, tau_s, w_s, d_log_scales, loss, reinterpret_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
 // ---------------------------------------------------------------- batched form
 slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int32_t n_frames,
                                     const slr_frame *frames, const slr_tiling *tiling, int64_t pair_capacity,

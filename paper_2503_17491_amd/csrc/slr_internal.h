@@ -137,6 +137,13 @@ void launch_loss_l1_normal(int64_t pixels, const float *depth, const float *norm
                            hipStream_t stream);
 void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream);
 size_t photo_workspace_bytes(int32_t H, int32_t W);
+void launch_cloud_to_range(int32_t H, int32_t W, double fu, double cu, double fv, double cv, int64_t n,
+                           const float *pts, float *range, hipStream_t stream);
+void launch_range_normals(int32_t H, int32_t W, double fu, double cu, double fv, double cv, const float *range,
+                          float *normals, hipStream_t stream);
+void launch_loss_map(int64_t P, const float *D, const float *N, const float *O, const float *Dt, const float *Nt,
+                     float wd, float wn, float wo, float *gD, float *gN, float *gO, double *loss, hipStream_t stream);
+void launch_scale_reg(int64_t n, const float *ls, double tau, double ws, float *g, double *loss, hipStream_t stream);
 void launch_photo_gn(int32_t H, int32_t W, double fu, double cu, double fv, double cv, double huber_k,
                      const float *depth, const float *query, const float *weight, const double *T, double *part,
                      double *out, hipStream_t stream);

@@ -59,7 +59,8 @@ class SurfelGrads(C.Structure):
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
            "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
-           "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_status_string", "slr_last_error"]
+           "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
+           "slr_scale_reg", "slr_status_string", "slr_last_error"]
 
 _lib = None
 
@@ -80,6 +81,10 @@ def lib():
         L.slr_pose_gn.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, D, P, P]
         L.slr_photo_workspace_size.argtypes = [P, P]
         L.slr_photo_gn.argtypes = [P, P, P, P, P, D, P, C.c_size_t, P, P]
+        L.slr_cloud_to_range.argtypes = [P, I64, P, P, P]
+        L.slr_range_normals.argtypes = [P, P, P, P]
+        L.slr_loss_map.argtypes = [I64, P, P, P, P, P, C.c_float, C.c_float, C.c_float, P, P, P, P, P]
+        L.slr_scale_reg.argtypes = [I64, P, D, D, P, P, P]
         BATCH = [I32, P, I32, P, P, I64, P, C.c_size_t]
         L.slr_batch_workspace_size.argtypes = [I32, P, I32, P, P, I64, P]
         L.slr_batch_prepare.argtypes = BATCH + [P]
@@ -98,7 +103,7 @@ def lib():
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
                   "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
                   "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
-                  "slr_photo_gn"):
+                  "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -407,6 +412,41 @@ class AdamConfig(C.Structure):
     _fields_ = [("lr_means", C.c_double), ("lr_quats", C.c_double), ("lr_log_scales", C.c_double),
                 ("lr_logits", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("step", C.c_int32)]
+
+
+def cloud_to_range(sensor, points, out=None):
+    """Range image [H,W] (FP32 CUDA) of a sensor-frame point cloud [n,3] (slr_cloud_to_range)."""
+    if points.dtype != torch.float32 or not points.is_contiguous() or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be a contiguous float32 [n, 3] tensor")
+    H, W = int(sensor["height"]), int(sensor["width"])
+    out = out if out is not None else torch.empty((H, W), dtype=torch.float32, device=points.device)
+    s = _sensor(sensor)
+    _check(lib().slr_cloud_to_range(C.byref(s), points.shape[0], _ptr(points), _ptr(out), _stream()),
+           "slr_cloud_to_range")
+    return out
+
+
+def range_normals(sensor, range_image, out=None):
+    """Normals [H,W,3] (FP32 CUDA) from the gradients of a range image (slr_range_normals)."""
+    if range_image.dtype != torch.float32 or not range_image.is_contiguous():
+        raise ValueError("range_image must be contiguous float32")
+    H, W = int(sensor["height"]), int(sensor["width"])
+    out = out if out is not None else torch.empty((H, W, 3), dtype=torch.float32, device=range_image.device)
+    s = _sensor(sensor)
+    _check(lib().slr_range_normals(C.byref(s), _ptr(range_image), _ptr(out), _stream()), "slr_range_normals")
+    return out
+
+
+def loss_map(D, N, O, Dt, Nt, w_d, w_n, w_o, gD, gN, gO, loss=None):
+    """Fused L_d + L_n + L_o and their gradients (slr_loss_map; writes gD, gN, gO, adds to loss)."""
+    _check(lib().slr_loss_map(D.numel(), _ptr(D), _ptr(N), _ptr(O), _ptr(Dt), _ptr(Nt), float(w_d), float(w_n),
+                              float(w_o), _ptr(gD), _ptr(gN), _ptr(gO), _ptr(loss), _stream()), "slr_loss_map")
+
+
+def scale_reg(log_scales, tau_s, w_s, d_log_scales, loss=None):
+    """Scale cap L_s (slr_scale_reg): adds its gradient to d_log_scales and its value to loss."""
+    _check(lib().slr_scale_reg(log_scales.shape[0], _ptr(log_scales), float(tau_s), float(w_s), _ptr(d_log_scales),
+                               _ptr(loss), _stream()), "slr_scale_reg")
 
 
 def photo_workspace_size(sensor):
