@@ -131,3 +131,102 @@ def scale_reg(log_scales, tau_s, w_s):
     g[over & first, 0] = w_s * smax[over & first]
     g[over & ~first, 1] = w_s * smax[over & ~first]
     return L, g
+
+
+# ---------------------------------------------------------------------------
+# Local model initialisation (Sec. 3.3.1): a weight map from the range
+# gradients over the valid pixels, weighted sampling of n_d pixels, splats
+# back-projected from them with their normals facing the sensor.
+#
+#   gx = (D(i, j+1) - D(i, j-1)) / 2,  gy = (D(i+1, j) - D(i-1, j)) / 2  (FP32,
+#        zero on the border or next to a pixel without a return)
+#   weight(u) = 0 where D(u) <= 0 or the caller's mask is 0, else
+#               floor(256 (|gx| + |gy|)) + 1 (an integer: 1 on flat ground,
+#               more across edges), capped at 2^24
+#   cum = inclusive prefix sum of the weights (exact integers)
+#   sample k: t = floor(U_k total) (FP64), the first pixel with cum > t
+#   splat: mean = T_wc (D v), normal n = -R_wc v, tangents t_a = normalize(n x
+#          e), e = world z unless |n_z| > 0.9 (then world x), t_b = n x t_a,
+#          quaternion (w >= 0) of R = (t_a t_b n), both scales D theta_px k
+#          (theta_px the larger angular pixel pitch), the given logit.
+# ---------------------------------------------------------------------------
+WEIGHT_CAP = 1 << 24
+
+
+def init_weights(D, mask=None):
+    D = np.asarray(D, np.float32)
+    H, W = D.shape
+    m = np.ones((H, W), np.float32) if mask is None else np.asarray(mask, np.float32)
+    w = np.zeros((H, W), np.int64)
+    valid = (D > 0) & (m != 0)
+    gx = np.zeros((H, W), np.float32)
+    gy = np.zeros((H, W), np.float32)
+    inner = np.zeros((H, W), bool)
+    inner[1:-1, 1:-1] = ((D[1:-1, 2:] > 0) & (D[1:-1, :-2] > 0) & (D[2:, 1:-1] > 0) & (D[:-2, 1:-1] > 0))
+    half = np.float32(0.5)
+    gx[1:-1, 1:-1] = (D[1:-1, 2:] - D[1:-1, :-2]) * half
+    gy[1:-1, 1:-1] = (D[2:, 1:-1] - D[:-2, 1:-1]) * half
+    g = np.where(inner, np.abs(gx) + np.abs(gy), np.float32(0)).astype(np.float32)
+    q = np.floor(g * np.float32(256.0)).astype(np.float64)
+    w[valid] = np.minimum(q[valid], WEIGHT_CAP).astype(np.int64) + 1
+    return w
+
+
+def quat_from_rot(R):
+    """(w, x, y, z), w >= 0, of a rotation matrix (Shepperd's method)."""
+    t = R[0, 0] + R[1, 1] + R[2, 2]
+    if t > 0:
+        s = 2.0 * np.sqrt(1.0 + t)
+        q = np.array([0.25 * s, (R[2, 1] - R[1, 2]) / s, (R[0, 2] - R[2, 0]) / s, (R[1, 0] - R[0, 1]) / s])
+    elif R[0, 0] > R[1, 1] and R[0, 0] > R[2, 2]:
+        s = 2.0 * np.sqrt(1.0 + R[0, 0] - R[1, 1] - R[2, 2])
+        q = np.array([(R[2, 1] - R[1, 2]) / s, 0.25 * s, (R[0, 1] + R[1, 0]) / s, (R[0, 2] + R[2, 0]) / s])
+    elif R[1, 1] > R[2, 2]:
+        s = 2.0 * np.sqrt(1.0 + R[1, 1] - R[0, 0] - R[2, 2])
+        q = np.array([(R[0, 2] - R[2, 0]) / s, (R[0, 1] + R[1, 0]) / s, 0.25 * s, (R[1, 2] + R[2, 1]) / s])
+    else:
+        s = 2.0 * np.sqrt(1.0 + R[2, 2] - R[0, 0] - R[1, 1])
+        q = np.array([(R[1, 0] - R[0, 1]) / s, (R[0, 2] + R[2, 0]) / s, (R[1, 2] + R[2, 1]) / s, 0.25 * s])
+    return q if q[0] >= 0 else -q
+
+
+def init_splats(sensor, D, T_cw, uniforms, mask=None, scale_factor=1.0, logit=0.0):
+    """Returns dict pixel [n] (-1 when no pixel has weight), means [n,3],
+    quats [n,4], log_scales [n,2], logits [n] (FP32) and the weights."""
+    D = np.asarray(D, np.float32)
+    H, W = D.shape
+    w = init_weights(D, mask).reshape(-1)
+    cum = np.cumsum(w)
+    total = int(cum[-1]) if cum.size else 0
+    U = np.asarray(uniforms, np.float64).reshape(-1)
+    n = U.size
+    out = dict(pixel=np.full(n, -1, np.int32), means=np.zeros((n, 3), np.float32),
+               quats=np.zeros((n, 4), np.float32), log_scales=np.zeros((n, 2), np.float32),
+               logits=np.zeros(n, np.float32), weights=w.reshape(H, W))
+    if total == 0:
+        return out
+    t = np.floor(U * float(total)).astype(np.int64)
+    idx = np.searchsorted(cum, t, side="right")
+    T_cw = np.asarray(T_cw, np.float64)
+    Rwc = T_cw[:3, :3].T
+    twc = -Rwc @ T_cw[:3, 3]
+    pitch = max(abs(1.0 / sensor["fu"]), abs(1.0 / sensor["fv"]))
+    for k in range(n):
+        p = int(idx[k])
+        i, j = divmod(p, W)
+        az = (j + 0.5 - sensor["cu"]) / sensor["fu"]
+        el = (i + 0.5 - sensor["cv"]) / sensor["fv"]
+        v = np.array([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+        d = float(D[i, j])
+        nrm = -(Rwc @ v)
+        e = np.array([1.0, 0.0, 0.0]) if abs(nrm[2]) > 0.9 else np.array([0.0, 0.0, 1.0])
+        ta = np.cross(nrm, e)
+        ta /= np.linalg.norm(ta)
+        tb = np.cross(nrm, ta)
+        R = np.stack([ta, tb, nrm], 1)
+        out["pixel"][k] = p
+        out["means"][k] = Rwc @ (d * v) + twc
+        out["quats"][k] = quat_from_rot(R)
+        out["log_scales"][k] = np.log(d * pitch * scale_factor)
+        out["logits"][k] = logit
+    return out

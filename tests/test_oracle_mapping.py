@@ -125,3 +125,71 @@ def test_scale_reg_closed_form_and_fd():
         fd = (O.mapping.scale_reg(ls + d, 0.25, 2.0)[0] - O.mapping.scale_reg(ls - d, 0.25, 2.0)[0]) / (2 * e)
         if k != 3:  # the tie at [3] has a kink
             assert abs(fd - g[k, c]) < 1e-5, (k, c, fd, g[k, c])
+
+
+def test_init_weights_on_a_ramp():
+    ii, jj = np.meshgrid(np.arange(10), np.arange(20), indexing="ij")
+    D = (5.0 + 0.125 * jj).astype(np.float32)          # gx = 0.125 exactly, gy = 0
+    D[4, 7] = 0.0
+    w = O.mapping.init_weights(D)
+    assert w[4, 7] == 0
+    # interior pixels away from the hole: floor(256 * 0.125) + 1 = 33; border and next to the hole: 1
+    assert w[2, 2] == 33 and w[0, 5] == 1 and w[9, 5] == 1 and w[5, 0] == 1 and w[5, 19] == 1
+    assert w[4, 6] == 1 and w[4, 8] == 1 and w[3, 7] == 1 and w[5, 7] == 1
+    mask = np.ones_like(D)
+    mask[:, :10] = 0
+    wm = O.mapping.init_weights(D, mask)
+    assert not wm[:, :10].any() and (wm[:, 11:19][1:-1] == 33).all()
+
+
+def test_init_sampling_by_brute_force_and_frequency():
+    s = O.make_sensor(12, 40)
+    g = np.random.default_rng(5)
+    D = g.uniform(2.0, 10.0, (12, 40)).astype(np.float32)
+    D[g.uniform(size=D.shape) < 0.2] = 0.0
+    U = g.uniform(size=4000)
+    out = O.mapping.init_splats(s, D, np.eye(4), U)
+    w = out["weights"].reshape(-1)
+    total = int(w.sum())
+    for k in range(200):   # brute force: the pixel whose interval holds floor(U total)
+        t = int(np.floor(U[k] * total))
+        acc = 0
+        for p, wp in enumerate(w):
+            if acc <= t < acc + wp:
+                break
+            acc += wp
+        assert out["pixel"][k] == p
+    freq = np.bincount(out["pixel"], minlength=w.size)
+    expect = U.size * w / total
+    big = expect > 20
+    assert np.abs(freq[big] - expect[big]).max() < 5 * np.sqrt(expect[big]).max()
+    assert (freq[w == 0] == 0).all()
+
+
+def test_init_splats_geometry():
+    s = O.make_sensor(12, 40)
+    g = np.random.default_rng(6)
+    D = g.uniform(2.0, 10.0, (12, 40)).astype(np.float32)
+    T_cw = h.perturb_cw(np.eye(4), np.array([0.5, -0.2, 0.1, 0.1, -0.2, 0.3]))
+    out = O.mapping.init_splats(s, D, T_cw, g.uniform(size=300), scale_factor=1.5, logit=-0.5)
+    Twc = np.linalg.inv(T_cw)
+    pitch = max(abs(1 / s["fu"]), abs(1 / s["fv"]))
+    for k in range(300):
+        p = out["pixel"][k]
+        i, j = divmod(int(p), 40)
+        mu = out["means"][k].astype(np.float64)
+        ps = T_cw[:3, :3] @ mu + T_cw[:3, 3]                 # back in the sensor frame
+        u, v = h.project(s, ps)
+        assert abs(u - (j + 0.5)) < 1e-4 and abs(v - (i + 0.5)) < 1e-4
+        assert abs(np.linalg.norm(ps) - D[i, j]) < 1e-5 * D[i, j]
+        q = out["quats"][k].astype(np.float64)
+        assert abs(np.linalg.norm(q) - 1) < 1e-6 and q[0] >= 0
+        R = h.rot_from_quat_wxyz(q)
+        n = R[:, 2]
+        assert np.dot(n, mu - Twc[:3, 3]) < 0                  # faces the sensor
+        np.testing.assert_allclose(n, -(Twc[:3, :3] @ h.ray_dir(s, i, j)), atol=1e-6)
+        np.testing.assert_allclose(out["log_scales"][k], math.log(float(D[i, j]) * pitch * 1.5), rtol=1e-6,
+                                   atol=1e-7)
+        assert out["logits"][k] == np.float32(-0.5)
+    empty = O.mapping.init_splats(s, np.zeros((12, 40), np.float32), T_cw, [0.3, 0.7])
+    assert (empty["pixel"] == -1).all() and not empty["means"].any()
