@@ -144,7 +144,7 @@ def scale_reg(log_scales, tau_s, w_s):
 #               floor(256 (|gx| + |gy|)) + 1 (an integer: 1 on flat ground,
 #               more across edges), capped at 2^24
 #   cum = inclusive prefix sum of the weights (exact integers)
-#   sample k: t = floor(U_k total) (FP64), the first pixel with cum > t
+#   sample k: t = min(floor(U_k total) (FP64), total - 1), the first pixel with cum > t
 #   splat: mean = T_wc (D v), normal n = -R_wc v, tangents t_a = normalize(n x
 #          e), e = world z unless |n_z| > 0.9 (then world x), t_b = n x t_a,
 #          quaternion (w >= 0) of R = (t_a t_b n), both scales D theta_px k
@@ -205,7 +205,8 @@ def init_splats(sensor, D, T_cw, uniforms, mask=None, scale_factor=1.0, logit=0.
                logits=np.zeros(n, np.float32), weights=w.reshape(H, W))
     if total == 0:
         return out
-    t = np.floor(U * float(total)).astype(np.int64)
+    # U total can round up to total for U within an ulp of 1: the draw stays on the last pixel
+    t = np.minimum(np.floor(U * float(total)).astype(np.int64), total - 1)
     idx = np.searchsorted(cum, t, side="right")
     T_cw = np.asarray(T_cw, np.float64)
     Rwc = T_cw[:3, :3].T

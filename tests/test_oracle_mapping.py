@@ -191,5 +191,7 @@ def test_init_splats_geometry():
         np.testing.assert_allclose(out["log_scales"][k], math.log(float(D[i, j]) * pitch * 1.5), rtol=1e-6,
                                    atol=1e-7)
         assert out["logits"][k] == np.float32(-0.5)
+    last = O.mapping.init_splats(s, D, T_cw, [np.nextafter(1.0, 0.0)])
+    assert last["pixel"][0] == 12 * 40 - 1
     empty = O.mapping.init_splats(s, np.zeros((12, 40), np.float32), T_cw, [0.3, 0.7])
     assert (empty["pixel"] == -1).all() and not empty["means"].any()
