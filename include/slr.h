@@ -350,6 +350,32 @@ slr_status slr_loss_map(int64_t pixels, const float *depth, const float *normal,
 slr_status slr_scale_reg(int64_t n, const float *log_scales, double tau_s, double w_s, float *d_log_scales,
                          double *loss, void *stream);
 
+/* Local model initialisation (Sec. 3.3.1): a weight map from the range
+ * gradients over the valid pixels and a weighted draw of n pixels, each
+ * back-projected into a splat whose normal faces the sensor.
+ *   weight(u) = 0 where range(u) <= 0 or mask(u) == 0 (mask nullable: ones),
+ *               else floor(256 (|gx| + |gy|)) + 1 capped at 2^24 + 1, with
+ *               gx, gy the FP32 central differences of the range image (0 on
+ *               the border and next to a pixel without a return);
+ *   draw k: t = min(floor(uniforms[k] * total), total - 1) over the exact
+ *           integer prefix sums of the weights; the first pixel whose running
+ *           sum exceeds t (uniforms: device FP64 [n] in [0, 1), the caller's
+ *           random numbers);
+ *   splat: mean T_wc (D v) (pose_cw: device FP64 [4,4] T_cw), normal
+ *          n = -R_wc v, tangents t_a = normalize(n x e) with e the world z axis
+ *          (x when |n_z| > 0.9) and t_b = n x t_a, quaternion (w,x,y,z), w >= 0,
+ *          of (t_a t_b n); both log-scales log(D pitch scale_factor) with
+ *          pitch the larger angular pixel pitch; logit as given.
+ * Outputs (device): means [n,3], quats [n,4], log_scales [n,2], logits [n]
+ * FP32 and pixel [n] int32 (the drawn pixel, row-major; -1 and zeros for
+ * every draw when no pixel has weight).  Workspace: device, 256-byte
+ * aligned, slr_init_workspace_size bytes. */
+slr_status slr_init_workspace_size(const slr_sensor *sensor, size_t *bytes);
+slr_status slr_init_splats(const slr_sensor *sensor, const float *range, const float *mask, const double *pose_cw,
+                           int64_t n, const double *uniforms, double scale_factor, float logit, void *workspace,
+                           size_t workspace_bytes, float *means, float *quats, float *log_scales, float *logits,
+                           int32_t *pixel, void *stream);
+
 /* Stage timers: when enabled, the library records HIP events on the
  * caller's stream around each stage it launches; slr_stage_times()
  * synchronises them and returns the accumulated milliseconds and launch

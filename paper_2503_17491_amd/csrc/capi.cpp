@@ -642,6 +642,38 @@ slr_status slr_scale_reg(int64_t n, const float *log_scales, double tau_s, doubl
     return SLR_OK;
 }
 
+slr_status slr_init_workspace_size(const slr_sensor *sensor, size_t *bytes)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (!bytes) return fail(SLR_E_INVALID, "bytes is NULL");
+    *bytes = slr::init_workspace_bytes(sensor->height, sensor->width);
+    return SLR_OK;
+}
+
+slr_status slr_init_splats(const slr_sensor *sensor, const float *range, const float *mask, const double *pose_cw,
+                           int64_t n, const double *uniforms, double scale_factor, float logit, void *workspace,
+                           size_t workspace_bytes, float *means, float *quats, float *log_scales, float *logits,
+                           int32_t *pixel, void *stream)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (n < 0) return fail(SLR_E_INVALID, "negative draw count");
+    if (!range || !pose_cw) return fail(SLR_E_INVALID, "range and pose_cw must be set");
+    if (n > 0 && (!uniforms || !means || !quats || !log_scales || !logits || !pixel))
+        return fail(SLR_E_INVALID, "uniforms and every output must be set");
+    if (!(scale_factor > 0.0) || !std::isfinite(scale_factor)) return fail(SLR_E_INVALID, "scale_factor must be > 0");
+    if (!std::isfinite(logit)) return fail(SLR_E_INVALID, "logit must be finite");
+    const size_t need = slr::init_workspace_bytes(sensor->height, sensor->width);
+    if (!workspace || !aligned(workspace, 256)) return fail(SLR_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < need) return fail(SLR_E_INVALID, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    slr::launch_init_splats(sensor->height, sensor->width, sensor->fu, sensor->cu, sensor->fv, sensor->cv, range, mask,
+                            pose_cw, n, uniforms, scale_factor, logit, reinterpret_cast<char *>(workspace), means, quats,
+                            log_scales, logits, pixel, reinterpret_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
 // ---------------------------------------------------------------- batched form
 slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int32_t n_frames,
                                     const slr_frame *frames, const slr_tiling *tiling, int64_t pair_capacity,

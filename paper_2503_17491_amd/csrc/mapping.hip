@@ -163,6 +163,182 @@ k_scale_reg(int64_t n, const float *__restrict__ ls, double tau, double ws, floa
     if (loss) block_add(part, loss);
 }
 
+// ---- local model initialisation (Sec. 3.3.1) ----
+// Integer weights from the range gradients (FP32 central differences, exact
+// IEEE operations, no square root) over the valid pixels:
+// floor(256 (|gx| + |gy|)) + 1, capped; 0 without a return or where the mask is 0.
+__global__ void __launch_bounds__(256)
+k_init_weights(MapSensor s, const float *__restrict__ D, const float *__restrict__ mask, uint32_t *__restrict__ w)
+{
+    const int64_t npix = (int64_t)s.H * s.W;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const int i = (int)(p / s.W), j = (int)(p - (int64_t)i * s.W);
+    const float d = D[p];
+    const bool valid = d > 0.f && (!mask || mask[p] != 0.f);
+    uint32_t out = 0;
+    if (valid) {
+        float g = 0.f;
+        if (i > 0 && i < s.H - 1 && j > 0 && j < s.W - 1) {
+            const float dl = D[p - 1], dr = D[p + 1], du = D[p - s.W], dd = D[p + s.W];
+            if (dl > 0.f && dr > 0.f && du > 0.f && dd > 0.f) {
+                const float gx = (dr - dl) * 0.5f, gy = (dd - du) * 0.5f;
+                g = fabsf(gx) + fabsf(gy);
+            }
+        }
+        const float q = fminf(floorf(g * 256.0f), 16777216.0f);
+        out = (uint32_t)q + 1u;
+    }
+    w[p] = out;
+}
+
+constexpr int kScanPer = 1024;   // items per scan block (256 threads x 4)
+
+__device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t *sh)
+{
+    // inclusive scan over the 256 threads of a block (Hillis-Steele in LDS)
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint64_t add = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    return sh[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_sums(const uint32_t *__restrict__ w, int64_t n, uint64_t *__restrict__ bsum)
+{
+    __shared__ uint64_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPer + 4 * threadIdx.x;
+    uint64_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (base + e < n) v += w[base + e];
+    const uint64_t inc = block_incl_scan(v, sh);
+    if (threadIdx.x == 255) bsum[blockIdx.x] = inc;
+}
+
+// exclusive prefix of the block sums, in place (one block, chunks of 256)
+__global__ void __launch_bounds__(256) k_scan_bsums(uint64_t *__restrict__ bsum, int64_t nb)
+{
+    __shared__ uint64_t sh[256];
+    uint64_t carry = 0;
+    for (int64_t c = 0; c < nb; c += 256) {
+        const int64_t k = c + threadIdx.x;
+        const uint64_t v = k < nb ? bsum[k] : 0;
+        const uint64_t inc = block_incl_scan(v, sh);
+        if (k < nb) bsum[k] = carry + inc - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_final(const uint32_t *__restrict__ w, int64_t n, const uint64_t *__restrict__ bexcl, uint64_t *__restrict__ cum)
+{
+    __shared__ uint64_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPer + 4 * threadIdx.x;
+    uint64_t x[4];
+    uint64_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        x[e] = base + e < n ? w[base + e] : 0;
+        v += x[e];
+    }
+    const uint64_t inc = block_incl_scan(v, sh);
+    uint64_t run = bexcl[blockIdx.x] + inc - v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        run += x[e];
+        if (base + e < n) cum[base + e] = run;
+    }
+}
+
+__device__ void quat_from_rot(const double R[3][3], double q[4])
+{
+    const double t = R[0][0] + R[1][1] + R[2][2];
+    if (t > 0.0) {
+        const double s = 2.0 * sqrt(1.0 + t);
+        q[0] = 0.25 * s; q[1] = (R[2][1] - R[1][2]) / s; q[2] = (R[0][2] - R[2][0]) / s; q[3] = (R[1][0] - R[0][1]) / s;
+    } else if (R[0][0] > R[1][1] && R[0][0] > R[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + R[0][0] - R[1][1] - R[2][2]);
+        q[0] = (R[2][1] - R[1][2]) / s; q[1] = 0.25 * s; q[2] = (R[0][1] + R[1][0]) / s; q[3] = (R[0][2] + R[2][0]) / s;
+    } else if (R[1][1] > R[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + R[1][1] - R[0][0] - R[2][2]);
+        q[0] = (R[0][2] - R[2][0]) / s; q[1] = (R[0][1] + R[1][0]) / s; q[2] = 0.25 * s; q[3] = (R[1][2] + R[2][1]) / s;
+    } else {
+        const double s = 2.0 * sqrt(1.0 + R[2][2] - R[0][0] - R[1][1]);
+        q[0] = (R[1][0] - R[0][1]) / s; q[1] = (R[0][2] + R[2][0]) / s; q[2] = (R[1][2] + R[2][1]) / s; q[3] = 0.25 * s;
+    }
+    if (q[0] < 0.0) { q[0] = -q[0]; q[1] = -q[1]; q[2] = -q[2]; q[3] = -q[3]; }
+}
+
+// One draw per thread: t = min(floor(U total), total - 1), the first pixel
+// whose running weight exceeds t (binary search), and its splat: mean
+// T_wc (D v), normal -R_wc v facing the sensor, tangents from the world z
+// axis (x when the normal is within acos 0.9 of z), both scales
+// D * pitch * scale_factor, the given logit.
+__global__ void __launch_bounds__(256)
+k_init_sample(int64_t n, const double *__restrict__ U, const uint64_t *__restrict__ cum, MapSensor s,
+              const float *__restrict__ D, const double *__restrict__ Tcw, double scale, float logit,
+              float *__restrict__ means, float *__restrict__ quats, float *__restrict__ ls,
+              float *__restrict__ logits, int32_t *__restrict__ pix)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t npix = (int64_t)s.H * s.W;
+    const uint64_t total = npix > 0 ? cum[npix - 1] : 0;
+    if (total == 0) {
+        pix[k] = -1;
+        means[3 * k] = means[3 * k + 1] = means[3 * k + 2] = 0.f;
+        quats[4 * k] = quats[4 * k + 1] = quats[4 * k + 2] = quats[4 * k + 3] = 0.f;
+        ls[2 * k] = ls[2 * k + 1] = 0.f;
+        logits[k] = 0.f;
+        return;
+    }
+    uint64_t t = (uint64_t)floor(U[k] * (double)total);
+    if (t > total - 1) t = total - 1;
+    int64_t lo = 0, hi = npix - 1;     // first index with cum > t (exists: cum[npix-1] = total > t)
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cum[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    const int i = (int)(lo / s.W), j = (int)(lo - (int64_t)i * s.W);
+    const double az = ((double)j + 0.5 - s.cu) / s.fu, el = ((double)i + 0.5 - s.cv) / s.fv;
+    double sa, ca, se, ce;
+    sincos(az, &sa, &ca);
+    sincos(el, &se, &ce);
+    const double v[3] = {ce * ca, ce * sa, se};
+    const double d = D[lo];
+    double Rwc[3][3], twc[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Rwc[r][c] = Tcw[4 * c + r];
+    for (int r = 0; r < 3; ++r) twc[r] = -(Rwc[r][0] * Tcw[3] + Rwc[r][1] * Tcw[7] + Rwc[r][2] * Tcw[11]);
+    double nrm[3], mu[3];
+    for (int r = 0; r < 3; ++r) {
+        mu[r] = (Rwc[r][0] * (d * v[0]) + Rwc[r][1] * (d * v[1]) + Rwc[r][2] * (d * v[2])) + twc[r];
+        nrm[r] = -(Rwc[r][0] * v[0] + Rwc[r][1] * v[1] + Rwc[r][2] * v[2]);
+    }
+    const double e[3] = {fabs(nrm[2]) > 0.9 ? 1.0 : 0.0, 0.0, fabs(nrm[2]) > 0.9 ? 0.0 : 1.0};
+    double ta[3] = {nrm[1] * e[2] - nrm[2] * e[1], nrm[2] * e[0] - nrm[0] * e[2], nrm[0] * e[1] - nrm[1] * e[0]};
+    const double tn = sqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
+    ta[0] /= tn; ta[1] /= tn; ta[2] /= tn;
+    const double tb[3] = {nrm[1] * ta[2] - nrm[2] * ta[1], nrm[2] * ta[0] - nrm[0] * ta[2], nrm[0] * ta[1] - nrm[1] * ta[0]};
+    const double R[3][3] = {{ta[0], tb[0], nrm[0]}, {ta[1], tb[1], nrm[1]}, {ta[2], tb[2], nrm[2]}};
+    double q[4];
+    quat_from_rot(R, q);
+    const double pitch = fmax(fabs(1.0 / s.fu), fabs(1.0 / s.fv));
+    const float lsc = (float)log(d * pitch * scale);
+    pix[k] = (int32_t)lo;
+    means[3 * k] = (float)mu[0]; means[3 * k + 1] = (float)mu[1]; means[3 * k + 2] = (float)mu[2];
+    quats[4 * k] = (float)q[0]; quats[4 * k + 1] = (float)q[1]; quats[4 * k + 2] = (float)q[2]; quats[4 * k + 3] = (float)q[3];
+    ls[2 * k] = lsc; ls[2 * k + 1] = lsc;
+    logits[k] = logit;
+}
+
 int grid_for(int64_t n)
 {
     const int64_t b = (n + 255) / 256;
@@ -199,6 +375,34 @@ void launch_loss_map(int64_t P, const float *D, const float *N, const float *O, 
     if (P == 0) return;
     hipLaunchKernelGGL(k_loss_map, dim3(grid_for(P)), dim3(256), 0, stream, P, D, N, O, Dt, Nt, wd, wn, wo, gD, gN,
                        gO, loss);
+}
+
+size_t init_workspace_bytes(int32_t H, int32_t W)
+{
+    const int64_t n = (int64_t)H * W, nb = (n + kScanPer - 1) / kScanPer;
+    const size_t a = ((4 * (size_t)n + 255) / 256) * 256, b = ((8 * (size_t)n + 255) / 256) * 256;
+    return a + b + 8 * (size_t)(nb > 0 ? nb : 1);
+}
+
+void launch_init_splats(int32_t H, int32_t W, double fu, double cu, double fv, double cv, const float *range,
+                        const float *mask, const double *Tcw, int64_t n, const double *U, double scale, float logit,
+                        char *ws, float *means, float *quats, float *ls, float *logits, int32_t *pix,
+                        hipStream_t stream)
+{
+    const int64_t npix = (int64_t)H * W, nb = (npix + kScanPer - 1) / kScanPer;
+    MapSensor s{fu, cu, fv, cv, H, W};
+    uint32_t *w = reinterpret_cast<uint32_t *>(ws);
+    uint64_t *cum = reinterpret_cast<uint64_t *>(ws + ((4 * (size_t)npix + 255) / 256) * 256);
+    uint64_t *bsum = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(cum) + ((8 * (size_t)npix + 255) / 256) * 256);
+    if (npix > 0) {
+        hipLaunchKernelGGL(k_init_weights, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, s, range, mask, w);
+        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, stream, w, npix, bsum);
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(256), 0, stream, bsum, nb);
+        hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, stream, w, npix, bsum, cum);
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(k_init_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, U, cum, s, range,
+                           Tcw, scale, logit, means, quats, ls, logits, pix);
 }
 
 void launch_scale_reg(int64_t n, const float *ls, double tau, double ws, float *g, double *loss, hipStream_t stream)

@@ -144,6 +144,11 @@ void launch_range_normals(int32_t H, int32_t W, double fu, double cu, double fv,
 void launch_loss_map(int64_t P, const float *D, const float *N, const float *O, const float *Dt, const float *Nt,
                      float wd, float wn, float wo, float *gD, float *gN, float *gO, double *loss, hipStream_t stream);
 void launch_scale_reg(int64_t n, const float *ls, double tau, double ws, float *g, double *loss, hipStream_t stream);
+size_t init_workspace_bytes(int32_t H, int32_t W);
+void launch_init_splats(int32_t H, int32_t W, double fu, double cu, double fv, double cv, const float *range,
+                        const float *mask, const double *Tcw, int64_t n, const double *U, double scale, float logit,
+                        char *ws, float *means, float *quats, float *ls, float *logits, int32_t *pix,
+                        hipStream_t stream);
 void launch_photo_gn(int32_t H, int32_t W, double fu, double cu, double fv, double cv, double huber_k,
                      const float *depth, const float *query, const float *weight, const double *T, double *part,
                      double *out, hipStream_t stream);

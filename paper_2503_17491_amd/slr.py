@@ -60,7 +60,7 @@ EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backwar
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
            "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
            "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
-           "slr_scale_reg", "slr_status_string", "slr_last_error"]
+           "slr_scale_reg", "slr_init_workspace_size", "slr_init_splats", "slr_status_string", "slr_last_error"]
 
 _lib = None
 
@@ -85,6 +85,8 @@ def lib():
         L.slr_range_normals.argtypes = [P, P, P, P]
         L.slr_loss_map.argtypes = [I64, P, P, P, P, P, C.c_float, C.c_float, C.c_float, P, P, P, P, P]
         L.slr_scale_reg.argtypes = [I64, P, D, D, P, P, P]
+        L.slr_init_workspace_size.argtypes = [P, P]
+        L.slr_init_splats.argtypes = [P, P, P, P, I64, P, D, C.c_float, P, C.c_size_t, P, P, P, P, P, P]
         BATCH = [I32, P, I32, P, P, I64, P, C.c_size_t]
         L.slr_batch_workspace_size.argtypes = [I32, P, I32, P, P, I64, P]
         L.slr_batch_prepare.argtypes = BATCH + [P]
@@ -103,7 +105,8 @@ def lib():
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
                   "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
                   "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
-                  "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg"):
+                  "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg",
+                  "slr_init_workspace_size", "slr_init_splats"):
             getattr(L, f).restype = I32
         _lib = L
     return _lib
@@ -447,6 +450,34 @@ def scale_reg(log_scales, tau_s, w_s, d_log_scales, loss=None):
     """Scale cap L_s (slr_scale_reg): adds its gradient to d_log_scales and its value to loss."""
     _check(lib().slr_scale_reg(log_scales.shape[0], _ptr(log_scales), float(tau_s), float(w_s), _ptr(d_log_scales),
                                _ptr(loss), _stream()), "slr_scale_reg")
+
+
+def init_splats(sensor, range_image, pose_cw, uniforms, mask=None, scale_factor=1.0, logit=0.0):
+    """Local model initialisation (slr_init_splats): splats drawn from a range
+    image by the range-gradient weight map; returns dict of CUDA tensors
+    means [n,3], quats [n,4], log_scales [n,2], logits [n], pixel [n] int32."""
+    for name, a in (("range_image", range_image), ("mask", mask)):
+        if a is not None and (a.dtype != torch.float32 or not a.is_contiguous()):
+            raise ValueError(f"{name} must be contiguous float32")
+    if uniforms.dtype != torch.float64 or not uniforms.is_contiguous():
+        raise ValueError("uniforms must be contiguous float64")
+    _pose(pose_cw)
+    n = uniforms.numel()
+    dev = range_image.device
+    s = _sensor(sensor)
+    nb = C.c_size_t(0)
+    _check(lib().slr_init_workspace_size(C.byref(s), C.byref(nb)), "slr_init_workspace_size")
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    out = dict(means=torch.empty((n, 3), dtype=torch.float32, device=dev),
+               quats=torch.empty((n, 4), dtype=torch.float32, device=dev),
+               log_scales=torch.empty((n, 2), dtype=torch.float32, device=dev),
+               logits=torch.empty((n,), dtype=torch.float32, device=dev),
+               pixel=torch.empty((n,), dtype=torch.int32, device=dev))
+    _check(lib().slr_init_splats(C.byref(s), _ptr(range_image), _ptr(mask), _ptr(pose_cw), n, _ptr(uniforms),
+                                 float(scale_factor), float(logit), _ptr(ws), ws.numel(), _ptr(out["means"]),
+                                 _ptr(out["quats"]), _ptr(out["log_scales"]), _ptr(out["logits"]), _ptr(out["pixel"]),
+                                 _stream()), "slr_init_splats")
+    return out
 
 
 def photo_workspace_size(sensor):

@@ -135,3 +135,30 @@ def test_scale_reg_parity(slr):
     assert abs(float(loss.cpu()) - L) <= 1e-9 * abs(L)
     # n = 0 is a no-op
     slr.scale_reg(torch.zeros((0, 2), device=DEV), 0.5, 0.3, torch.zeros((0, 2), device=DEV), loss)
+
+
+def test_init_splats_parity(slr):
+    sensor = slr.make_sensor(128, 1024)
+    Dr = raycast_image(sensor, 4)
+    g = np.random.default_rng(14)
+    mask = (g.uniform(size=Dr.shape) > 0.1).astype(np.float32)
+    T_cw = synth.circle_poses(8, 0)[4]
+    U = g.uniform(size=50_000)
+    U[:3] = [0.0, np.nextafter(1.0, 0.0), 0.5]
+    say("init_splats 50k draws on 128x1024")
+    out = slr.init_splats(sensor, dev(Dr), torch.from_numpy(T_cw).to(DEV), torch.from_numpy(U).to(DEV),
+                          dev(mask), scale_factor=1.2, logit=-1.0)
+    ref = O.mapping.init_splats(sensor, Dr, T_cw, U, mask, 1.2, -1.0)
+    pix = out["pixel"].cpu().numpy()
+    np.testing.assert_array_equal(pix, ref["pixel"])
+    assert (pix >= 0).all() and len(np.unique(pix)) > 10_000
+    np.testing.assert_allclose(out["means"].cpu().numpy(), ref["means"], rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(out["log_scales"].cpu().numpy(), ref["log_scales"], rtol=1e-6, atol=1e-6)
+    assert (out["logits"].cpu().numpy() == np.float32(-1.0)).all()
+    q, qr = out["quats"].cpu().numpy(), ref["quats"]
+    dq = np.minimum(np.abs(q - qr).max(1), np.abs(q + qr).max(1))
+    assert dq.max() < 1e-6
+    # no weight anywhere: every draw reports -1
+    e = slr.init_splats(sensor, torch.zeros((128, 1024), device=DEV), torch.from_numpy(T_cw).to(DEV),
+                        torch.from_numpy(U[:100]).to(DEV))
+    assert (e["pixel"].cpu().numpy() == -1).all() and not e["means"].cpu().numpy().any()
