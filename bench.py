@@ -180,6 +180,49 @@ def measure_photo(torch, slr, sensor, kf, depth, steps):
             "bound": "latency: 8 B of images per pixel, ~1 MB per launch"}
 
 
+def measure_mapping(torch, slr, sensor, kf, d, steps):
+    """Mapping-side image kernels on keyframe 0's scan (its ray-cast target
+    back-projected into a sensor-frame point cloud): cloud to range image,
+    normals from range gradients, the fused refinement losses, the scale cap
+    over the map, and 100k initialisation draws.  HIP events on the launch
+    stream, mean over `steps` calls each."""
+    Dt = kf["Dt"]
+    Hh, Ww = Dt.shape
+    ii, jj = torch.meshgrid(torch.arange(Hh, device="cuda", dtype=torch.float64),
+                            torch.arange(Ww, device="cuda", dtype=torch.float64), indexing="ij")
+    az = (jj + 0.5 - sensor["cu"]) / sensor["fu"]
+    el = (ii + 0.5 - sensor["cv"]) / sensor["fv"]
+    ray = torch.stack([torch.cos(el) * torch.cos(az), torch.cos(el) * torch.sin(az), torch.sin(el)], -1)
+    pts = (Dt.double()[..., None] * ray)[Dt > 0].float().contiguous()
+    rng = torch.empty_like(Dt)
+    nrm = torch.empty(Hh, Ww, 3, device="cuda")
+    gD, gN, gO = torch.empty_like(Dt), torch.empty_like(nrm), torch.empty_like(Dt)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    O = torch.full_like(Dt, 0.9)
+    gls = torch.zeros_like(d["log_scales"])
+    U = torch.rand(100_000, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    calls = {
+        "cloud_to_range": lambda: slr.cloud_to_range(sensor, pts, out=rng),
+        "range_normals": lambda: slr.range_normals(sensor, Dt, out=nrm),
+        "loss_map": lambda: slr.loss_map(Dt, nrm, O, Dt, nrm, 1.0, 1.0, 1.0, gD, gN, gO, loss),
+        "scale_reg": lambda: slr.scale_reg(d["log_scales"], 0.5, 1.0, gls, loss),
+        "init_splats": lambda: slr.init_splats(sensor, Dt, kf["T"], U),
+    }
+    out = {"scan_points": int(pts.shape[0]), "image": f"{Hh}x{Ww}", "surfels": int(d["log_scales"].shape[0]),
+           "init_draws": int(U.numel())}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round(a.elapsed_time(b) / steps, 4)
+    return out
+
+
 def cpu_baseline(sc, sensor, kfs, budget_s):
     """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
     import numpy as np
@@ -371,12 +414,14 @@ def main():
     value = batched_iters if args.form == "batched" else plain_iters
     dt = batched_dt if args.form == "batched" else plain_dt
 
-    gn = photo = None
+    gn = photo = mapping = None
     if not args.no_gn:
         gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar), args.steps, census0)
         log("pose-only Gauss-Newton:", gn)
         photo = measure_photo(torch, slr, sensor, kfs[0], br.out[0][0], args.steps)
         log("photometric registration:", photo)
+        mapping = measure_mapping(torch, slr, sensor, kfs[0], d, args.steps)
+        log("mapping kernels:", mapping)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -396,7 +441,7 @@ def main():
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
-        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn, "photo_gn": photo,
+        "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn, "photo_gn": photo, "mapping": mapping,
     }
     print(json.dumps(out), flush=True)
 
