@@ -569,10 +569,43 @@ static int el_lt(double ra, double za, double rb, double zb) { return za * rb - 
 
 /* Per-surfel box.  Writes rows [r0, r1] and up to two column intervals.
  * Returns the number of column intervals (0 = culled). */
+/* Box modes: 0 the exact angular box of the 3-sigma square (R12); 1 the same
+ * box of the opacity-aware square below; 2 the paper's relaxed box (Supp. B):
+ * the angular extent of the four projected vertices only, which can miss
+ * pixels where an edge bulges beyond its vertices or the sensor's axis
+ * pierces the square.
+ *
+ * Opacity-aware support radius (box mode 1).  A pair contributes only when
+ * alpha = o G >= 1/255 (R7), i.e. inside the disk |s_hat|^2 <= 2 ln(255 o);
+ * the square of half-side r = k/16 bounds it for the smallest integer k with
+ * 255 o exp(-(k/16)^2 / 2) <= 0.999 (a 0.1 % margin over the threshold),
+ * found by binary search with the reproducible exp, so that both sides take
+ * the same integer decision.  Returns 0 when no pixel can reach the threshold
+ * (255 o <= 0.999) and 3 when the disk is not smaller than the 3-sigma
+ * square. */
+static double support_radius(double logit)
+{
+    double o = 1.0 / (1.0 + box_exp(-logit));
+    double c = 255.0 * o;
+    if (c <= 0.999) return 0.0;
+    if (!(c * box_exp(-(48.0 * 48.0) / 512.0) <= 0.999)) return 3.0;
+    int lo = 1, hi = 48;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (c * box_exp(-(double)(mid * mid) / 512.0) <= 0.999) hi = mid; else lo = mid + 1;
+    }
+    return (double)lo / 16.0;
+}
+
 static int surfel_box(const double *mu, const double *q, const double *ls, double logit, const double *pose,
-                      double near_m, const box_tables *T, int32_t *rows, int32_t *cols)
+                      double near_m, const box_tables *T, int32_t box_mode, int32_t *rows, int32_t *cols)
 {
     if (!finite_params(mu, q, ls, logit)) return 0;
+    double rad = 3.0;
+    if (box_mode == 1) {
+        rad = support_radius(logit);
+        if (rad == 0.0) return 0;
+    }
     double w = q[0], x = q[1], y = q[2], z = q[3];
     double qq = ((w * w + x * x) + y * y) + z * z;
     if (!(qq > 0.0)) return 0;
@@ -581,7 +614,7 @@ static int surfel_box(const double *mu, const double *q, const double *ls, doubl
     /* first two columns of R(q) */
     double ta[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
     double tb[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
-    double sa = 3.0 * box_exp(ls[0]), sb = 3.0 * box_exp(ls[1]);
+    double sa = rad * box_exp(ls[0]), sb = rad * box_exp(ls[1]);
     double Aw[3] = {sa * ta[0], sa * ta[1], sa * ta[2]};
     double Bw[3] = {sb * tb[0], sb * tb[1], sb * tb[2]};
     double A[3], B[3], C[3];
@@ -610,7 +643,9 @@ static int surfel_box(const double *mu, const double *q, const double *ls, doubl
     double Rb = (range + an) + bn;
     double E = 4e-15 * (an * bn);
     double as = fabs(sc);
-    if (!(as > (1e-9 * Rb) * nn + E * range)) {
+    if (box_mode == 2) {
+        /* vertex-only box (Supp. B's relaxed box): no pierce test */
+    } else if (!(as > (1e-9 * Rb) * nn + E * range)) {
         full_az = 1; rows_top = 1; rows_bot = 1;      /* sensor (nearly) in the square's plane */
     } else if (as - E * range > Rb * (fabs(det) + E)) {
         /* the axis meets the plane beyond the square, or never (plane parallel to it) */
@@ -645,7 +680,7 @@ static int surfel_box(const double *mu, const double *q, const double *ls, doubl
         double q2 = P0[0] * P0[0] + P0[1] * P0[1];
         double d2 = dx * dx + dy * dy;
         double den = dz * qd - P0[2] * d2;
-        if (den != 0.0) {
+        if (box_mode != 2 && den != 0.0) {   /* the vertex-only box skips the edges' stationary points */
             double ts = (P0[2] * qd - dz * q2) / den;
             if (ts > 0.0 && ts < 1.0) {
                 cand[nc][0] = P0[0] + ts * dx; cand[nc][1] = P0[1] + ts * dy; cand[nc][2] = P0[2] + ts * dz; ++nc;
@@ -756,7 +791,7 @@ static int bin_cmp(const void *a, const void *b)
  * Returns 0, or 1 when the pair capacity is too small (K still reported). */
 int or_bin(int64_t n, const double *means, const double *quats, const double *log_scales,
            const double *logits, const double *pose, const or_sensor *s, int32_t tile_h, int32_t tile_w, double margin,
-           uint32_t *keys, int32_t *counts, int32_t *pixbox, int32_t *rects,
+           int32_t box_mode, uint32_t *keys, int32_t *counts, int32_t *pixbox, int32_t *rects,
            int64_t capacity, int64_t *K, int32_t *sorted_tile, int32_t *sorted_id, int32_t *ranges)
 {
     if (n < 0 || !s || tile_h <= 0 || tile_w <= 0) return -1;
@@ -772,7 +807,7 @@ int or_bin(int64_t n, const double *means, const double *quats, const double *lo
         keys[k] = kb;
         int32_t rows[2] = {-1, -1}, cols[4] = {-1, -1, -1, -1}, rc[8];
         for (int e = 0; e < 8; ++e) rc[e] = -1;
-        int nint = surfel_box(mu, quats + 4 * k, log_scales + 2 * k, logits[k], pose, s->near_m, &T, rows, cols);
+        int nint = surfel_box(mu, quats + 4 * k, log_scales + 2 * k, logits[k], pose, s->near_m, &T, box_mode, rows, cols);
         int nr = box_rects(nint, rows, cols, tile_h, tile_w, rc);
         int32_t cnt = 0;
         for (int r = 0; r < nr; ++r) cnt += (rc[4 * r + 1] - rc[4 * r] + 1) * (rc[4 * r + 3] - rc[4 * r + 2] + 1);
@@ -797,7 +832,8 @@ int or_bin(int64_t n, const double *means, const double *quats, const double *lo
     for (int64_t k = 0; k < n; ++k) {
         if (!counts[k]) continue;
         int32_t rows[2], cols[4] = {-1, -1, -1, -1}, rc[8];
-        int nint = surfel_box(means + 3 * k, quats + 4 * k, log_scales + 2 * k, logits[k], pose, s->near_m, &T2, rows, cols);
+        int nint = surfel_box(means + 3 * k, quats + 4 * k, log_scales + 2 * k, logits[k], pose, s->near_m, &T2, box_mode,
+                              rows, cols);
         int nr = box_rects(nint, rows, cols, tile_h, tile_w, rc);
         for (int r = 0; r < nr; ++r)
             for (int32_t ty = rc[4 * r + 2]; ty <= rc[4 * r + 3]; ++ty)
@@ -864,3 +900,4 @@ int or_frames(int64_t n, const double *means, const double *quats, const double 
 
 /* Exposed for the tests: the reproducible exp used by the box. */
 double or_box_exp(double x) { return box_exp(x); }
+double or_support_radius(double logit) { return support_radius(logit); }

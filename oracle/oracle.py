@@ -44,12 +44,14 @@ def lib():
         L.or_pixel_basis.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.or_render_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         L.or_backward_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
-        L.or_bin.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_double,
+        L.or_bin.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                              P, P, P, P, C.c_int64, P, P, P, P]
         L.or_pair_support.argtypes = [P, P, P, C.c_double, P, P, C.c_int32, C.c_int32, P]
         L.or_frames.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, P, P, P]
         L.or_box_exp.argtypes = [C.c_double]
         L.or_box_exp.restype = C.c_double
+        L.or_support_radius.argtypes = [C.c_double]
+        L.or_support_radius.restype = C.c_double
         for f in ("or_render_pixels", "or_backward_pixels", "or_bin", "or_pair_support", "or_frames"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -171,8 +173,9 @@ def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, 
 
 
 def bin_surfels(means, quats, log_scales, logits, T_cw, sensor, tile_h=16, tile_w=16, margin=2e-5,
-                capacity=None):
-    """Bit-mirror binning: keys, counts, pixel boxes, rects, sorted (tile, id) and tile ranges."""
+                capacity=None, box_mode=0):
+    """Bit-mirror binning: keys, counts, pixel boxes, rects, sorted (tile, id) and tile ranges.
+    box_mode 0: the 3-sigma square; 1: the opacity-aware support radius."""
     n, m, q, ls, lo = _surfels(means, quats, log_scales, logits)
     H, W = int(sensor["height"]), int(sensor["width"])
     ntiles = ((H + tile_h - 1) // tile_h) * ((W + tile_w - 1) // tile_w)
@@ -186,12 +189,12 @@ def bin_surfels(means, quats, log_scales, logits, T_cw, sensor, tile_h=16, tile_
     pose = _pose12(T_cw)
     cap = capacity
     if cap is None:
-        rc = lib().or_bin(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), tile_h, tile_w, margin,
+        rc = lib().or_bin(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), tile_h, tile_w, margin, box_mode,
                           _p(keys), _p(counts), _p(pixbox), _p(rects), 0, _p(K), None, None, _p(ranges))
         cap = int(K[0])
     st = np.zeros(max(cap, 1), np.int32)
     sid = np.zeros(max(cap, 1), np.int32)
-    rc = lib().or_bin(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), tile_h, tile_w, margin,
+    rc = lib().or_bin(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), tile_h, tile_w, margin, box_mode,
                       _p(keys), _p(counts), _p(pixbox), _p(rects), cap, _p(K), _p(st), _p(sid), _p(ranges))
     if rc < 0:
         raise RuntimeError("or_bin failed")
@@ -226,3 +229,8 @@ def frames(means, quats, log_scales, logits, T_cw, near=0.2):
 
 def box_exp(x):
     return lib().or_box_exp(float(x))
+
+
+def support_radius(logit):
+    """Opacity-aware half-side of the support square (box mode 1), in sigma units."""
+    return lib().or_support_radius(float(logit))

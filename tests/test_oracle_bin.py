@@ -231,3 +231,119 @@ def test_non_finite_and_near_are_culled():
     sc["means"][4] = [0.1, 0.05, 0.0]
     b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s)
     assert (b["counts"][:5] == 0).all()
+
+
+# ---- opacity-aware box (mode 1) -------------------------------------------
+
+def test_support_radius_closed_form():
+    """The smallest sixteenth k/16 with 255 o exp(-(k/16)^2/2) <= 0.999, i.e.
+    the first multiple of 1/16 at or above sqrt(2 ln(255 o / 0.999)); 0 when
+    255 o <= 0.999, 3 at the 3-sigma square."""
+    for logit in np.linspace(-7.0, 8.0, 301):
+        o = 1.0 / (1.0 + math.exp(-logit))
+        r = O.support_radius(logit)
+        c = 255.0 * o / 0.999
+        if c <= 1.0:
+            assert r == 0.0, (logit, r)
+            continue
+        rstar = math.sqrt(2.0 * math.log(c))
+        if rstar > 47.0 / 16.0 + 1e-9:
+            assert r == 3.0, (logit, r, rstar)
+            continue
+        assert abs(r * 16 - round(r * 16)) == 0 and 1 <= r * 16 <= 48
+        assert r >= rstar - 1e-12 and r - 1.0 / 16.0 < rstar + 1e-12, (logit, r, rstar)
+
+
+def support_masks_alpha(sc, T, s):
+    """Support masks that also require alpha = o G >= 1/255 (FP64)."""
+    M = support_masks(sc, T, s)
+    H, W = s["height"], s["width"]
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    V = h.ray_dir(s, ii, jj)
+    for k in range(M.shape[0]):
+        if not M[k].any():
+            continue
+        mu = sc["means"][k].astype(np.float64)
+        ba, bb, bc, n, o, _ = h.sensor_frame_vectors(mu, sc["quats"][k].astype(np.float64),
+                                                     sc["log_scales"][k].astype(np.float64),
+                                                     float(sc["logits"][k]), T)
+        nv = V @ n
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.dot(n, bc) / nv
+            X = t[..., None] * V - bc
+            sa = X @ ba / np.dot(ba, ba)
+            sb = X @ bb / np.dot(bb, bb)
+            alpha = o * np.exp(-0.5 * (sa * sa + sb * sb))
+        M[k] &= alpha >= (1.0 / 255.0) * (1 - 1e-9)
+    return M
+
+
+@pytest.mark.parametrize("th,tw", [(16, 16), (32, 8), (8, 32), (4, 64)])
+def test_opacity_box_conservative(th, tw):
+    s = O.make_sensor(32, 256)
+    for sc, T in ((synth.shell_scene(500, 21), np.eye(4)), (adversarial_scene(), np.eye(4)),
+                  (synth.structured_scene(500, 22)[0], synth.circle_poses(3, 5)[1])):
+        sc = dict(sc)
+        sc["logits"] = np.random.default_rng(23).normal(0.0, 2.0, sc["logits"].shape).astype(np.float32)
+        b = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s, th, tw, box_mode=1)
+        M = support_masks_alpha(sc, T, s)
+        tx = (s["width"] + tw - 1) // tw
+        for k in range(M.shape[0]):
+            rr, cc = np.nonzero(M[k])
+            if rr.size == 0:
+                continue
+            pb = b["pixbox"][k]
+            assert b["counts"][k] > 0, k
+            assert (rr >= pb[0]).all() and (rr <= pb[1]).all(), k
+            inc = (cc >= pb[2]) & (cc <= pb[3])
+            if pb[4] >= 0:
+                inc |= (cc >= pb[4]) & (cc <= pb[5])
+            assert inc.all(), k
+            rc = b["rects"][k]
+            mine = set()
+            for r in range(2):
+                if rc[4 * r] < 0:
+                    continue
+                for ty in range(rc[4 * r + 2], rc[4 * r + 3] + 1):
+                    for x in range(rc[4 * r], rc[4 * r + 1] + 1):
+                        mine.add(ty * tx + x)
+            assert set(np.unique((rr // th) * tx + cc // tw).tolist()) <= mine
+
+
+def test_opacity_box_reduces_pairs():
+    s = O.make_sensor(64, 512)
+    sc, _ = synth.structured_scene(3000, 7)
+    T = synth.circle_poses(8, 0)[1]
+    b0 = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s)
+    b1 = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, s, box_mode=1)
+    assert b1["K"] < b0["K"], (b0["K"], b1["K"])
+    assert (b1["counts"] <= b0["counts"]).all()
+    # surfels whose opacity can never reach the threshold are culled
+    low = sc["logits"] < math.log(0.999 / (255 - 0.999))
+    assert (b1["counts"][low] == 0).all()
+    # an opaque map (logit 6: r = 3) bins exactly as the 3-sigma square
+    sc6 = dict(sc, logits=np.full_like(sc["logits"], 6.0))
+    a = O.bin_surfels(sc6["means"], sc6["quats"], sc6["log_scales"], sc6["logits"], T, s)
+    c = O.bin_surfels(sc6["means"], sc6["quats"], sc6["log_scales"], sc6["logits"], T, s, box_mode=1)
+    np.testing.assert_array_equal(a["sorted_id"], c["sorted_id"])
+
+
+def test_vertex_box_can_miss_and_is_never_wider():
+    """Supp. B's relaxed box (mode 2): vertices only.  Never wider than the
+    exact box; on the adversarial scene (pierced axis, bulging edges) it
+    misses support pixels that the exact box covers."""
+    s = O.make_sensor(32, 256)
+    sc = adversarial_scene()
+    b0 = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s)
+    b2 = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], np.eye(4), s, box_mode=2)
+    assert b2["K"] < b0["K"]
+    M = support_masks(sc, np.eye(4), s)
+    missed = 0
+    for k in range(M.shape[0]):
+        rr, cc = np.nonzero(M[k])
+        if rr.size == 0:
+            continue
+        pb = b2["pixbox"][k]
+        inc = (rr >= pb[0]) & (rr <= pb[1]) & (((cc >= pb[2]) & (cc <= pb[3])) | ((pb[4] >= 0) & (cc >= pb[4]) & (cc <= pb[5])))
+        missed += int((~inc).sum())
+    assert missed > 0
