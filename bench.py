@@ -278,6 +278,9 @@ def main():
                     help="run one 256 MiB device-to-device copy first (calibrates HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gn", action="store_true", help="skip the pose-only Gauss-Newton measurement")
+    ap.add_argument("--box", choices=["exact", "opacity", "vertex"], default="exact",
+                    help="bounding box: exact 3-sigma square, opacity-aware square (same images, fewer pairs), "
+                         "or the relaxed vertex-only box (can miss pixels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -296,6 +299,7 @@ def main():
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
     th = tw = None
     bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
+    box = {"exact": slr.BOX_EXACT, "opacity": slr.BOX_OPACITY, "vertex": slr.BOX_VERTEX}[args.box]
     if args.tile != "auto":
         th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:
@@ -310,14 +314,14 @@ def main():
     tune_ms = None
     if th is None:
         # the autotuner times every candidate tiling on this batch (outside the timed region)
-        br = make_batch(torch, slr, d, sensor, kfs, slr.TUNE_CANDIDATES[0])
+        br = make_batch(torch, slr, d, sensor, kfs, tuple(slr.TUNE_CANDIDATES[0]) + (box,))
         for u in br.up:
             for t in u:
                 t.fill_(1.0)
         tune_ms = br.autotune()
-        th, tw, var, sch, bvar = br.tiling
+        th, tw, var, sch, bvar, box = br.tiling
         log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}": round(v, 3) for c, v in tune_ms.items()})
-    rend = [slr.Renderer(sensor, (th, tw, var, sch, bvar), capacity=4 << 20) for _ in kfs]
+    rend = [slr.Renderer(sensor, (th, tw, var, sch, bvar, box), capacity=4 << 20) for _ in kfs]
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
@@ -352,7 +356,7 @@ def main():
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
     if br is None:
-        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch, bvar))
+        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch, bvar, box))
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -416,7 +420,7 @@ def main():
 
     gn = photo = mapping = None
     if not args.no_gn:
-        gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar), args.steps, census0)
+        gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar, box), args.steps, census0)
         log("pose-only Gauss-Newton:", gn)
         photo = measure_photo(torch, slr, sensor, kfs[0], br.out[0][0], args.steps)
         log("photometric registration:", photo)
@@ -437,6 +441,7 @@ def main():
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
                    "schedule": {0: "default", 1: "tile", 2: "longest"}[sch],
                    "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar], "autotuned": tune_ms is not None,
+                   "box": args.box,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,

@@ -78,13 +78,24 @@ typedef struct slr_sensor {
  * the compositing backward: 0 = the same as variant (the library default if
  * that is 0), 1 = one workgroup per tile (records staged through LDS, one
  * flush per tile and record), 3 = one wave per 64-pixel strip.  Every variant
- * and schedule produces bit-identical forward outputs. */
+ * and schedule produces bit-identical forward outputs.  box selects the
+ * bounding box of a surfel (Sec. 3.2.3, Supp. B): 0 = the exact angular box
+ * of its 3-sigma square; 1 = the same box of the smaller square that can
+ * still hold a pixel reaching alpha >= 1/255 (half-side k/16, k the smallest
+ * integer with 255 o exp(-(k/16)^2 / 2) <= 0.999; surfels with 255 o <= 0.999
+ * are culled) -- fewer pairs, identical images; 2 = the paper's relaxed box,
+ * the angular extent of the square's four vertices only, which can miss
+ * pixels (for comparison). */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
     int32_t variant;
     int32_t schedule;
     int32_t bwd_variant;
+    int32_t box;
 } slr_tiling;
+#define SLR_BOX_EXACT 0
+#define SLR_BOX_OPACITY 1
+#define SLR_BOX_VERTEX 2
 #define SLR_VARIANT_DEFAULT 0
 #define SLR_VARIANT_LDS 1
 #define SLR_VARIANT_SCALAR 2

@@ -87,6 +87,7 @@ slr_status check_tiling(const slr_tiling *t)
         return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
+    if (t->box < SLR_BOX_EXACT || t->box > SLR_BOX_VERTEX) return fail(SLR_E_INVALID, "unknown box mode %d", t->box);
     return SLR_OK;
 }
 
@@ -210,6 +211,7 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
     b->L.bwd_variant = tiling->bwd_variant != SLR_VARIANT_DEFAULT ? tiling->bwd_variant
                        : (b->L.variant == SLR_VARIANT_WAVE ? SLR_VARIANT_WAVE : SLR_VARIANT_LDS);
     b->L.schedule = tiling->schedule == SLR_SCHEDULE_DEFAULT ? slr::kDefaultSchedule : tiling->schedule;
+    b->L.box_mode = tiling->box;
     if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");
     return SLR_OK;
 }

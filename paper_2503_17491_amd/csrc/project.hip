@@ -63,10 +63,32 @@ struct BoxOut {
     int r0, r1, c[4];
 };
 
+// Opacity-aware half-side of the support square (box mode 1): a pair only
+// contributes where alpha = o G >= 1/255, inside |s_hat|^2 <= 2 ln(255 o); the
+// square of half-side k/16 holds that disk for the smallest integer k with
+// 255 o exp(-(k/16)^2 / 2) <= 0.999 (binary search with the reproducible exp,
+// so the integer decision is reproducible).  0: no pixel can reach the
+// threshold (255 o <= 0.999); 3: the disk is not inside the 3-sigma square.
+__device__ double support_radius(double logit)
+{
+    const double o = 1.0 / (1.0 + box_exp(-logit));
+    const double c = 255.0 * o;
+    if (c <= 0.999) return 0.0;
+    if (!(c * box_exp(-(48.0 * 48.0) / 512.0) <= 0.999)) return 3.0;
+    int lo = 1, hi = 48;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c * box_exp(-(double)(mid * mid) / 512.0) <= 0.999) hi = mid; else lo = mid + 1;
+    }
+    return (double)lo / 16.0;
+}
+
 // Exact angular box of the square {C + a A + b B : |a|, |b| <= 1}; range = |C|.
+// vertex_only: the relaxed box of Supp. B (no pierce test, no stationary
+// points on the edges), kept for comparison -- it can miss pixels.
 __device__ BoxOut angular_box(const double A[3], const double B[3], const double C[3], double range, int H, int W,
                               const double2 *__restrict__ col, const double2 *__restrict__ rlo,
-                              const double2 *__restrict__ rhi, double cm, double sm)
+                              const double2 *__restrict__ rhi, double cm, double sm, bool vertex_only)
 {
     BoxOut o;
     o.nint = 0;
@@ -84,7 +106,9 @@ __device__ BoxOut angular_box(const double A[3], const double B[3], const double
     double Rb = (range + an) + bn;
     double E = 4e-15 * (an * bn);
     double as = fabs(sc);
-    if (!(as > (1e-9 * Rb) * nn + E * range)) {
+    if (vertex_only) {
+        // the relaxed box: no pierce test
+    } else if (!(as > (1e-9 * Rb) * nn + E * range)) {
         full_az = to_top = to_bottom = true;      // sensor (nearly) in the square's plane
     } else if (as - E * range > Rb * (fabs(det) + E)) {
         // the axis meets the plane beyond the square, or never
@@ -124,7 +148,7 @@ __device__ BoxOut angular_box(const double A[3], const double B[3], const double
         double cx[2], cy[2], cz[2];
         int nc = 1;
         cx[0] = P0[0]; cy[0] = P0[1]; cz[0] = P0[2];
-        if (den != 0.0) {
+        if (!vertex_only && den != 0.0) {
             double ts = (P0[2] * qd - dz * q2) / den;
             if (ts > 0.0 && ts < 1.0) {
                 cx[1] = P0[0] + ts * dx; cy[1] = P0[1] + ts * dy; cz[1] = P0[2] + ts * dz;
@@ -221,7 +245,7 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
 __global__ void __launch_bounds__(256)
 k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ tables, double cm, double sm,
           RasterRec *__restrict__ rec, FrameRec *__restrict__ frame, ChatRec *__restrict__ chat, PixBox *__restrict__ box,
-          uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts)
+          uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts, int box_mode)
 {
     const FrameDesc &fd = descs[blockIdx.y];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,13 +264,18 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     double w = fq.x, x = fq.y, y = fq.z, z = fq.w;
     double qq = ((w * w + x * x) + y * y) + z * z;
     bool ok = fin && qq > 0.0;
+    double rad = 3.0;
+    if (ok && box_mode == SLR_BOX_OPACITY) {
+        rad = support_radius((double)flg);
+        ok = rad > 0.0;
+    }
     double R[9], t[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         R[3 * e] = fd.pose[4 * e]; R[3 * e + 1] = fd.pose[4 * e + 1]; R[3 * e + 2] = fd.pose[4 * e + 2];
         t[e] = fd.pose[4 * e + 3];
     }
-    double A[3], B[3], C[3], N[3];
+    double A[3], B[3], C[3], N[3], ba[3], bb[3];
     double range = 0.0;
     if (ok) {
         double qn = sqrt(qq);
@@ -254,9 +283,14 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
         double ta[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
         double tb[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
         double tn[3] = {2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y)};
-        double s3a = 3.0 * box_exp((double)fl0), s3b = 3.0 * box_exp((double)fl1);
+        double s3a = rad * box_exp((double)fl0), s3b = rad * box_exp((double)fl1);
         double Aw[3] = {s3a * ta[0], s3a * ta[1], s3a * ta[2]};
         double Bw[3] = {s3b * tb[0], s3b * tb[1], s3b * tb[2]};
+        // the splat axes themselves (independent of the box's half-side, so that
+        // every box mode composites identical records)
+        double sa1 = box_exp((double)fl0), sb1 = box_exp((double)fl1);
+        double Au[3] = {sa1 * ta[0], sa1 * ta[1], sa1 * ta[2]};
+        double Bu[3] = {sb1 * tb[0], sb1 * tb[1], sb1 * tb[2]};
         double m0 = fm0, m1 = fm1, m2 = fm2;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -265,13 +299,15 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
             B[r] = (Rr[0] * Bw[0] + Rr[1] * Bw[1]) + Rr[2] * Bw[2];
             C[r] = ((Rr[0] * m0 + Rr[1] * m1) + Rr[2] * m2) + t[r];
             N[r] = (Rr[0] * tn[0] + Rr[1] * tn[1]) + Rr[2] * tn[2];
+            ba[r] = (Rr[0] * Au[0] + Rr[1] * Au[1]) + Rr[2] * Au[2];
+            bb[r] = (Rr[0] * Bu[0] + Rr[1] * Bu[1]) + Rr[2] * Bu[2];
         }
         range = sqrt((C[0] * C[0] + C[1] * C[1]) + C[2] * C[2]);
         ok = range > fd.near_m;
     }
     BoxOut bx;
     bx.nint = 0;
-    if (ok) bx = angular_box(A, B, C, range, H, W, col, rlo, rhi, cm, sm);
+    if (ok) bx = angular_box(A, B, C, range, H, W, col, rlo, rhi, cm, sm, box_mode == SLR_BOX_VERTEX);
     int32_t cnt = 0;
     PixBox pb = {-1, -1, -1, -1, -1, -1, (int16_t)blockIdx.y, 0};
     if (bx.nint > 0) {
@@ -300,9 +336,7 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     float key = (float)range;
     keys[it] = __float_as_uint(key);
 
-    // compositing record: b_alpha = A / 3, b_beta = B / 3, b_c = C
-    double ba[3] = {A[0] / 3.0, A[1] / 3.0, A[2] / 3.0};
-    double bb[3] = {B[0] / 3.0, B[1] / 3.0, B[2] / 3.0};
+    // compositing record: b_alpha, b_beta, b_c = C
     RasterRec rr;
     cross3(bb, C, rr.P);
     cross3(C, ba, rr.Q);
@@ -371,7 +405,7 @@ void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream
                        reinterpret_cast<FrameRec *>(ws + L.frame), reinterpret_cast<ChatRec *>(ws + L.chat),
                        reinterpret_cast<PixBox *>(ws + L.box),
                        reinterpret_cast<uint32_t *>(ws + L.skey), reinterpret_cast<uint32_t *>(ws + L.val0),
-                       reinterpret_cast<int32_t *>(ws + L.cnt));
+                       reinterpret_cast<int32_t *>(ws + L.cnt), (int)L.box_mode);
 }
 
 }  // namespace slr

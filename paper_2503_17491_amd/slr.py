@@ -28,7 +28,7 @@ class Sensor(C.Structure):
 
 class Tiling(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32),
-                ("bwd_variant", C.c_int32)]
+                ("bwd_variant", C.c_int32), ("box", C.c_int32)]
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
@@ -286,6 +286,7 @@ class Renderer:
 
 # Candidate tilings of the autotuner: (tile_h, tile_w, forward variant,
 # schedule, backward variant).
+BOX_EXACT, BOX_OPACITY, BOX_VERTEX = 0, 1, 2
 TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((16, 16), (8, 32), (32, 8))
                    for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
@@ -343,7 +344,11 @@ class BatchRenderer:
         """Time render + backward of this batch for each candidate tiling (median
         of reps, after one untimed step) and keep the fastest.  Returns
         {tiling: ms} (-1 where the pairs overflowed the capacity)."""
-        cands = [tuple(c) + (0,) * (5 - len(c)) for c in (candidates or TUNE_CANDIDATES)]
+        box = tuple(self.tiling)[5] if len(self.tiling) > 5 else 0   # the binning's box mode is kept
+        cands = []
+        for c in (candidates or TUNE_CANDIDATES):
+            c = tuple(c) + (0,) * max(0, 5 - len(c))
+            cands.append(c if len(c) > 5 else c + (box,))
         arr = (Tiling * len(cands))(*[Tiling(*c) for c in cands])
         need = 0
         for c in cands:

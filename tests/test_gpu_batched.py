@@ -175,7 +175,8 @@ def test_autotune_picks_a_candidate(slr):
     upstream(br, 3)
     cands = [(16, 16, 3, 2, 3), (8, 32, 3, 2, 1), (16, 16, 1, 2, 1)]
     ms = br.autotune(cands, reps=2)
-    assert set(ms) == set(cands) and all(v > 0 for v in ms.values())
+    # each candidate keeps the renderer's box mode (0 here) as its sixth entry
+    assert set(ms) == {c + (0,) for c in cands} and all(v > 0 for v in ms.values())
     assert br.tiling == min(ms, key=ms.get)
     br.render()
     torch.cuda.synchronize()
