@@ -21,7 +21,6 @@
 using slr::FrameDesc;
 using slr::FrameGeom;
 using slr::Layout;
-using slr::ChatRec;
 
 namespace {
 
@@ -374,8 +373,6 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.tables = take(16 * (size_t)L.tab_entries);
     L.tile_frame = take(4 * (size_t)L.tiles);
     L.rec = take(sizeof(RasterRec) * nn);
-    L.frame = take(sizeof(FrameRec) * nn);
-    L.chat = take(sizeof(ChatRec) * nn);
     L.box = take(sizeof(PixBox) * nn);
     L.skey = take(4 * nn);
     L.key0 = take(4 * nn); L.val0 = take(4 * nn); L.key1 = take(4 * nn); L.val1 = take(4 * nn);

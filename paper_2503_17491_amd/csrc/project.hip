@@ -3,7 +3,7 @@
 // One thread per surfel:
 //   * the splat-to-sensor transform T = T_cw H of Supp. D (b_alpha, b_beta,
 //     b_c, n) in FP64, packed into the compositing record (Cramer form, see
-//     RasterRec) and the gradient frame;
+//     RasterRec; the backward rebuilds the axes from it);
 //   * the range key: FP32 rounding of |b_c|;
 //   * the bounding box of Sec. 3.2.3 / Supp. B, computed as the exact angular
 //     box of the 3-sigma splat square, widened by an angular margin, with the
@@ -244,7 +244,7 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
 
 __global__ void __launch_bounds__(256)
 k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ tables, double cm, double sm,
-          RasterRec *__restrict__ rec, FrameRec *__restrict__ frame, ChatRec *__restrict__ chat, PixBox *__restrict__ box,
+          RasterRec *__restrict__ rec, PixBox *__restrict__ box,
           uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts, int box_mode)
 {
     const FrameDesc &fd = descs[blockIdx.y];
@@ -346,14 +346,6 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     rr.n[0] = (float)N[0]; rr.n[1] = (float)N[1]; rr.n[2] = (float)N[2];
     rr.rows = (uint32_t)bx.r0 | ((uint32_t)bx.r1 << 16);
     rec[it] = rr;
-    FrameRec fr;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) { fr.ba[r] = ba[r]; fr.bb[r] = bb[r]; fr.bc[r] = C[r]; fr.n[r] = (float)N[r]; }
-    fr.pad[0] = fr.pad[1] = fr.pad[2] = 0.0f;
-    frame[it] = fr;
-    ChatRec ch;
-    ch.c[0] = C[0] / range; ch.c[1] = C[1] / range; ch.c[2] = C[2] / range;
-    chat[it] = ch;
 }
 
 // Descriptor upload through kernel arguments (no host buffer outlives the call).
@@ -402,7 +394,6 @@ void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream
     hipLaunchKernelGGL(k_project, dim3(blocks, L.frames), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double2 *>(ws + L.tables),
                        cos(kBoxMargin), sin(kBoxMargin), reinterpret_cast<RasterRec *>(ws + L.rec),
-                       reinterpret_cast<FrameRec *>(ws + L.frame), reinterpret_cast<ChatRec *>(ws + L.chat),
                        reinterpret_cast<PixBox *>(ws + L.box),
                        reinterpret_cast<uint32_t *>(ws + L.skey), reinterpret_cast<uint32_t *>(ws + L.val0),
                        reinterpret_cast<int32_t *>(ws + L.cnt), (int)L.box_mode);

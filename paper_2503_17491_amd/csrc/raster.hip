@@ -684,6 +684,40 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
     g[15] = u.gn0 * w; g[16] = u.gn1 * w; g[17] = u.gn2 * w;
 }
 
+// The splat axes from a record: P, Q, M are the cofactors of (b_alpha b_beta
+// b_c), so P x Q = tau b_c, Q x M = tau b_alpha, M x P = tau b_beta with
+// tau^2 = M . (P x Q) and the sign of the stored tau (FP64, ~1e-12 relative).
+__device__ __forceinline__ void record_axes(const RasterRec &r, double *ba, double *bb, double *bc)
+{
+    double pq[3], qm[3], mp[3];
+    dcross(r.P, r.Q, pq); dcross(r.Q, r.M, qm); dcross(r.M, r.P, mp);
+    const double t2 = (r.M[0] * pq[0] + r.M[1] * pq[1]) + r.M[2] * pq[2];
+    const double it = (r.tau < 0.0f ? -1.0 : 1.0) / sqrt(t2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { ba[c] = qm[c] * it; bb[c] = mp[c] * it; bc[c] = pq[c] * it; }
+}
+
+// Unit direction of b_c, the centring reference of the partials: the
+// direction of P x Q with the sign of tau.  The accumulation and the flush
+// read the same staged value.
+__device__ __forceinline__ void centre_dir(const RasterRec &r, ChatRec &ch)
+{
+    double pq[3];
+    dcross(r.P, r.Q, pq);
+    const double sg = (r.tau < 0.0f ? -1.0 : 1.0) / sqrt((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ch.c[c] = pq[c] * sg;
+}
+
+// The axes of a staged record for its flush.
+__device__ __forceinline__ FrameRec flush_axes(const RasterRec &r)
+{
+    FrameRec fr;
+    record_axes(r, fr.ba, fr.bb, fr.bc);
+    fr.n[0] = r.n[0]; fr.n[1] = r.n[1]; fr.n[2] = r.n[2];
+    return fr;
+}
+
 // A record's pixel sums of the 18 partials -> dL/d(b_alpha, b_beta, b_c, n) in
 // FP64 (dPv = E_a + A_a ch, dQv = E_b + A_b ch; g_alpha = E_b x b_c + b_beta x C_s
 // + T_a M, g_beta = b_c x E_a + C_s x b_alpha + T_b M, g_c = dPv x b_beta +
@@ -744,7 +778,7 @@ template <int TW>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
-             const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame, const ChatRec *__restrict__ chat,
+             const RasterRec *__restrict__ rec,
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
@@ -817,7 +851,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         if ((int)threadIdx.x < cnt) {
             const uint32_t id = pval[b0 + threadIdx.x];
             srec[threadIdx.x] = rec[id];
-            schat[threadIdx.x] = chat[id];
+            centre_dir(srec[threadIdx.x], schat[threadIdx.x]);
         }
         __syncthreads();
         // the batch's records that meet this wave's rows and lie before its last
@@ -867,7 +901,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
                 sflag[k] = 0;
                 const uint32_t id = pval[b0 + k];
-                flush_record(s, frame[id], srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
+                const FrameRec fr = flush_axes(srec[k]);
+                flush_record(s, fr, srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
             }
         }
     }
@@ -911,8 +946,7 @@ template <int TW>
 __global__ void __launch_bounds__(64)
 k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
                const uint32_t *__restrict__ order,
-               const RasterRec *__restrict__ rec, const FrameRec *__restrict__ frame,
-               const ChatRec *__restrict__ chat, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+               const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
                double *__restrict__ pose_part, int pose_only, int64_t ntiles)
@@ -965,20 +999,16 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     float *acc_base = pose_only ? nullptr : fd.acc;
     const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
     int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64;
-    // a record travels as six 16-byte words (the last one ends with the rows
-    // word) and the centre direction as three doubles
+    // a record travels as six 16-byte words (the last one ends with the rows word)
     static_assert(sizeof(RasterRec) == 96 && offsetof(RasterRec, rows) == 92, "record layout");
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     u32x4 nrec[6];
-    double nch[3];
     uint32_t nid = 0;
     if (c >= rg.x && c + lane < end) {
         nid = pval[c + lane];
         const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
 #pragma unroll
         for (int f = 0; f < 6; ++f) nrec[f] = src[f];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
     }
     for (; c >= rg.x; c -= 64) {
         const bool inr = c + lane < end;
@@ -990,16 +1020,16 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[lane]);
 #pragma unroll
             for (int f = 0; f < 6; ++f) dst[f] = nrec[f];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) schat[lane].c[f] = nch[f];
+            centre_dir(sbuf[lane], schat[lane]);
         }
+        // keep the next chunk's loads below the staging arithmetic (their
+        // registers would otherwise be live across it)
+        __builtin_amdgcn_sched_barrier(0);
         if (c - 64 >= rg.x) {   // the previous chunk's records, read while this one is processed
             nid = pval[c - 64 + lane];
             const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
 #pragma unroll
             for (int f = 0; f < 6; ++f) nrec[f] = src[f];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) nch[f] = chat[nid].c[f];
         }
         const uint64_t m = __ballot(meets);
         const int nact = __popcll(m);
@@ -1080,7 +1110,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
             float s[kNg];
 #pragma unroll
             for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
-            flush_record(s, frame[id], sbuf[lane].M, schat[lane].c, fd.pose,
+            const FrameRec fr = flush_axes(sbuf[lane]);
+            flush_record(s, fr, sbuf[lane].M, schat[lane].c, fd.pose,
                          acc_base ? acc_base + (size_t)(id - fd.item_off) * kAccStride : nullptr, pacc);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1124,7 +1155,7 @@ template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
             const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
-            const FrameRec *__restrict__ frame, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+            const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
             const double2 *__restrict__ tables, const float *__restrict__ stT_all,
             const int32_t *__restrict__ stN_all, double *__restrict__ gn_part)
 {
@@ -1176,11 +1207,12 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
         if ((int)threadIdx.x < cnt) {
             const uint32_t id = pval[b0 + threadIdx.x];
             srec[threadIdx.x] = rec[id];
-            const FrameRec &fr = frame[id];
+            double ba[3], bb[3], bc[3];
+            record_axes(srec[threadIdx.x], ba, bb, bc);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sab[threadIdx.x][c] = (float)fr.ba[c];
-                sab[threadIdx.x][3 + c] = (float)fr.bb[c];
+                sab[threadIdx.x][c] = (float)ba[c];
+                sab[threadIdx.x][3 + c] = (float)bb[c];
             }
         }
         __syncthreads();
@@ -1308,8 +1340,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
         hipLaunchKernelGGL(k_raster_bwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
-                           reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                           reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
+                           reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels,
@@ -1318,8 +1349,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     }
     hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
-                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                       reinterpret_cast<const ChatRec *>(ws + L.chat), pval,
+                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<double *>(ws + L.pose_part),
@@ -1333,8 +1363,7 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     hipLaunchKernelGGL(k_raster_gn<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
-                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), reinterpret_cast<const FrameRec *>(ws + L.frame),
-                       pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                       ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<double *>(ws + L.gn_part));
 }

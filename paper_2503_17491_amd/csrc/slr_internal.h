@@ -33,7 +33,8 @@ struct __align__(16) RasterRec {
 };
 static_assert(sizeof(RasterRec) == 96, "RasterRec layout");
 
-// Sensor-frame splat axes for the per-surfel gradient conversion.
+// Sensor-frame splat axes of a record (rebuilt from its P, Q, M when a
+// record's sums are converted into splat gradients).
 struct __align__(16) FrameRec {
     double ba[3], bb[3], bc[3];
     float n[3];
@@ -41,8 +42,9 @@ struct __align__(16) FrameRec {
 };
 static_assert(sizeof(FrameRec) == 96, "FrameRec layout");
 
-// Unit centre direction b_c / |b_c| of a record (FP64), the reference the
-// backward subtracts from pixel rays before accumulating.
+// Unit direction of b_c of a record (FP64), the reference the backward
+// subtracts from pixel rays before accumulating (derived from the record when
+// it is staged).
 struct ChatRec {
     double c[3];
 };
@@ -100,7 +102,7 @@ struct Layout {
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
-    size_t desc, tables, tile_frame, rec, frame, chat, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
+    size_t desc, tables, tile_frame, rec, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
     size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
