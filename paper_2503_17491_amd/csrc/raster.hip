@@ -600,7 +600,7 @@ k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     }
 }
 
-constexpr int kBwdBatch = 128;
+constexpr int kBwdBatch = 192;   // records staged per backward batch (fits 4 workgroups per CU)
 constexpr int kNg = 18;
 
 __device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
