@@ -318,7 +318,7 @@ def main():
         for u in br.up:
             for t in u:
                 t.fill_(1.0)
-        tune_ms = br.autotune()
+        tune_ms = br.autotune(reps=5)
         th, tw, var, sch, bvar, box = br.tiling
         log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}": round(v, 3) for c, v in tune_ms.items()})
     rend = [slr.Renderer(sensor, (th, tw, var, sch, bvar, box), capacity=4 << 20) for _ in kfs]
