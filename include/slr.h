@@ -286,9 +286,10 @@ slr_status slr_batch_autotune(int32_t n_sets, const slr_surfels *sets, const slr
                               int32_t n_candidates, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
                               int32_t reps, double *ms, int32_t *best, void *stream);
 
-/* Device address of three uint64 words in the workspace: the pair count K
- * of the last render, the overflow word (K when K > pair_capacity, else 0)
- * and the pair count actually binned. */
+/* Device address of four uint64 words in the workspace: the pair count K
+ * of the last render, the overflow word (K when K > pair_capacity, else 0),
+ * the pair count actually binned and the number of surfel records that bin
+ * into at least one tile. */
 slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
                               const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                               size_t workspace_bytes, const uint64_t **counters);

@@ -4,8 +4,11 @@
 // index).  They are produced by a least-significant-digit radix sort on the
 // composite (tile, range) key, split in two stages because all pairs of one
 // surfel share its range digits:
+//   0. the surfels that bin into at least one tile are compacted, in index
+//      order, into (range key, index) pairs: on a LiDAR frame a third or more
+//      of the map is behind the sensor, culled or outside the image;
 //   1. the range digits are sorted at surfel granularity: a stable LSD radix
-//      sort of the N (key, index) pairs (8-bit digits, 4 passes);
+//      sort of those pairs (8-bit digits, 4 passes);
 //   2. the pairs are emitted in that order (exclusive scan of the per-surfel
 //      tile counts, then one thread per surfel writes its tile indices);
 //   3. the tile digits are sorted with the same stable LSD radix passes over
@@ -189,9 +192,11 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
 
 // ---- scan of tile counts in range order ----
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_reduce(const uint32_t *__restrict__ rcounts, int64_t n, uint32_t *__restrict__ blocksum)
+k_scan_reduce(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t *__restrict__ n_dev,
+              uint32_t *__restrict__ blocksum)
 {
     __shared__ uint32_t s_wave[kWaves];
+    const int64_t n = (int64_t)min((uint64_t)n_max, *n_dev);
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     uint32_t acc = 0;
 #pragma unroll 4
@@ -221,11 +226,12 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n, const uint32_t *__restrict__ blocksum,
-             uint32_t *__restrict__ offsets)
+k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t *__restrict__ n_dev,
+             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_items[kSortTile];
+    const int64_t n = (int64_t)min((uint64_t)n_max, *n_dev);
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
@@ -252,6 +258,73 @@ k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n, const uint32_t *__
     }
 }
 
+// ---- compaction of the records that bin into some tile ----
+// Records without a tile (culled, behind, outside the image: count 0) do not
+// enter the range sort.  The visible ones keep their index order, so the
+// stable sort still breaks range ties by index.
+__global__ void __launch_bounds__(kSortThreads)
+k_vis_count(const int32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ blocksum)
+{
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) acc += cnt[idx] > 0 ? 1u : 0u;
+    }
+    uint32_t tot;
+    block_exscan(acc, s_wave, &tot);
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+}
+
+// Ranks are row-major like the radix scatter's: items base + i kSortThreads +
+// t, so every wave's surviving lanes of one row write consecutive slots.
+__global__ void __launch_bounds__(kSortThreads)
+k_vis_write(const uint32_t *__restrict__ keys, const int32_t *__restrict__ cnt, int64_t n,
+            const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout)
+{
+    constexpr int kSlots = kSortItems * kWaves;
+    __shared__ uint32_t s_pre[kSlots];   // (row, wave) -> rank of its first survivor in the block
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint64_t mask[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+        mask[i] = __ballot(idx < n && cnt[idx] > 0);
+        if (lane == 0) s_pre[i * kWaves + wid] = (uint32_t)__popcll(mask[i]);
+    }
+    __syncthreads();
+    if (wid == 0) {
+        uint32_t carry = 0;
+        for (int c0 = 0; c0 < kSlots; c0 += 64) {
+            const int c = c0 + lane;
+            const uint32_t v = c < kSlots ? s_pre[c] : 0u;
+            uint32_t x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (c < kSlots) s_pre[c] = carry + x - v;
+            carry += __shfl(x, 63, 64);
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    const uint32_t b0 = blocksum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if ((mask[i] >> lane) & 1ull) {
+            const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
+            const uint32_t pos = b0 + s_pre[i * kWaves + wid] + (uint32_t)__popcll(mask[i] & lt);
+            kout[pos] = keys[idx];
+            vout[pos] = (uint32_t)idx;
+        }
+    }
+}
+
 // Pair-capacity check on the device: the effective pair count is K, or 0 with
 // the overflow word set to K when K exceeds the capacity.
 __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
@@ -264,11 +337,11 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
 // One thread per record in range order: write its global tile indices and its index.
 __global__ void __launch_bounds__(256)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-       const uint32_t *__restrict__ rcounts, const PixBox *__restrict__ rbox, int64_t n, const uint64_t *__restrict__ keff,
-       uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
+       const uint32_t *__restrict__ rcounts, const PixBox *__restrict__ rbox, const uint64_t *__restrict__ n_dev,
+       const uint64_t *__restrict__ keff, uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n || *keff == 0) return;
+    if ((uint64_t)r >= *n_dev || *keff == 0) return;
     if (rcounts[r] == 0) return;
     const uint32_t id = order[r];
     PixBox b = rbox[r];
@@ -374,12 +447,18 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     uint32_t *k1 = reinterpret_cast<uint32_t *>(ws + L.key1), *v1 = reinterpret_cast<uint32_t *>(ws + L.val1);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
-    // pass 0 reads the per-record keys (kept for inspection) and the indices in val0
+    uint64_t *nvis = reinterpret_cast<uint64_t *>(ws + L.misc) + 3;
+    // the records that bin into some tile, in index order, into (key0, val0)
+    const int32_t *cnt = reinterpret_cast<const int32_t *>(ws + L.cnt);
+    uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
+    const int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(k_vis_count, dim3(nblocks), dim3(kSortThreads), 0, stream, cnt, L.items, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, nvis);
+    hipLaunchKernelGGL(k_vis_write, dim3(nblocks), dim3(kSortThreads), 0, stream, ks, cnt, L.items, bs, k0, v0);
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
-        const uint32_t *kin = p == 0 ? ks : (even ? k0 : k1);
         const bool last = p == L.depth_passes - 1;
-        radix_pass(kin, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nullptr, 8 * p, 8, hist, totals,
+        radix_pass(even ? k0 : k1, even ? v0 : v1, even ? k1 : k0, even ? v1 : v0, L.items, nvis, 8 * p, 8, hist, totals,
                    stream, last ? reinterpret_cast<const PixBox *>(ws + L.box) : nullptr,
                    last ? reinterpret_cast<uint32_t *>(ws + L.rcnt) : nullptr,
                    last ? reinterpret_cast<PixBox *>(ws + L.rbox) : nullptr);
@@ -390,15 +469,16 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
 {
     uint64_t *misc = reinterpret_cast<uint64_t *>(ws + L.misc);
     if (L.items == 0) {
-        launch_fill_u32(misc, 0u, 6, stream);
+        launch_fill_u32(misc, 0u, 8, stream);
         return;
     }
+    const uint64_t *nvis = misc + 3;
     const uint32_t *rcounts = reinterpret_cast<const uint32_t *>(ws + L.rcnt);   // in range order
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
     int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, bs);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, bs,
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs,
                        reinterpret_cast<uint32_t *>(ws + L.off));
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
@@ -425,7 +505,8 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
                        reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
-                       reinterpret_cast<const PixBox *>(ws + L.rbox), L.items, keff, t0, v0);
+                       reinterpret_cast<const PixBox *>(ws + L.rbox),
+                       reinterpret_cast<const uint64_t *>(ws + L.misc) + 3, keff, t0, v0);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);
     // split the tile bits evenly over the passes (each <= 8 bits)

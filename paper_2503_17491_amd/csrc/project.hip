@@ -245,7 +245,7 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
 __global__ void __launch_bounds__(256)
 k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ tables, double cm, double sm,
           RasterRec *__restrict__ rec, PixBox *__restrict__ box,
-          uint32_t *__restrict__ keys, uint32_t *__restrict__ ids, int32_t *__restrict__ counts, int box_mode)
+          uint32_t *__restrict__ keys, int32_t *__restrict__ counts, int box_mode)
 {
     const FrameDesc &fd = descs[blockIdx.y];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,7 +255,6 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     const double2 *col = tables + fd.tab_off;
     const double2 *rlo = col + W + H;
     const double2 *rhi = rlo + H;
-    ids[it] = (uint32_t)it;
     float fm0 = fd.means[3 * k], fm1 = fd.means[3 * k + 1], fm2 = fd.means[3 * k + 2];
     float4 fq = *reinterpret_cast<const float4 *>(fd.quats + 4 * k);
     float fl0 = fd.lsc[2 * k], fl1 = fd.lsc[2 * k + 1], flg = fd.logits[k];
@@ -395,7 +394,7 @@ void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double2 *>(ws + L.tables),
                        cos(kBoxMargin), sin(kBoxMargin), reinterpret_cast<RasterRec *>(ws + L.rec),
                        reinterpret_cast<PixBox *>(ws + L.box),
-                       reinterpret_cast<uint32_t *>(ws + L.skey), reinterpret_cast<uint32_t *>(ws + L.val0),
+                       reinterpret_cast<uint32_t *>(ws + L.skey),
                        reinterpret_cast<int32_t *>(ws + L.cnt), (int)L.box_mode);
 }
 

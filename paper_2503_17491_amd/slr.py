@@ -383,7 +383,7 @@ class BatchRenderer:
         _check(lib().slr_batch_counters(*self._args(), _ptr(self.ws), self.ws.numel(), C.byref(ptr)),
                "slr_batch_counters")
         off = ptr.value - self.ws.data_ptr()
-        self.counters = self.ws[off:off + 24].view(torch.int64)
+        self.counters = self.ws[off:off + 32].view(torch.int64)
 
     def render(self):
         _check(lib().slr_batch_render(*self._args(), _ptr(self.ws), self.ws.numel(), _stream()), "slr_batch_render")
@@ -398,6 +398,10 @@ class BatchRenderer:
         """(K, overflow) of the last render (synchronises)."""
         c = self.counters.cpu().tolist()
         return int(c[0]), int(c[1])
+
+    def binned_records(self):
+        """Number of surfel records of the last render that bin into some tile (synchronises)."""
+        return int(self.counters[3].cpu())
 
     def ensure_capacity(self, margin=1.25):
         """Grow the pair capacity if the last render overflowed; True if it did."""

@@ -70,10 +70,11 @@ def test_batched_matches_plain(slr, tiling):
     K, over = br.pairs()
     assert over == 0 and K > 0
     sum_g = {k: torch.zeros_like(v) for k, v in br.grads[0].items()}
-    Ksum = 0
+    Ksum = vis = 0
     for k, f in enumerate(frames):
         (D, N, A), g, dp, r = plain_frame(slr, sets[f["set"]], f, tiling, br.up[k])
         Ksum += r.K
+        vis += int((r.views()["counts"] > 0).sum())
         # forward: bit-identical (same per-pixel contributor order and arithmetic)
         for a, b in zip((D, N, A), br.out[k]):
             assert torch.equal(a, b), f"frame {k}"
@@ -86,6 +87,7 @@ def test_batched_matches_plain(slr, tiling):
                 np.testing.assert_allclose(br.grads[1][key].cpu().numpy(), g[key].cpu().numpy(), rtol=1e-4,
                                            atol=1e-6)
     assert K == Ksum
+    assert br.binned_records() == vis
     for key in sum_g:
         a, b = br.grads[0][key].cpu().numpy(), sum_g[key].cpu().numpy()
         scale = np.abs(b).max()
