@@ -10,7 +10,8 @@
 //   1. the range digits are sorted at surfel granularity: a stable LSD radix
 //      sort of those pairs (8-bit digits, 4 passes);
 //   2. the pairs are emitted in that order (exclusive scan of the per-surfel
-//      tile counts, then one thread per surfel writes its tile indices);
+//      tile counts, then blocks of a fixed number of output slots expand the
+//      surfels that cover them);
 //   3. the tile digits are sorted with the same stable LSD radix passes over
 //      the K pairs (ceil(log2 tiles / 8) passes);
 //   4. tile ranges [start, end) from key boundaries.
@@ -28,6 +29,7 @@ namespace slr {
 namespace {
 
 constexpr int kWaves = kSortThreads / 64;
+constexpr int kEmitThreads = 256;
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
@@ -227,7 +229,8 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
 
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t *__restrict__ n_dev,
-             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets)
+             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets, uint32_t *__restrict__ estart,
+             uint64_t cap)
 {
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_items[kSortTile];
@@ -254,7 +257,16 @@ k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) offsets[idx] = s_items[i * kSortThreads + threadIdx.x];
+        if (idx < n) {
+            const uint32_t o = s_items[i * kSortThreads + threadIdx.x];
+            offsets[idx] = o;
+            // the record holding the first slot of emit block m: exactly one
+            // record covers each slot m kEmitSlots < K (blocks past the pair
+            // capacity are never emitted)
+            const uint64_t e = min((uint64_t)o + rcounts[idx], cap);
+            for (uint64_t m = ((uint64_t)o + kEmitSlots - 1) / kEmitSlots; m * kEmitSlots < e; ++m)
+                estart[m] = (uint32_t)idx;
+        }
     }
 }
 
@@ -334,30 +346,65 @@ __global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
     misc[2] = K > cap ? 0 : K;
 }
 
-// One thread per record in range order: write its global tile indices and its index.
-__global__ void __launch_bounds__(256)
+// Pairs of the records in range order, kEmitSlots output slots per block.
+// The pair counts are skewed (the nearest surfels come first in range order
+// and span the most tiles), so the work is split by slots, not by records:
+// block m fills slots [m S, m S + S) and decodes into LDS the records that
+// cover them, from the one the scan marked as holding slot m S on.  Every
+// record has at least one pair, so a block sees at most S + 1 records.  A
+// slot's record is the last one whose offset is <= the slot; within a record
+// the slots go row by row, and in a row the first column interval, then the
+// second.  Consecutive threads write consecutive slots.
+__global__ void __launch_bounds__(kEmitThreads)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-       const uint32_t *__restrict__ rcounts, const PixBox *__restrict__ rbox, const uint64_t *__restrict__ n_dev,
+       const PixBox *__restrict__ rbox, const uint32_t *__restrict__ estart, const uint64_t *__restrict__ n_dev,
        const uint64_t *__restrict__ keff, uint32_t *__restrict__ ptile, uint32_t *__restrict__ pval)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((uint64_t)r >= *n_dev || *keff == 0) return;
-    if (rcounts[r] == 0) return;
-    const uint32_t id = order[r];
-    PixBox b = rbox[r];
-    const FrameDesc &fd = descs[b.frame];
-    const int th = fd.th, tw = fd.tw, tiles_x = fd.tiles_x, toff = fd.tile_off;
-    uint32_t o = offsets[r];
-    int ty0 = b.r0 / th, ty1 = b.r1 / th;
-    int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
-    int bx0 = 0, bx1 = -1;
-    if (b.c2 >= 0) {
-        bx0 = b.c2 / tw; bx1 = b.c3 / tw;
-        if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
+    constexpr int kRecs = kEmitSlots + 1;
+    __shared__ uint32_t s_off[kRecs], s_id[kRecs], s_row0[kRecs];
+    __shared__ int32_t s_ty0[kRecs], s_ax0[kRecs], s_na[kRecs], s_bx0[kRecs], s_len[kRecs], s_tx[kRecs];
+    const uint64_t K = *keff, n = *n_dev;
+    const uint64_t q0 = (uint64_t)blockIdx.x * kEmitSlots;
+    if (q0 >= K || n == 0) return;
+    const uint64_t qend = q0 + kEmitSlots < K ? q0 + kEmitSlots : K;
+    const uint32_t k0 = estart[blockIdx.x];
+    uint64_t klast = qend < K ? (uint64_t)estart[blockIdx.x + 1] : n - 1;
+    klast = klast < n - 1 ? klast : n - 1;
+    const int nrec = klast < k0 ? 1 : (int)min(klast - k0 + 1, (uint64_t)kRecs);
+    for (int i = threadIdx.x; i < nrec; i += kEmitThreads) {
+        const uint32_t r = k0 + (uint32_t)i;
+        const PixBox b = rbox[r];
+        const FrameDesc &fd = descs[b.frame];
+        const int th = fd.th, tw = fd.tw;
+        int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
+        int bx0 = 0, bx1 = -1;
+        if (b.c2 >= 0) {
+            bx0 = b.c2 / tw; bx1 = b.c3 / tw;
+            if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
+        }
+        s_off[i] = offsets[r];
+        s_id[i] = order[r];
+        s_ty0[i] = b.r0 / th;
+        s_ax0[i] = ax0;
+        s_na[i] = ax1 - ax0 + 1;
+        s_bx0[i] = bx0;
+        s_len[i] = (ax1 - ax0 + 1) + (bx1 - bx0 + 1);
+        s_tx[i] = fd.tiles_x;
+        s_row0[i] = (uint32_t)fd.tile_off;
     }
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = ax0; tx <= ax1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
-        for (int tx = bx0; tx <= bx1; ++tx) { ptile[o] = (uint32_t)(toff + ty * tiles_x + tx); pval[o] = id; ++o; }
+    __syncthreads();
+    for (uint64_t q = q0 + threadIdx.x; q < qend; q += kEmitThreads) {
+        const uint32_t qq = (uint32_t)q;
+        int lo = 0;
+#pragma unroll
+        for (int step = kEmitSlots; step > 0; step >>= 1)
+            if (lo + step < nrec && s_off[lo + step] <= qq) lo += step;
+        const int j = (int)(qq - s_off[lo]);
+        const int len = s_len[lo], na = s_na[lo];
+        const int dy = j / len, cc = j - dy * len;
+        const int tx = cc < na ? s_ax0[lo] + cc : s_bx0[lo] + (cc - na);
+        ptile[q] = s_row0[lo] + (uint32_t)((s_ty0[lo] + dy) * s_tx[lo] + tx);
+        pval[q] = s_id[lo];
     }
 }
 
@@ -479,7 +526,8 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs,
-                       reinterpret_cast<uint32_t *>(ws + L.off));
+                       reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.estart),
+                       (uint64_t)L.cap);
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
@@ -502,10 +550,10 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *order = reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0));
     uint32_t *t0 = reinterpret_cast<uint32_t *>(ws + L.pt0), *v0 = reinterpret_cast<uint32_t *>(ws + L.pv0);
     uint32_t *t1 = reinterpret_cast<uint32_t *>(ws + L.pt1), *v1 = reinterpret_cast<uint32_t *>(ws + L.pv1);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.items + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((L.cap + kEmitSlots - 1) / kEmitSlots)), dim3(kEmitThreads), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), order,
-                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
-                       reinterpret_cast<const PixBox *>(ws + L.rbox),
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const PixBox *>(ws + L.rbox),
+                       reinterpret_cast<const uint32_t *>(ws + L.estart),
                        reinterpret_cast<const uint64_t *>(ws + L.misc) + 3, keff, t0, v0);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.misc + 64);

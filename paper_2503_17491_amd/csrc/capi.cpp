@@ -378,6 +378,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.key0 = take(4 * nn); L.val0 = take(4 * nn); L.key1 = take(4 * nn); L.val1 = take(4 * nn);
     L.cnt = take(4 * nn);
     L.off = take(4 * nn);
+    // per emit block: the record holding its first pair slot
+    L.estart = take(4 * (size_t)(cc / kEmitSlots + 2));
     const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);

@@ -83,6 +83,7 @@ constexpr int kAccStride = 13;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // items per block
+constexpr int kEmitSlots = 512;                      // (tile, surfel) pairs per emit block (a power of two)
 constexpr int kMaxDigitBits = 8;
 
 // Workgroups of the one-wave compositing forms: 4 strips per tile, tiles in
@@ -102,7 +103,7 @@ struct Layout {
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;
-    size_t desc, tables, tile_frame, rec, box, skey, key0, val0, key1, val1, cnt, off, blocksum;
+    size_t desc, tables, tile_frame, rec, box, skey, key0, val0, key1, val1, cnt, off, estart, blocksum;
     size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
