@@ -7,7 +7,8 @@
 //   * the range key: FP32 rounding of |b_c|;
 //   * the bounding box of Sec. 3.2.3 / Supp. B, computed as the exact angular
 //     box of the 3-sigma splat square, widened by an angular margin, with the
-//     azimuth seam handled by ordering directions instead of angles (no atan2);
+//     azimuth seam handled by ordering directions instead of angles (angles
+//     only guess where the exact direction tests start);
 //   * the tile count of the box.
 // The key and the box use only IEEE-exact FP64 +,-,*,/,sqrt in a fixed order
 // (this translation unit is compiled with contraction off) plus host-made
@@ -58,6 +59,33 @@ __device__ inline bool angle_le(double ax, double ay, double bx, double by)
 // Elevation of (r, z) strictly below elevation of (r', z') (r, r' >= 0).
 __device__ inline bool elev_below(double r, double z, double r2, double z2) { return z * r2 - r * z2 < 0.0; }
 
+// First index in [0, n) where a monotone predicate holds (n if none), as a
+// bisection finds it, but started from a guess: two independent probes at
+// g - 1 and g settle it when the guess is right; otherwise the bisection runs
+// on the side the probes leave open.  The guess changes only the cost.
+template <class Pred>
+__device__ int first_true(int g, int n, const Pred &pred)
+{
+    g = g < 0 ? 0 : (g > n ? n : g);
+    const bool below = g > 0 ? pred(g - 1) : false;
+    const bool at = g < n ? pred(g) : true;
+    if (!below && at) return g;
+    int lo = below ? 0 : g + 1, hi = below ? g - 1 : n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pred(mid)) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Guess of the first index i with a boundary position x <= i (ceil) or
+// x < i (floor + 1), from an FP32 estimate; 0 when x is not a usable number.
+__device__ inline int guess_ceil(float x, int n) { return (x > -1.0f && x < (float)n + 1.0f) ? (int)ceilf(x) : 0; }
+__device__ inline int guess_above(float x, int n)
+{
+    return (x > -1.0f && x < (float)n + 1.0f) ? (int)floorf(x) + 1 : 0;
+}
+
 struct BoxOut {
     int nint;   // 0 = empty
     int r0, r1, c[4];
@@ -88,7 +116,8 @@ __device__ double support_radius(double logit)
 // points on the edges), kept for comparison -- it can miss pixels.
 __device__ BoxOut angular_box(const double A[3], const double B[3], const double C[3], double range, int H, int W,
                               const double2 *__restrict__ col, const double2 *__restrict__ rlo,
-                              const double2 *__restrict__ rhi, double cm, double sm, bool vertex_only)
+                              const double2 *__restrict__ rhi, double cm, double sm, bool vertex_only,
+                              float fu, float cu, float fv, float cv)
 {
     BoxOut o;
     o.nint = 0;
@@ -163,28 +192,27 @@ __device__ BoxOut angular_box(const double A[3], const double B[3], const double
         }
     }
     // rows: elevation decreases with the row index
+    // Row i has elevation (i + 1/2 - cv) / fv (fv < 0: decreasing with i); the
+    // guesses invert that in FP32, the decisions are the exact FP64 tests.
+    const float kMarginF = (float)kBoxMargin;
     int r0, r1;
     if (to_top) {
         r0 = 0;
     } else {  // first row with el_i - margin <= el_max
-        int lo = 0, hi = H;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            double2 e = rlo[mid];
-            if (zmax * e.x - rmax * e.y >= 0.0) hi = mid; else lo = mid + 1;
-        }
-        r0 = lo;
+        const float el = atan2f((float)zmax, (float)rmax);
+        r0 = first_true(guess_ceil(fv * (el + kMarginF) + cv - 0.5f, H), H, [&](int i) {
+            const double2 e = rlo[i];
+            return zmax * e.x - rmax * e.y >= 0.0;
+        });
     }
     if (to_bottom) {
         r1 = H - 1;
     } else {  // last row with el_i + margin >= el_min
-        int lo = 0, hi = H;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            double2 e = rhi[mid];
-            if (!(zmin * e.x - rmin * e.y <= 0.0)) hi = mid; else lo = mid + 1;
-        }
-        r1 = lo - 1;
+        const float el = atan2f((float)zmin, (float)rmin);
+        r1 = first_true(guess_above(fv * (el - kMarginF) + cv - 0.5f, H), H, [&](int i) {
+                 const double2 e = rhi[i];
+                 return !(zmin * e.x - rmin * e.y <= 0.0);
+             }) - 1;
     }
     if (r0 > r1) return o;
     o.r0 = r0; o.r1 = r1;
@@ -202,20 +230,18 @@ __device__ BoxOut angular_box(const double A[3], const double B[3], const double
         if (!(xcross(lx, ly, ux, uy) > 0.0)) {
             full_az = true;
         } else {
-            int lo = 0, hi = W;  // first column with azimuth <= upper end
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                double2 d = col[mid];
-                if (angle_le(d.x, d.y, ux, uy)) hi = mid; else lo = mid + 1;
-            }
-            int jf = lo;
-            lo = 0; hi = W;      // last column with azimuth >= lower end
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                double2 d = col[mid];
-                if (!angle_le(lx, ly, d.x, d.y)) hi = mid; else lo = mid + 1;
-            }
-            int jl = lo - 1;
+            // column j has azimuth (j + 1/2 - cu) / fu (fu < 0: decreasing with j)
+            const float azu = atan2f((float)uy, (float)ux), azl = atan2f((float)ly, (float)lx);
+            // first column with azimuth <= upper end
+            const int jf = first_true(guess_ceil(fu * azu + cu - 0.5f, W), W, [&](int j) {
+                const double2 d = col[j];
+                return angle_le(d.x, d.y, ux, uy);
+            });
+            // last column with azimuth >= lower end
+            const int jl = first_true(guess_above(fu * azl + cu - 0.5f, W), W, [&](int j) {
+                               const double2 d = col[j];
+                               return !angle_le(lx, ly, d.x, d.y);
+                           }) - 1;
             if (angle_le(lx, ly, ux, uy)) {
                 if (jf > jl) return o;
                 o.c[0] = jf; o.c[1] = jl; o.c[2] = -1; o.c[3] = -1;
@@ -306,7 +332,9 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     }
     BoxOut bx;
     bx.nint = 0;
-    if (ok) bx = angular_box(A, B, C, range, H, W, col, rlo, rhi, cm, sm, box_mode == SLR_BOX_VERTEX);
+    if (ok)
+        bx = angular_box(A, B, C, range, H, W, col, rlo, rhi, cm, sm, box_mode == SLR_BOX_VERTEX, (float)fd.fu,
+                         (float)fd.cu, (float)fd.fv, (float)fd.cv);
     int32_t cnt = 0;
     PixBox pb = {-1, -1, -1, -1, -1, -1, (int16_t)blockIdx.y, 0};
     if (bx.nint > 0) {
