@@ -83,10 +83,8 @@ def make_batch(torch, slr, d, sensor, kfs, tiling):
 
 def batched_step(slr, br, kfs, loss):
     br.render()
-    for k, kf in enumerate(kfs):
-        D, N, _ = br.out[k]
-        gD, gN, _ = br.up[k]
-        slr.loss_l1_normal(D, N, kf["Dt"], kf["Nt"], kf["w"], kf["w"], gD, gN, loss)
+    slr.loss_l1_normal_frames([(br.out[k][0], br.out[k][1], kf["Dt"], kf["Nt"], kf["w"], kf["w"], br.up[k][0],
+                                br.up[k][1]) for k, kf in enumerate(kfs)], loss)
     br.backward()
 
 

@@ -322,6 +322,23 @@ slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *n
                               const float *target_normal, float w_d, float w_n, float *dL_ddepth,
                               float *dL_dnormal, double *loss, void *stream);
 
+/* The same loss over several images in one call (the keyframes of a batch):
+ * image f has its own pixel count, buffers (layouts as in
+ * slr_loss_l1_normal, device, FP32; outputs overwritten) and weights, and its
+ * gradients are bit-identical to an slr_loss_l1_normal call on it alone.  The
+ * sum of the images' L is added to *loss (device FP64, nullable; the
+ * summation order differs from separate calls).  frames is a host array of
+ * n_frames entries, read before the call returns.  Errors: n_frames < 0, a
+ * NULL frames array, a negative pixel count, a NULL buffer of an image with
+ * pixels, non-finite weights (nothing is launched then). */
+typedef struct slr_loss_frame {
+    int64_t pixels;
+    const float *depth, *normal, *target_depth, *target_normal;
+    float w_d, w_n;
+    float *dL_ddepth, *dL_dnormal;
+} slr_loss_frame;
+slr_status slr_loss_l1_normal_frames(int32_t n_frames, const slr_loss_frame *frames, double *loss, void *stream);
+
 /* Range image of a point cloud (Sec. 3.1, Eq. spherical-projection): each
  * point (device FP32 [n,3], sensor frame) goes to (u, v) = K psi(p) and lands
  * in the pixel whose cell contains it, (i, j) = (floor(v), floor(u)) (pixel

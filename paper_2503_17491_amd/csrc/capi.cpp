@@ -846,6 +846,28 @@ slr_status slr_loss_l1_normal(int64_t pixels, const float *depth, const float *n
     return SLR_OK;
 }
 
+slr_status slr_loss_l1_normal_frames(int32_t n_frames, const slr_loss_frame *frames, double *loss, void *stream)
+{
+    if (n_frames < 0) return fail(SLR_E_INVALID, "negative frame count");
+    if (n_frames > 0 && !frames) return fail(SLR_E_INVALID, "frames is NULL");
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const slr_loss_frame &x = frames[f];
+        if (x.pixels < 0) return fail(SLR_E_INVALID, "frame %d: negative pixel count", f);
+        if (x.pixels > 0 && (!x.depth || !x.normal || !x.target_depth || !x.target_normal || !x.dL_ddepth ||
+                             !x.dL_dnormal))
+            return fail(SLR_E_INVALID, "frame %d: loss buffer is NULL", f);
+        if (!std::isfinite(x.w_d) || !std::isfinite(x.w_n))
+            return fail(SLR_E_INVALID, "frame %d: loss weights must be finite", f);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        StageScope t(7, s);
+        slr::launch_loss_frames(n_frames, frames, loss, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
 slr_status slr_adam_step(int64_t n, float *means, float *quats, float *log_scales, float *logits,
                          const slr_surfel_grads *grads, float *m, float *v, const slr_adam_config *cfg, void *stream)
 {

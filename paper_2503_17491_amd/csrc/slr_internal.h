@@ -138,6 +138,11 @@ void launch_surfel_grad(const float *quats, const float *lsc, const float *logit
 void launch_loss_l1_normal(int64_t pixels, const float *depth, const float *normal, const float *td,
                            const float *tn, float wd, float wn, float *gD, float *gN, double *loss,
                            hipStream_t stream);
+constexpr int kLossFramesPerLaunch = 16;
+struct LossPack {
+    slr_loss_frame f[kLossFramesPerLaunch];
+};
+void launch_loss_frames(int32_t n_frames, const slr_loss_frame *frames, double *loss, hipStream_t stream);
 void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream);
 size_t photo_workspace_bytes(int32_t H, int32_t W);
 void launch_cloud_to_range(int32_t H, int32_t W, double fu, double cu, double fv, double cv, int64_t n,

@@ -18,38 +18,72 @@
 namespace slr {
 namespace {
 
+// One pixel of the loss: writes dL/dD and dL/dN, returns its share of L.
+// All loads are issued before the mask test, so a pixel costs one round trip.
+__device__ __forceinline__ double loss_pixel(int64_t p, const float *__restrict__ D, const float *__restrict__ N,
+                                             const float *__restrict__ Dt, const float *__restrict__ Nt, float wd,
+                                             float wn, float *__restrict__ gD, float *__restrict__ gN)
+{
+    const float dt = Dt[p], d = D[p];
+    const float t0 = Nt[3 * p], t1 = Nt[3 * p + 1], t2 = Nt[3 * p + 2];
+    const float m0 = N[3 * p], m1 = N[3 * p + 1], m2 = N[3 * p + 2];
+    float g = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    double part = 0.0;
+    if (dt > 0.f) {
+        const float r = d - dt;
+        g = r > 0.f ? wd : (r < 0.f ? -wd : 0.f);
+        const float dot = m0 * t0 + m1 * t1 + m2 * t2;
+        n0 = -wn * t0; n1 = -wn * t1; n2 = -wn * t2;
+        part = (double)wd * fabsf(r) + (double)wn * (1.0f - dot);
+    }
+    gD[p] = g;
+    gN[3 * p] = n0; gN[3 * p + 1] = n1; gN[3 * p + 2] = n2;
+    return part;
+}
+
+// Block sum of the loss shares into one FP64 atomic.  Same-address atomics
+// serialize, so the launches keep the number of blocks per image small.
+__device__ __forceinline__ void loss_block_add(double part, double *loss)
+{
+    __shared__ double s_part[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double v = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        if (v != 0.0) atomicAdd(loss, v);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_loss_l1_normal(int64_t P, const float *__restrict__ D, const float *__restrict__ N, const float *__restrict__ Dt,
                  const float *__restrict__ Nt, float wd, float wn, float *__restrict__ gD, float *__restrict__ gN,
                  double *__restrict__ loss)
 {
-    __shared__ double s_part[4];
     double part = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const float dt = Dt[p];
-        float g = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-        if (dt > 0.f) {
-            const float r = D[p] - dt;
-            g = r > 0.f ? wd : (r < 0.f ? -wd : 0.f);
-            const float t0 = Nt[3 * p], t1 = Nt[3 * p + 1], t2 = Nt[3 * p + 2];
-            const float dot = N[3 * p] * t0 + N[3 * p + 1] * t1 + N[3 * p + 2] * t2;
-            n0 = -wn * t0; n1 = -wn * t1; n2 = -wn * t2;
-            part += (double)wd * fabsf(r) + (double)wn * (1.0f - dot);
-        }
-        gD[p] = g;
-        gN[3 * p] = n0; gN[3 * p + 1] = n1; gN[3 * p + 2] = n2;
-    }
-    if (loss) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const double v = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-            if (v != 0.0) atomicAdd(loss, v);
-        }
-    }
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
+        part += loss_pixel(p, D, N, Dt, Nt, wd, wn, gD, gN);
+    if (loss) loss_block_add(part, loss);
 }
+
+// The same loss over up to kLossFramesPerLaunch images in one launch
+// (blockIdx.y = image), each with its own buffers and weights; every image's
+// per-pixel arithmetic is that of k_loss_l1_normal.
+__global__ void __launch_bounds__(256)
+k_loss_frames(LossPack pack, double *__restrict__ loss)
+{
+    const slr_loss_frame &f = pack.f[blockIdx.y];
+    double part = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < f.pixels;
+         p += (int64_t)gridDim.x * blockDim.x)
+        part += loss_pixel(p, f.depth, f.normal, f.target_depth, f.target_normal, f.w_d, f.w_n, f.dL_ddepth,
+                           f.dL_dnormal);
+    if (loss) loss_block_add(part, loss);
+}
+
+// blocks per image of the loss launches (see loss_block_add)
+constexpr int64_t kLossBlocks = 64;
 
 // omb1 = 1 - b1, omb2 = 1 - b2, both formed in FP64 on the host
 __device__ __forceinline__ void adam1(float &p, float g, float &m, float &v, float s, float omb1, float b2, float omb2,
@@ -104,9 +138,26 @@ void launch_loss_l1_normal(int64_t P, const float *D, const float *N, const floa
 {
     if (P <= 0) return;
     int64_t blocks = (P + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > kLossBlocks) blocks = kLossBlocks;
     hipLaunchKernelGGL(k_loss_l1_normal, dim3((unsigned)blocks), dim3(256), 0, stream, P, D, N, Dt, Nt, wd, wn, gD,
                        gN, loss);
+}
+
+void launch_loss_frames(int32_t n_frames, const slr_loss_frame *frames, double *loss, hipStream_t stream)
+{
+    for (int32_t b = 0; b < n_frames; b += kLossFramesPerLaunch) {
+        LossPack pack;
+        const int c = n_frames - b < kLossFramesPerLaunch ? n_frames - b : kLossFramesPerLaunch;
+        int64_t pmax = 0;
+        for (int i = 0; i < c; ++i) {
+            pack.f[i] = frames[b + i];
+            pmax = frames[b + i].pixels > pmax ? frames[b + i].pixels : pmax;
+        }
+        if (pmax <= 0) continue;
+        int64_t blocks = (pmax + 255) / 256;
+        if (blocks > kLossBlocks) blocks = kLossBlocks;
+        hipLaunchKernelGGL(k_loss_frames, dim3((unsigned)blocks, c), dim3(256), 0, stream, pack, loss);
+    }
 }
 
 }  // namespace slr

@@ -56,9 +56,16 @@ class SurfelGrads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("quats", C.c_void_p), ("log_scales", C.c_void_p), ("logits", C.c_void_p)]
 
 
+class LossFrame(C.Structure):
+    _fields_ = [("pixels", C.c_int64), ("depth", C.c_void_p), ("normal", C.c_void_p), ("target_depth", C.c_void_p),
+                ("target_normal", C.c_void_p), ("w_d", C.c_float), ("w_n", C.c_float), ("dL_ddepth", C.c_void_p),
+                ("dL_dnormal", C.c_void_p)]
+
+
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-           "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times",
+           "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames", "slr_adam_step",
+           "slr_stage_timer_enable", "slr_stage_times",
            "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
            "slr_scale_reg", "slr_init_workspace_size", "slr_init_splats", "slr_status_string", "slr_last_error"]
 
@@ -95,6 +102,7 @@ def lib():
         L.slr_batch_counters.argtypes = BATCH + [P]
         L.slr_batch_autotune.argtypes = [I32, P, P, I32, P, P, I32, I64, P, C.c_size_t, I32, P, P, P]
         L.slr_loss_l1_normal.argtypes = [I64, P, P, P, P, C.c_float, C.c_float, P, P, P, P]
+        L.slr_loss_l1_normal_frames.argtypes = [I32, P, P, P]
         L.slr_adam_step.argtypes = [I64, P, P, P, P, P, P, P, P, P]
         L.slr_stage_timer_enable.argtypes = [I32]
         L.slr_stage_times.argtypes = [P, P]
@@ -103,8 +111,8 @@ def lib():
         L.slr_last_error.restype = C.c_char_p
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-                  "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_adam_step",
-                  "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
+                  "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames",
+                  "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
                   "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg",
                   "slr_init_workspace_size", "slr_init_splats"):
             getattr(L, f).restype = I32
@@ -418,6 +426,21 @@ def loss_l1_normal(D, N, Dt, Nt, w_d, w_n, gD, gN, loss=None):
     P = D.numel()
     _check(lib().slr_loss_l1_normal(P, _ptr(D), _ptr(N), _ptr(Dt), _ptr(Nt), float(w_d), float(w_n), _ptr(gD),
                                     _ptr(gN), _ptr(loss), _stream()), "slr_loss_l1_normal")
+
+
+def loss_l1_normal_frames(items, loss=None):
+    """The fused loss over several images in one launch.  items: sequence of
+    (D, N, Dt, Nt, w_d, w_n, gD, gN) per image (writes gD, gN; adds the sum of
+    the images' losses to loss)."""
+    arr = (LossFrame * max(len(items), 1))()
+    for i, (D, N, Dt, Nt, w_d, w_n, gD, gN) in enumerate(items):
+        P = D.numel()
+        for t, k in ((Dt, 1), (N, 3), (Nt, 3), (gD, 1), (gN, 3)):
+            if t.numel() != k * P:
+                raise ValueError(f"image {i}: buffer sizes do not match {P} pixels")
+        arr[i] = LossFrame(P, D.data_ptr(), N.data_ptr(), Dt.data_ptr(), Nt.data_ptr(), float(w_d), float(w_n),
+                           gD.data_ptr(), gN.data_ptr())
+    _check(lib().slr_loss_l1_normal_frames(len(items), arr, _ptr(loss), _stream()), "slr_loss_l1_normal_frames")
 
 
 class AdamConfig(C.Structure):

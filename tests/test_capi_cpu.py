@@ -162,3 +162,24 @@ def test_photo_gn_rejects_bad_arguments_without_gpu():
     assert st == slr.SLR_E_INVALID and b"needs" in L.slr_last_error()
     st = L.slr_photo_gn(C.byref(s), ip, ip, None, tp, 0.0, None, need, op, None)
     assert st == slr.SLR_E_INVALID
+
+
+def test_loss_frames_rejects_bad_arguments_without_gpu():
+    L = slr.lib()
+    buf = np.zeros(3 * 64, np.float32)
+    p = buf.ctypes.data
+    good = slr.LossFrame(64, p, p, p, p, 1.0, 1.0, p, p)
+    assert L.slr_loss_l1_normal_frames(-1, None, None, None) == slr.SLR_E_INVALID
+    assert L.slr_loss_l1_normal_frames(2, None, None, None) == slr.SLR_E_INVALID
+    # valid calls pass validation (without a GPU the launch step then reports the runtime's error)
+    assert L.slr_loss_l1_normal_frames(0, None, None, None) != slr.SLR_E_INVALID
+    bad = [slr.LossFrame(-1, p, p, p, p, 1.0, 1.0, p, p), slr.LossFrame(64, p, None, p, p, 1.0, 1.0, p, p),
+           slr.LossFrame(64, p, p, p, p, float("nan"), 1.0, p, p), slr.LossFrame(64, p, p, p, p, 1.0, float("inf"), p, p),
+           slr.LossFrame(64, p, p, p, p, 1.0, 1.0, p, None)]
+    for b in bad:
+        arr = (slr.LossFrame * 2)(good, b)
+        assert L.slr_loss_l1_normal_frames(2, arr, None, None) == slr.SLR_E_INVALID
+        assert b"frame 1" in L.slr_last_error()
+    # an image without pixels needs no buffers
+    arr = (slr.LossFrame * 1)(slr.LossFrame(0, None, None, None, None, 1.0, 1.0, None, None))
+    assert L.slr_loss_l1_normal_frames(1, arr, None, None) != slr.SLR_E_INVALID

@@ -50,6 +50,42 @@ def test_loss_matches_oracle(slr, H, W):
     assert abs(loss.item() - L) <= 1e-6 * max(abs(L), 1e-30) + 1e-12
 
 
+def test_loss_frames_matches_single_image_calls(slr):
+    """18 images (two launches of at most 16), ragged sizes and an empty one:
+    gradients bit-identical to one call per image and to the oracle; the
+    summed loss to the oracle's sum."""
+    g = np.random.default_rng(7)
+    sizes = [(64, 512), (37, 300), (1, 1), (0, 0)] + [(16, 64)] * 14
+    items, ref, Lsum = [], [], 0.0
+    for k, (H, W) in enumerate(sizes):
+        P = H * W
+        D = g.uniform(0, 30, P).astype(np.float32)
+        Dt = (D + g.normal(0, 0.5, P)).astype(np.float32)
+        Dt[g.uniform(size=P) < 0.2] = 0.0
+        N = g.normal(size=(P, 3)).astype(np.float32)
+        Nt = g.normal(size=(P, 3)).astype(np.float32)
+        wd, wn = 1.0 / max(P, 1), (0.5 + 0.1 * k) / max(P, 1)
+        t = [torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for v in (D, N, Dt, Nt)]
+        gD = torch.full((P,), 7.0, device=DEV)
+        gN = torch.full((P, 3), 7.0, device=DEV)
+        items.append((t[0], t[1], t[2], t[3], wd, wn, gD, gN))
+        L, rD, rN = O.loss_l1_normal(D, N, Dt, Nt, wd, wn)
+        ref.append((rD, rN))
+        Lsum += L
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    say("loss over", len(items), "images")
+    slr.loss_l1_normal_frames(items, loss)
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        gD1, gN1 = torch.empty_like(it[6]), torch.empty_like(it[7])
+        slr.loss_l1_normal(it[0], it[1], it[2], it[3], it[4], it[5], gD1, gN1, None)
+        torch.cuda.synchronize()
+        assert torch.equal(it[6], gD1) and torch.equal(it[7], gN1), k
+        np.testing.assert_array_equal(it[6].cpu().numpy(), ref[k][0])
+        np.testing.assert_array_equal(it[7].cpu().numpy(), ref[k][1])
+    assert abs(loss.item() - Lsum) <= 1e-6 * abs(Lsum)
+
+
 @pytest.mark.parametrize("n", [1, 1000, 70001])
 def test_adam_matches_oracle(slr, n):
     say("adam", n)
