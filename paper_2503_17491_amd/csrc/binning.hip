@@ -82,15 +82,36 @@ __global__ void __launch_bounds__(kSortThreads)
 k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ totals)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_items[kSortTile];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
-    for (int b0 = 0; b0 < nblocks; b0 += kSortThreads) {
-        int b = b0 + threadIdx.x;
-        uint32_t v = b < nblocks ? row[b] : 0u;
+    // chunks of kSortTile counts: coalesced loads into LDS, kSortItems
+    // consecutive counts per thread, one block scan per chunk
+    for (int c0 = 0; c0 < nblocks; c0 += kSortTile) {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int b = c0 + i * kSortThreads + threadIdx.x;
+            s_items[i * kSortThreads + threadIdx.x] = b < nblocks ? row[b] : 0u;
+        }
+        __syncthreads();
+        uint32_t local[kSortItems], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            local[i] = sum;
+            sum += s_items[threadIdx.x * kSortItems + i];
+        }
         uint32_t tot;
-        uint32_t ex = block_exscan(v, s_wave, &tot);
-        if (b < nblocks) row[b] = carry + ex;
+        const uint32_t pre = carry + block_exscan(sum, s_wave, &tot);
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) s_items[threadIdx.x * kSortItems + i] = pre + local[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int b = c0 + i * kSortThreads + threadIdx.x;
+            if (b < nblocks) row[b] = s_items[i * kSortThreads + threadIdx.x];
+        }
         carry += tot;
+        __syncthreads();
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
@@ -412,11 +433,11 @@ __global__ void __launch_bounds__(256)
 k_ranges(const uint32_t *__restrict__ ptile, const uint64_t *__restrict__ keff, int2 *__restrict__ ranges)
 {
     const int64_t K = (int64_t)*keff;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= K) return;
-    uint32_t t = ptile[p];
-    if (p == 0 || ptile[p - 1] != t) ranges[t].x = (int)p;
-    if (p == K - 1 || ptile[p + 1] != t) ranges[t].y = (int)(p + 1);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < K; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = ptile[p];
+        if (p == 0 || ptile[p - 1] != t) ranges[t].x = (int)p;
+        if (p == K - 1 || ptile[p + 1] != t) ranges[t].y = (int)(p + 1);
+    }
 }
 
 // Longest-first tile schedule: tiles are bucketed by their list length on a
@@ -567,7 +588,9 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)
         done += bits;
     }
     const uint32_t *ts = L.tile_in_1 ? t1 : t0;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, stream, ts, keff, ranges);
+    const int64_t rblocks = (L.cap + 255) / 256;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)(rblocks < 8192 ? rblocks : 8192)), dim3(256), 0, stream, ts, keff,
+                       ranges);
     launch_tile_order(L, ws, stream);
 }
 

@@ -345,6 +345,14 @@ int grid_for(int64_t n)
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
+// Launches that end in one same-address FP64 atomic per block: those
+// atomics serialize, so few blocks loop over the items.
+int grid_reduce(int64_t n)
+{
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 128 ? (b > 0 ? b : 1) : 128);
+}
+
 }  // namespace
 
 void launch_cloud_to_range(int32_t H, int32_t W, double fu, double cu, double fv, double cv, int64_t n,
@@ -373,7 +381,7 @@ void launch_loss_map(int64_t P, const float *D, const float *N, const float *O, 
                      float wd, float wn, float wo, float *gD, float *gN, float *gO, double *loss, hipStream_t stream)
 {
     if (P == 0) return;
-    hipLaunchKernelGGL(k_loss_map, dim3(grid_for(P)), dim3(256), 0, stream, P, D, N, O, Dt, Nt, wd, wn, wo, gD, gN,
+    hipLaunchKernelGGL(k_loss_map, dim3(grid_reduce(P)), dim3(256), 0, stream, P, D, N, O, Dt, Nt, wd, wn, wo, gD, gN,
                        gO, loss);
 }
 
@@ -408,7 +416,7 @@ void launch_init_splats(int32_t H, int32_t W, double fu, double cu, double fv, d
 void launch_scale_reg(int64_t n, const float *ls, double tau, double ws, float *g, double *loss, hipStream_t stream)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_scale_reg, dim3(grid_for(n)), dim3(256), 0, stream, n, ls, tau, ws, g, loss);
+    hipLaunchKernelGGL(k_scale_reg, dim3(grid_reduce(n)), dim3(256), 0, stream, n, ls, tau, ws, g, loss);
 }
 
 }  // namespace slr
