@@ -233,7 +233,7 @@ k_scan_reduce(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict__ total_out)
+k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict__ total_out, int64_t cap)
 {
     __shared__ uint32_t s_wave[kWaves];
     uint64_t carry = 0;
@@ -245,7 +245,15 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
         if (b < nblocks) blocksum[b] = (uint32_t)carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total_out = carry;
+    if (threadIdx.x == 0) {
+        total_out[0] = carry;
+        // pair-capacity check (cap >= 0): the effective pair count is K, or 0
+        // with the overflow word set to K when K exceeds the capacity
+        if (cap >= 0) {
+            total_out[1] = carry > (uint64_t)cap ? carry : 0;
+            total_out[2] = carry > (uint64_t)cap ? 0 : carry;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kSortThreads)
@@ -356,15 +364,6 @@ k_vis_write(const uint32_t *__restrict__ keys, const int32_t *__restrict__ cnt, 
             vout[pos] = (uint32_t)idx;
         }
     }
-}
-
-// Pair-capacity check on the device: the effective pair count is K, or 0 with
-// the overflow word set to K when K exceeds the capacity.
-__global__ void k_capacity(uint64_t *__restrict__ misc, uint64_t cap)
-{
-    const uint64_t K = misc[0];
-    misc[1] = K > cap ? K : 0;
-    misc[2] = K > cap ? 0 : K;
 }
 
 // Pairs of the records in range order, kEmitSlots output slots per block.
@@ -521,7 +520,7 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
     const int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_vis_count, dim3(nblocks), dim3(kSortThreads), 0, stream, cnt, L.items, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, nvis);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, nvis, (int64_t)-1);
     hipLaunchKernelGGL(k_vis_write, dim3(nblocks), dim3(kSortThreads), 0, stream, ks, cnt, L.items, bs, k0, v0);
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
@@ -545,11 +544,10 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
     int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc, (int64_t)L.cap);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs,
                        reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.estart),
                        (uint64_t)L.cap);
-    hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, stream, misc, (uint64_t)L.cap);
 }
 
 static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)
