@@ -171,6 +171,66 @@ def test_graph_capture_replays_match_eager(slr):
             np.testing.assert_allclose(p.cpu().numpy(), r.cpu().numpy(), rtol=1e-6, atol=1e-9)
 
 
+def test_graph_step_with_loss_replays_match_eager(slr):
+    """The benchmark's step (render, loss over all keyframes in one launch,
+    backward) captured once and replayed: every replay matches the eager step
+    (images and loss gradients bit for bit, surfel and pose gradients to the
+    atomics' order, the loss to its summation order)."""
+    say("graph capture with the multi-image loss")
+    sets, frames, _, br = make_batch(slr)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    tg = []
+    for f in frames:
+        H, W = int(f["sensor"]["height"]), int(f["sensor"]["width"])
+        Dt = (torch.rand(H, W, generator=g) * 30.0) * (torch.rand(H, W, generator=g) > 0.2)
+        Nt = torch.nn.functional.normalize(torch.randn(H, W, 3, generator=g), dim=-1)
+        tg.append((Dt.to(DEV), Nt.to(DEV), 1.0 / max(int((Dt > 0).sum()), 1)))
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+
+    def step():
+        br.render()
+        slr.loss_l1_normal_frames([(br.out[k][0], br.out[k][1], Dt, Nt, w, w, br.up[k][0], br.up[k][1])
+                                   for k, (Dt, Nt, w) in enumerate(tg)], loss)
+        br.backward()
+
+    step()
+    torch.cuda.synchronize()
+    ref_out = [tuple(t.clone() for t in o) for o in br.out]
+    ref_up = [(u[0].clone(), u[1].clone()) for u in br.up]
+    ref_g = {k: v.clone() for k, v in br.grads[0].items()}
+    ref_p = [p.clone() for p in br.dpose]
+    ref_loss = loss.item()
+    assert ref_loss > 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=s):
+        step()
+    for rep in range(3):
+        loss.zero_()   # eager work between replays
+        for o in br.out:
+            for t in o:
+                t.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(br.out, ref_out):
+            for a, b in zip(o, r):
+                assert torch.equal(a, b), f"replay {rep}"
+        for u, r in zip(br.up, ref_up):
+            assert torch.equal(u[0], r[0]) and torch.equal(u[1], r[1]), f"replay {rep}"
+        assert abs(loss.item() - ref_loss) <= 1e-9 * ref_loss, rep
+        for k in ref_g:
+            d = (br.grads[0][k] - ref_g[k]).abs().max().item()
+            assert d <= 1e-4 * ref_g[k].abs().max().item(), (rep, k)
+        for p, r in zip(br.dpose, ref_p):
+            np.testing.assert_allclose(p.cpu().numpy(), r.cpu().numpy(), rtol=1e-6, atol=1e-9)
+
+
 def test_autotune_picks_a_candidate(slr):
     say("autotune")
     sets, frames, _, br = make_batch(slr, (16, 16))
