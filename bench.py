@@ -118,7 +118,10 @@ def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
     the pose, then the normal equations against the keyframe's target (least
     squares, weight 1 where the target has a return).  The 6x6 solve is the
     caller's and is not timed.  The kernel walks the pairs the backward walks,
-    so its algorithmic FLOP come from keyframe 0's backward census."""
+    so its algorithmic FLOP come from keyframe 0's backward census.  The
+    normal equations take their one-wave-per-strip form (backward form 3):
+    on one keyframe's 512 tiles the workgroup form waits at its barrier."""
+    tiling = tuple(tiling[:4]) + (slr.VARIANT_WAVE,) + tuple(tiling[5:])
     r = slr.Renderer(sensor, tiling, capacity=4 << 20)
     m = (kf["Dt"] > 0).float()
     buf = torch.empty(43, dtype=torch.float64, device="cuda")
@@ -147,7 +150,8 @@ def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
     flops = BWD_EVAL_FLOPS * census0[2] + GN_CONTRIB_FLOPS * census0[3]
     ach = flops / (ms * 1e-3) / 1e12
     return {"workload": "keyframe 0 of the map, 128x1024: render + Gauss-Newton normal equations per iteration",
-            "iter_s": round(steps / dt, 3), "kernel": "raster_gn", "kernel_ms": round(ms, 4),
+            "iter_s": round(steps / dt, 3), "kernel": "raster_gn_w", "form": "one wave per 64-pixel strip",
+            "kernel_ms": round(ms, 4),
             "render_ms": round(sum(st[k][0] for k in ("project", "range_sort", "count_scan", "emit_tile_sort",
                                                        "raster_fwd")) / n, 4),
             "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -184,8 +184,12 @@ slr_status slr_backward(const slr_surfels *surfels, const double *pose_cw, const
  * target = D_t, weight = m (nullable: all ones; 0 drops a pixel, e.g. where
  * the target has no return).  Output (device FP64, overwritten, 43 values):
  * H row-major [0..35], g [36..41], cost [42].  Sums are taken in a fixed
- * order (bit-reproducible).  Errors: NULL depth, target or normal_eq, NaN
- * huber_k, and the same checks as slr_backward. */
+ * order (bit-reproducible).  tiling.bwd_variant picks the kernel form:
+ * SLR_VARIANT_WAVE runs one wave per 64-pixel strip (no workgroup barrier;
+ * the faster form for a single keyframe), otherwise one workgroup per tile;
+ * both see the same records in the same order per pixel and agree to the
+ * last bits of FP32.  Errors: NULL depth, target or normal_eq, NaN huber_k,
+ * and the same checks as slr_backward. */
 slr_status slr_pose_gn(const slr_surfels *surfels, const double *pose_cw, const slr_sensor *sensor,
                        const slr_tiling *tiling, void *workspace, size_t workspace_bytes, int64_t pair_capacity,
                        const float *depth, const float *target, const float *weight, double huber_k,

@@ -388,8 +388,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.rbox = take(sizeof(PixBox) * nn);
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
     L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
-    // per Gauss-Newton workgroup (one per tile): its partial normal equations
-    L.gn_part = take(sizeof(double) * kGnRow * (size_t)L.tiles);
+    // per Gauss-Newton workgroup (one per tile) or strip wave (four per tile): its partial normal equations
+    L.gn_part = take(sizeof(double) * kGnRow * 4 * (size_t)L.tiles);   // up to four strip rows per tile
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));

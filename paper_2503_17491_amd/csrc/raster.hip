@@ -1305,6 +1305,153 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
     if (threadIdx.x == kGnVals) row[kGnVals] = (double)tile_frame[tile];
 }
 
+// Gauss-Newton terms, one wave per 64-pixel strip (the counterpart of
+// k_raster_gn without its workgroup barrier).  The strip's list is read from
+// its wave's last contributor backwards in chunks of 64 records, one per lane;
+// the records that meet the strip's rows are compacted and every lane runs the
+// reverse step for its pixel over them in reverse order.  A pixel sees the
+// same records in the same order with the same arithmetic as in k_raster_gn
+// (up to the compiler's choice of fused multiply-adds); the wave's sums are
+// written to row 4 tile slot + strip, and k_gn_reduce adds a tile's four
+// strip rows in the order k_raster_gn adds its four waves.
+template <int TW>
+__global__ void __launch_bounds__(64)
+k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+              const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
+              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+              const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+              const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, int64_t ntiles)
+{
+    constexpr int TH = 256 / TW, SR = 64 / TW;
+    __shared__ RasterRec sbuf[64];
+    __shared__ float sab[64][6];   // b_alpha, b_beta in FP32
+    __shared__ uint8_t slist[64];
+    int strip, tslot;
+    if (!strip_of_block(ntiles, strip, tslot)) return;
+    const int tile = order ? (int)order[tslot] : tslot;
+    const FrameDesc &fd = descs[tile_frame[tile]];
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x;
+    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + strip * SR, wr1 = wr0 + SR - 1;
+    const int p = inside ? i * W + j : 0;
+    const float Tfin = inside ? stT[p] : 1.0f;
+    const int last = inside ? stN[p] : 0;
+    int wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+
+    BwdState st = {Tfin, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    const BwdUpstream up = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, Tfin};   // dL/dD = 1
+    float J[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
+    for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
+        bool meets = false;
+        if (c + lane < end) {
+            sbuf[lane] = rec[pval[c + lane]];
+            const uint32_t rows = sbuf[lane].rows;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+            double ba[3], bb[3], bc[3];
+            record_axes(sbuf[lane], ba, bb, bc);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                sab[lane][q] = (float)ba[q];
+                sab[lane][3 + q] = (float)bb[q];
+            }
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        if (meets)
+            slist[__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = nact - 1; q >= 0; --q) {
+            const int k = slist[q];
+            const int pos = c + k - rg.x;
+            PairEval e;
+            const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
+            if (act) {
+                const RasterRec &r = sbuf[k];
+                const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up);
+                const float ax = sab[k][0], ay = sab[k][1], az = sab[k][2];
+                const float bx = sab[k][3], by = sab[k][4], bz = sab[k][5];
+                const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
+                J[0] += sc.da * (by * fvz - bz * fvy) + sc.db * (fvy * az - fvz * ay) - sc.tt * Mx;
+                J[1] += sc.da * (bz * fvx - bx * fvz) + sc.db * (fvz * ax - fvx * az) - sc.tt * My;
+                J[2] += sc.da * (bx * fvy - by * fvx) + sc.db * (fvx * ay - fvy * ax) - sc.tt * Mz;
+                const float km = sc.dcs - sc.tt * e.t;
+                const float gx = sc.da * (float)r.P[0] + sc.db * (float)r.Q[0] + km * Mx;
+                const float gy = sc.da * (float)r.P[1] + sc.db * (float)r.Q[1] + km * My;
+                const float gz = sc.da * (float)r.P[2] + sc.db * (float)r.Q[2] + km * Mz;
+                J[3] += fvy * gz - fvz * gy;
+                J[4] += fvz * gx - fvx * gz;
+                J[5] += fvx * gy - fvy * gx;
+            }
+        }
+        // every lane is done with this chunk's records before they are replaced
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // this pixel's terms and the wave's sums (FP64 butterflies), as in k_raster_gn
+    double Jd[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Jd[q] = J[q];
+    double wgt = 0.0, wr = 0.0, cost = 0.0;
+    if (inside) {
+        const float mw = fd.gn_weight ? fd.gn_weight[p] : 1.0f;
+        if (mw != 0.0f) {
+            const double r = (double)fd.depth[p] - (double)fd.gn_target[p];
+            const double k = fd.huber_k, a = fabs(r);
+            const bool lin = k > 0.0 && a > k;
+            wgt = (double)mw * (lin ? k / a : 1.0);
+            wr = wgt * r;
+            cost = (double)mw * (lin ? k * (a - 0.5 * k) : 0.5 * r * r);
+        }
+    }
+    double *row = gn_part + (size_t)kGnRow * (4 * (size_t)tslot + strip);
+    int cidx = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+#pragma unroll
+        for (int b = a; b < 6; ++b) {
+            double v = wgt * Jd[a] * Jd[b];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) row[cidx] = v;
+            ++cidx;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        double v = wr * Jd[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) row[21 + a] = v;
+    }
+    {
+        double v = cost;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) row[27] = v;
+    }
+    if (lane == 0) row[kGnVals] = (double)tile_frame[tile];
+}
+
 template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
@@ -1361,6 +1508,16 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
+    if (L.bwd_variant == SLR_VARIANT_WAVE) {
+        hipLaunchKernelGGL(k_raster_gn_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+                           reinterpret_cast<const FrameDesc *>(ws + L.desc),
+                           reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
+                           reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
+                           reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
+                           reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
+                           reinterpret_cast<double *>(ws + L.gn_part), L.tiles);
+        return;
+    }
     hipLaunchKernelGGL(k_raster_gn<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),

@@ -43,7 +43,7 @@ k_pose_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ pa
 // and the keyframe index) in a fixed order, written out as H (6x6, both
 // triangles), g (6) and the cost.  Frames without an output pointer are skipped.
 __global__ void __launch_bounds__(128)
-k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts)
+k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts, int strips)
 {
     __shared__ double red[kGnVals][128];
     const int f = blockIdx.x;
@@ -52,11 +52,19 @@ k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part
     double v[kGnVals];
 #pragma unroll
     for (int c = 0; c < kGnVals; ++c) v[c] = 0.0;
+    // one row per tile slot, or (strips = 4) four strip rows per tile slot,
+    // added in strip order first
     for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
-        const double *pp = part + (size_t)kGnRow * b;
+        const double *pp = part + (size_t)kGnRow * strips * b;
         if ((int)pp[kGnVals] != f) continue;
+        if (strips == 1) {
 #pragma unroll
-        for (int c = 0; c < kGnVals; ++c) v[c] += pp[c];
+            for (int c = 0; c < kGnVals; ++c) v[c] += pp[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < kGnVals; ++c)
+                v[c] += ((pp[c] + pp[kGnRow + c]) + pp[2 * kGnRow + c]) + pp[3 * kGnRow + c];
+        }
     }
 #pragma unroll
     for (int c = 0; c < kGnVals; ++c) red[c][threadIdx.x] = v[c];
@@ -162,7 +170,7 @@ void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream)
     if (L.frames == 0) return;
     hipLaunchKernelGGL(k_gn_reduce, dim3((unsigned)L.frames), dim3(128), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.gn_part),
-                       L.tiles);
+                       L.tiles, L.bwd_variant == SLR_VARIANT_WAVE ? 4 : 1);
 }
 
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,

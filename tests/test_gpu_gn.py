@@ -137,6 +137,49 @@ def test_pose_gn_repeatable_and_degenerate(slr):
     assert abs(float(ce.cpu()) - want) <= 1e-6 * want
 
 
+def same_gn(a, b):
+    np.testing.assert_array_equal(b[0], b[0].T)
+    assert np.abs(a[0] - b[0]).max() <= 1e-12 * np.abs(a[0]).max()
+    assert np.abs(a[1] - b[1]).max() <= 1e-12 * np.abs(a[1]).max()
+    assert abs(a[2] - b[2]) <= 1e-12 * abs(a[2])
+
+
+def test_pose_gn_wave_form_matches_workgroup_form(slr):
+    """One wave per strip (backward form 3) and one workgroup per tile
+    (backward form 1) give the same normal equations: each pixel sees the same
+    records in the same order, and a tile's four strip sums are added in the
+    workgroup's order.  The two kernels may contract different multiply-adds
+    (FP32 last-bit differences in a pixel's terms), so the comparison allows
+    1e-12 relative.  The room case at all tile shapes, and the benchmark's map
+    at 128x1024."""
+    from paper_2503_17491_amd import targets
+    sc, sensor, T, target, weight, ref = room_case(0.03)
+    for th, tw in ((16, 16), (32, 8), (8, 32), (4, 64)):
+        say("wave vs workgroup form, room", th, tw)
+        a = gpu_gn(slr, sc, T, sensor, target, weight, 0.03, (th, tw, 3, 2, 1))
+        b = gpu_gn(slr, sc, T, sensor, target, weight, 0.03, (th, tw, 3, 2, 3))
+        same_gn(a[:3], b[:3])
+        assert np.abs(b[0] - ref["H"]).max() <= 2e-3 * np.abs(ref["H"]).max()
+    big, prims = synth.structured_scene(1_000_000, 0)
+    Tb = synth.circle_poses(8, 0)[0]
+    sb = slr.make_sensor(128, 1024)
+    Dt, _ = targets.raycast(prims, sb, Tb, seed=100)
+    m = (Dt > 0).astype(np.float32)
+    out = []
+    for bv in (1, 3):
+        say("wave vs workgroup form, 1M 128x1024, backward form", bv)
+        r = slr.Renderer(sb, (32, 8, 3, 2, bv), 4 << 20)
+        d = to_dev(big)
+        Td = pose_dev(Tb)
+        D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+        Hm, g, c = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D,
+                             torch.from_numpy(Dt).to(DEV), torch.from_numpy(m).to(DEV), 0.05)
+        out.append((Hm.cpu().numpy(), g.cpu().numpy(), float(c.cpu())))
+        del r
+        torch.cuda.empty_cache()
+    same_gn(out[0], out[1])
+
+
 def test_pose_gn_fullsize_properties(slr):
     """The benchmark's map and image size: 1M structured-scene surfels, 128x1024."""
     from paper_2503_17491_amd import targets
