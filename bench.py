@@ -323,11 +323,33 @@ def main():
         tune_ms = br.autotune(reps=5)
         th, tw, var, sch, bvar, box = br.tiling
         log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}": round(v, 3) for c, v in tune_ms.items()})
-    rend = [slr.Renderer(sensor, (th, tw, var, sch, bvar, box), capacity=4 << 20) for _ in kfs]
+    tiling = (th, tw, var, sch, bvar, box)
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plain_tiling = tiling
+    if tune_ms is not None and args.only == "both":
+        # the plain loop renders one keyframe per launch, where the backward's
+        # workgroup barrier weighs more: its backward form is picked by timing
+        # both on the same shape (untimed)
+        best = None
+        for bv in (slr.VARIANT_LDS, slr.VARIANT_WAVE):
+            cand = (th, tw, var, sch, bv, box)
+            rr = [slr.Renderer(sensor, cand, capacity=4 << 20) for _ in kfs]
+            plain_step(torch, slr, d, kfs, rr, grads, dposes, scratch, loss)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                plain_step(torch, slr, d, kfs, rr, grads, dposes, scratch, loss)
+            torch.cuda.synchronize()
+            dt_c = time.perf_counter() - t0
+            if best is None or dt_c < best[0]:
+                best = (dt_c, cand)
+            del rr
+        plain_tiling = best[1]
+        log("plain form tiling:", plain_tiling)
+    rend = [slr.Renderer(sensor, plain_tiling, capacity=4 << 20) for _ in kfs]
 
     plain_iters = None
     if args.only == "both":
@@ -348,6 +370,11 @@ def main():
         torch.cuda.synchronize()
     ef = cf = eb = cb = 0
     census0 = None
+    if plain_tiling != tiling:   # the census of the batched form's tiling
+        del rend
+        rend = [slr.Renderer(sensor, tiling, capacity=4 << 20) for _ in kfs]
+        plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
+        torch.cuda.synchronize()
     for r in rend:  # compositing work census (identical in both forms)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
         ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
@@ -446,7 +473,9 @@ def main():
                    "box": args.box,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
-                   "plain_iter_s": None if plain_iters is None else round(plain_iters, 3), "pairs_per_step": pairs,
+                   "plain_iter_s": None if plain_iters is None else round(plain_iters, 3),
+                   "plain_bwd_variant": {0: "default", 1: "lds", 3: "wave"}[plain_tiling[4]],
+                   "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
         "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn, "photo_gn": photo, "mapping": mapping,
     }
