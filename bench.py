@@ -438,9 +438,13 @@ def main():
     achieved = flops / (ms * 1e-3) / 1e12
     vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
     tiling_name = f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}"
+    traffic = counted_traffic(dom, tiling_name)
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": counted_traffic(dom, tiling_name),
+            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": traffic,
             "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
+    if traffic is not None:   # the same launch against the HBM roofline (8 TB/s)
+        roof["hbm_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+        roof["hbm_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
     if args.form == "plain" and plain_iters is None:
         raise SystemExit("--form plain needs --only both")
