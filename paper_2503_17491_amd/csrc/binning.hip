@@ -374,7 +374,7 @@ k_vis_write(const uint32_t *__restrict__ keys, const int32_t *__restrict__ cnt, 
 // record has at least one pair, so a block sees at most S + 1 records.  A
 // slot's record is the last one whose offset is <= the slot; within a record
 // the slots go row by row, and in a row the first column interval, then the
-// second.  Consecutive threads write consecutive slots.
+// second.  Consecutive threads write consecutive pairs of slots.
 __global__ void __launch_bounds__(kEmitThreads)
 k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
        const PixBox *__restrict__ rbox, const uint32_t *__restrict__ estart, const uint64_t *__restrict__ n_dev,
@@ -413,18 +413,33 @@ k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, 
         s_row0[i] = (uint32_t)fd.tile_off;
     }
     __syncthreads();
-    for (uint64_t q = q0 + threadIdx.x; q < qend; q += kEmitThreads) {
-        const uint32_t qq = (uint32_t)q;
-        int lo = 0;
+    // two consecutive slots per thread: a search for the first, and the second
+    // is in the same record or the next one
+    static_assert(kEmitSlots == 2 * kEmitThreads, "two slots per thread");
+    const uint64_t q = q0 + 2 * (uint64_t)threadIdx.x;
+    if (q >= qend) return;
+    const uint32_t qq = (uint32_t)q;
+    int lo = 0;
 #pragma unroll
-        for (int step = kEmitSlots; step > 0; step >>= 1)
-            if (lo + step < nrec && s_off[lo + step] <= qq) lo += step;
-        const int j = (int)(qq - s_off[lo]);
+    for (int step = kEmitSlots; step > 0; step >>= 1)
+        if (lo + step < nrec && s_off[lo + step] <= qq) lo += step;
+    uint32_t tile[2], val[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1 && lo + 1 < nrec && s_off[lo + 1] <= qq + 1) ++lo;
+        const int j = (int)(qq + h - s_off[lo]);
         const int len = s_len[lo], na = s_na[lo];
         const int dy = j / len, cc = j - dy * len;
         const int tx = cc < na ? s_ax0[lo] + cc : s_bx0[lo] + (cc - na);
-        ptile[q] = s_row0[lo] + (uint32_t)((s_ty0[lo] + dy) * s_tx[lo] + tx);
-        pval[q] = s_id[lo];
+        tile[h] = s_row0[lo] + (uint32_t)((s_ty0[lo] + dy) * s_tx[lo] + tx);
+        val[h] = s_id[lo];
+    }
+    if (q + 1 < qend) {   // q is even: an aligned pair of slots
+        *reinterpret_cast<uint2 *>(ptile + q) = make_uint2(tile[0], tile[1]);
+        *reinterpret_cast<uint2 *>(pval + q) = make_uint2(val[0], val[1]);
+    } else {
+        ptile[q] = tile[0];
+        pval[q] = val[0];
     }
 }
 
