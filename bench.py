@@ -284,6 +284,8 @@ def main():
                     help="bounding box: exact 3-sigma square, opacity-aware square (same images, fewer pairs), "
                          "or the relaxed vertex-only box (can miss pixels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--bwd-batch", type=int, choices=[0, 128, 192], default=0,
+                    help="records per LDS batch of the workgroup backward (0: library default)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -302,6 +304,7 @@ def main():
     th = tw = None
     bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
     box = {"exact": slr.BOX_EXACT, "opacity": slr.BOX_OPACITY, "vertex": slr.BOX_VERTEX}[args.box]
+    bbatch = args.bwd_batch
     if args.tile != "auto":
         th, tw = (int(x) for x in args.tile.split("x"))
     if args.copy_calib:
@@ -321,9 +324,11 @@ def main():
             for t in u:
                 t.fill_(1.0)
         tune_ms = br.autotune(reps=5)
-        th, tw, var, sch, bvar, box = br.tiling
-        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}": round(v, 3) for c, v in tune_ms.items()})
-    tiling = (th, tw, var, sch, bvar, box)
+        th, tw, var, sch, bvar, box = br.tiling[:6]
+        bbatch = br.tiling[6] if len(br.tiling) > 6 else 0
+        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}" + (f"/{c[6]}" if len(c) > 6 else ""):
+                                             round(v, 3) for c, v in tune_ms.items()})
+    tiling = (th, tw, var, sch, bvar, box, bbatch)
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
     scratch = (torch.empty(H, W, device="cuda"), torch.empty(H, W, 3, device="cuda"))
@@ -335,7 +340,7 @@ def main():
         # both on the same shape (untimed)
         best = None
         for bv in (slr.VARIANT_LDS, slr.VARIANT_WAVE):
-            cand = (th, tw, var, sch, bv, box)
+            cand = (th, tw, var, sch, bv, box, bbatch)
             rr = [slr.Renderer(sensor, cand, capacity=4 << 20) for _ in kfs]
             plain_step(torch, slr, d, kfs, rr, grads, dposes, scratch, loss)
             torch.cuda.synchronize()
@@ -385,7 +390,7 @@ def main():
 
     # ---- batched form: all keyframes per launch, no host sync, one graph launch per iteration
     if br is None:
-        br = make_batch(torch, slr, d, sensor, kfs, (th, tw, var, sch, bvar, box))
+        br = make_batch(torch, slr, d, sensor, kfs, tiling)
     batched_step(slr, br, kfs, loss)
     if br.ensure_capacity():
         batched_step(slr, br, kfs, loss)
@@ -437,7 +442,8 @@ def main():
         dom, flops, ms = "raster_fwd", fwd_flops, fwd_ms
     achieved = flops / (ms * 1e-3) / 1e12
     vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
-    tiling_name = f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}"
+    tiling_name = f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}" + (
+        f" batch {bbatch}" if bvar == slr.VARIANT_LDS and bbatch not in (0, 192) else "")
     traffic = counted_traffic(dom, tiling_name)
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": traffic,
@@ -453,7 +459,7 @@ def main():
 
     gn = photo = mapping = None
     if not args.no_gn:
-        gn = measure_gn(torch, slr, d, sensor, kfs[0], (th, tw, var, sch, bvar, box), args.steps, census0)
+        gn = measure_gn(torch, slr, d, sensor, kfs[0], tiling, args.steps, census0)
         log("pose-only Gauss-Newton:", gn)
         photo = measure_photo(torch, slr, sensor, kfs[0], br.out[0][0], args.steps)
         log("photometric registration:", photo)
@@ -473,7 +479,8 @@ def main():
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
                    "schedule": {0: "default", 1: "tile", 2: "longest"}[sch],
-                   "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar], "autotuned": tune_ms is not None,
+                   "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar],
+                   "bwd_batch": bbatch if bbatch else 192, "autotuned": tune_ms is not None,
                    "box": args.box,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),

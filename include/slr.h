@@ -85,13 +85,17 @@ typedef struct slr_sensor {
  * integer with 255 o exp(-(k/16)^2 / 2) <= 0.999; surfels with 255 o <= 0.999
  * are culled) -- fewer pairs, identical images; 2 = the paper's relaxed box,
  * the angular extent of the square's four vertices only, which can miss
- * pixels (for comparison). */
+ * pixels (for comparison).  bwd_batch is the number of surfel records the
+ * workgroup backward (bwd_variant 1) stages in LDS per batch: 0 = library
+ * default (192), or 128 or 192; results do not depend on it beyond the
+ * order of the gradient atomics. */
 typedef struct slr_tiling {
     int32_t tile_h, tile_w;
     int32_t variant;
     int32_t schedule;
     int32_t bwd_variant;
     int32_t box;
+    int32_t bwd_batch;
 } slr_tiling;
 #define SLR_BOX_EXACT 0
 #define SLR_BOX_OPACITY 1

@@ -84,6 +84,8 @@ slr_status check_tiling(const slr_tiling *t)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
     if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
+    if (t->bwd_batch != 0 && t->bwd_batch != 128 && t->bwd_batch != 192)
+        return fail(SLR_E_INVALID, "unsupported backward batch %d (0, 128 or 192)", t->bwd_batch);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
     if (t->box < SLR_BOX_EXACT || t->box > SLR_BOX_VERTEX) return fail(SLR_E_INVALID, "unknown box mode %d", t->box);
@@ -209,6 +211,7 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
     // the backward form: as asked, else the forward's (the scalar-cache forward pairs with the workgroup backward)
     b->L.bwd_variant = tiling->bwd_variant != SLR_VARIANT_DEFAULT ? tiling->bwd_variant
                        : (b->L.variant == SLR_VARIANT_WAVE ? SLR_VARIANT_WAVE : SLR_VARIANT_LDS);
+    b->L.bwd_batch = tiling->bwd_batch != 0 ? tiling->bwd_batch : 192;
     b->L.schedule = tiling->schedule == SLR_SCHEDULE_DEFAULT ? slr::kDefaultSchedule : tiling->schedule;
     b->L.box_mode = tiling->box;
     if (b->L.tiles >= (int64_t(1) << 24)) return fail(SLR_E_INVALID, "batch has too many tiles");

@@ -600,7 +600,7 @@ k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     }
 }
 
-constexpr int kBwdBatch = 192;   // records staged per backward batch (fits 4 workgroups per CU)
+constexpr int kBwdBatch = 192;   // default records staged per backward batch (fits 4 workgroups per CU)
 constexpr int kNg = 18;
 
 __device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
@@ -774,7 +774,7 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
 }
 
 
-template <int TW>
+template <int TW, int BATCH>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -785,11 +785,11 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              double *__restrict__ pose_part, int pose_only)
 {
     constexpr int TH = 256 / TW;
-    __shared__ RasterRec srec[kBwdBatch];
-    __shared__ ChatRec schat[kBwdBatch];
-    __shared__ float sred[kNg][kBwdBatch];   // wave sums of the four waves, added in LDS
-    __shared__ int sflag[kBwdBatch];
-    __shared__ uint8_t slist[4][kBwdBatch];
+    __shared__ RasterRec srec[BATCH];
+    __shared__ ChatRec schat[BATCH];
+    __shared__ float sred[kNg][BATCH];   // wave sums of the four waves, added in LDS
+    __shared__ int sflag[BATCH];
+    __shared__ uint8_t slist[4][BATCH];
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
 
@@ -825,8 +825,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
     const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
     if (threadIdx.x == 0) s_last = 0;
-    for (int e = threadIdx.x; e < kNg * kBwdBatch; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
-    for (int e = threadIdx.x; e < kBwdBatch; e += blockDim.x) sflag[e] = 0;
+    for (int e = threadIdx.x; e < kNg * BATCH; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
+    for (int e = threadIdx.x; e < BATCH; e += blockDim.x) sflag[e] = 0;
     __syncthreads();
     if (last > 0) atomicMax(&s_last, last);
     __syncthreads();
@@ -844,8 +844,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const BwdUpstream up = {gd, go, gn0, gn1, gn2, Tfin};
     int n_eval = 0, n_con = 0;
 
-    for (int b_end = end; b_end > rg.x; b_end -= kBwdBatch) {
-        const int b0 = max(rg.x, b_end - kBwdBatch);
+    for (int b_end = end; b_end > rg.x; b_end -= BATCH) {
+        const int b0 = max(rg.x, b_end - BATCH);
         const int cnt = b_end - b0;
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
@@ -1494,7 +1494,8 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                            reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles);
         return;
     }
-    hipLaunchKernelGGL(k_raster_bwd<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+    auto kern = L.bwd_batch == 128 ? k_raster_bwd<TW, 128> : k_raster_bwd<TW, kBwdBatch>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),

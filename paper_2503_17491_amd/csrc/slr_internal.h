@@ -99,7 +99,7 @@ constexpr double kBoxMargin = 2e-5;
 
 // Workspace layout of a batch (offsets in bytes from the workspace base).
 struct Layout {
-    int32_t frames, sets, th, tw, variant, schedule, bwd_variant, box_mode;
+    int32_t frames, sets, th, tw, variant, schedule, bwd_variant, box_mode, bwd_batch;
     int64_t items, cap, tiles, pixels, acc_floats, tab_entries;
     int tile_bits, depth_passes, tile_passes;
     bool depth_in_1, tile_in_1;

@@ -28,7 +28,7 @@ class Sensor(C.Structure):
 
 class Tiling(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("tile_w", C.c_int32), ("variant", C.c_int32), ("schedule", C.c_int32),
-                ("bwd_variant", C.c_int32), ("box", C.c_int32)]
+                ("bwd_variant", C.c_int32), ("box", C.c_int32), ("bwd_batch", C.c_int32)]
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
@@ -293,10 +293,13 @@ class Renderer:
 
 
 # Candidate tilings of the autotuner: (tile_h, tile_w, forward variant,
-# schedule, backward variant).
+# schedule, backward variant[, backward batch]); the renderer's box mode is
+# inserted as the sixth entry.
 BOX_EXACT, BOX_OPACITY, BOX_VERTEX = 0, 1, 2
 TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((16, 16), (8, 32), (32, 8))
-                   for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS)]
+                   for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS),
+                                                             (32, 8, VARIANT_WAVE, SCHEDULE_LONGEST, VARIANT_LDS, 128),
+                                                             (16, 16, VARIANT_WAVE, SCHEDULE_LONGEST, VARIANT_LDS, 128)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
 
 
@@ -356,7 +359,7 @@ class BatchRenderer:
         cands = []
         for c in (candidates or TUNE_CANDIDATES):
             c = tuple(c) + (0,) * max(0, 5 - len(c))
-            cands.append(c if len(c) > 5 else c + (box,))
+            cands.append(c[:5] + (box,) + c[5:])
         arr = (Tiling * len(cands))(*[Tiling(*c) for c in cands])
         need = 0
         for c in cands:

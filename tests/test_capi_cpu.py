@@ -47,6 +47,12 @@ def test_workspace_size_and_validation():
     bad = dict(s, fu=-s["fu"])
     with pytest.raises(slr.SlrError):
         slr.workspace_size(bad, (16, 16), 10, 10)
+    # the workgroup backward stages 128 or 192 records per batch (0: default)
+    for batch in (0, 128, 192):
+        assert slr.workspace_size(s, (32, 8, 3, 2, 1, 0, batch), 10, 10) > 0
+    with pytest.raises(slr.SlrError) as e:
+        slr.workspace_size(s, (32, 8, 3, 2, 1, 0, 100), 10, 10)
+    assert e.value.status == slr.SLR_E_INVALID and "batch" in str(e.value)
     pole = slr.make_sensor(64, 512, el=(math.radians(-89.5), math.radians(10)))
     with pytest.raises(slr.SlrError) as e:
         slr.workspace_size(pole, (16, 16), 10, 10)

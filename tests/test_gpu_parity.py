@@ -274,6 +274,32 @@ def test_backward_parity_fullsize_sparse(slr):
                    1 << 20)
 
 
+def test_backward_batch_sizes_agree(slr):
+    """The workgroup backward stages 128 or 192 records per LDS batch
+    (slr_tiling.bwd_batch): the same pairs in the same per-pixel order, so the
+    gradients agree up to the order of the float atomics and the per-tile
+    pose partials; the forward is untouched."""
+    sc, _ = synth.structured_scene(20000, 5)
+    sensor = slr.make_sensor(64, 512)
+    T = synth.circle_poses(8, 1)[2]
+    g = np.random.default_rng(19)
+    GD = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
+    GN = torch.from_numpy(g.normal(size=(64, 512, 3)).astype(np.float32)).to(DEV)
+    GO = torch.from_numpy(g.normal(size=(64, 512)).astype(np.float32)).to(DEV)
+    outs = []
+    for batch in (192, 128):
+        say("backward batch", batch)
+        r, d, Td, D, N, A = gpu_render(slr, sc, T, sensor, (32, 8, 3, 2, 1, 0, batch), 1 << 20)
+        gr, dp = r.backward(d["means"], d["quats"], d["log_scales"], d["logits"], Td, GD, GN, GO)
+        torch.cuda.synchronize()
+        outs.append((D, [gr[k].cpu().numpy().copy() for k in ("means", "quats", "log_scales", "logits")],
+                     dp.cpu().numpy().copy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(a).max()))
+    np.testing.assert_allclose(outs[0][2], outs[1][2], rtol=1e-6, atol=1e-9 * float(np.abs(outs[0][2]).max()))
+
+
 def test_backward_repeatable(slr):
     """The pose gradient is reduced from per-workgroup partials in a fixed
     order: with the one-wave form (whose record sums are deterministic) two
