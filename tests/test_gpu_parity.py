@@ -85,7 +85,21 @@ def assert_forward_close(D, N, A, ref, pix=None, max_flagged=0.01):
 
 
 # ---------------------------------------------------------------- binning
+def giant_scene():
+    """A shell scene plus a few surfels far larger than the sensor's
+    surroundings: a horizontal one above the sensor (pierced by the z-axis:
+    full azimuth, every row up to the top), one below, and a vertical wall,
+    so single records span more pair slots than one emit block holds."""
+    sc = synth.shell_scene(3000, 12)
+    sc["means"][:3] = np.array([[0.4, 0.3, 3.0], [-0.2, 0.5, -2.5], [6.0, 0.5, 0.2]], np.float32)
+    sc["quats"][:3] = np.array([[1, 0, 0, 0], [1, 0, 0, 0], [0.7071068, 0, 0.7071068, 0]], np.float32)
+    sc["log_scales"][:3] = np.log(np.array([[30.0, 25.0], [20.0, 30.0], [15.0, 12.0]], np.float32))
+    sc["logits"][:3] = 2.0
+    return sc
+
+
 BIN_CASES = [
+    ("giant-surfels-128x2048-8x32", giant_scene, lambda: np.eye(4), (128, 2048), (8, 32)),
     ("shell-2k-64x512", lambda: synth.shell_scene(2000, 1), lambda: np.eye(4), (64, 512), (16, 16)),
     ("shell-2k-64x512-8x32", lambda: synth.shell_scene(2000, 1), lambda: np.eye(4), (64, 512), (8, 32)),
     ("shell-5k-posed-4x64", lambda: synth.shell_scene(5000, 4), lambda: synth.perturbed_pose(4, 1.0, 30.0),
