@@ -58,7 +58,8 @@ typedef int32_t slr_status;
 
 /* Spherical sensor: image size and the camera matrix K of Supp. A. */
 typedef struct slr_sensor {
-    int32_t height, width; /* rows (elevation), columns (azimuth) */
+    int32_t height, width; /* rows (elevation), columns (azimuth); each in [1, 32767]
+                              and 3 * height * width < 2^31 */
     double fu, cu, fv, cv; /* u = fu*az + cu, v = fv*el + cv; fu, fv must be < 0 */
     double near_m;         /* pairs with ray range t <= near_m are rejected, and
                               surfels whose centre range <= near_m are culled */
@@ -230,8 +231,11 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
                                slr_views *views);
 
 /* ------------------------------------------------------------------------
- * Batched form: many frames (keyframes, each with its own pose, sensor and
- * image size) rendered by one set of launches with no host synchronisation,
+ * Batched form (Sec. 3.3.2: the local model is refined over keyframes sampled
+ * from its keyframe set; this form renders and differentiates the keyframes
+ * of one refinement iteration together): many frames (keyframes, each with
+ * its own pose, sensor and image size) rendered by one set of launches with
+ * no host synchronisation,
  * so that a whole optimisation iteration can be captured in a HIP graph and
  * replayed.  Frames reference surfel sets; several frames may share one set
  * (one map seen from several keyframes), in which case the set's gradients
@@ -265,12 +269,14 @@ slr_status slr_batch_workspace_size(int32_t n_sets, const slr_surfels *sets, int
 slr_status slr_batch_prepare(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
                              const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                              size_t workspace_bytes, void *stream);
-/* Forward of every frame: projection, one range sort and one tile sort for
- * the batch, one compositing launch over all tiles of all frames. */
+/* Forward of every frame (Sec. 3.2.1-3.2.3 and Supp. D forward process, as
+ * slr_render): projection, one range sort and one tile sort for the batch,
+ * one compositing launch over all tiles of all frames. */
 slr_status slr_batch_render(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
                             const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                             size_t workspace_bytes, void *stream);
-/* Backward of every frame.  grads: host array of n_sets entries (device
+/* Backward of every frame (Supp. D gradient computation and the se(3) pose
+ * gradient of Sec. 3.3.3, as slr_backward).  grads: host array of n_sets entries (device
  * pointers; an entry of all-NULL pointers skips that set), or NULL with
  * SLR_POSE_ONLY.  Frame pose gradients go to frames[f].d_pose when set.
  * With SLR_ACCUMULATE the set gradients are added to the outputs. */
@@ -278,7 +284,8 @@ slr_status slr_batch_backward(int32_t n_sets, const slr_surfels *sets, const slr
                               int32_t n_frames, const slr_frame *frames, const slr_tiling *tiling,
                               int64_t pair_capacity, void *workspace, size_t workspace_bytes, uint32_t flags,
                               void *stream);
-/* Tile autotuner (the tile shape, compositing form and schedule of a batch):
+/* Tile autotuner (Sec. 3.2.1 splits the image into 16x16 tiles; here the
+ * tile shape, compositing form and schedule of a batch are chosen by timing):
  * for each of the n_candidates tilings, renders and back-propagates the batch
  * once untimed and reps times timed (HIP events on stream; the call
  * synchronises), and writes the median ms per candidate to ms (host,
@@ -294,13 +301,28 @@ slr_status slr_batch_autotune(int32_t n_sets, const slr_surfels *sets, const slr
                               int32_t n_candidates, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
                               int32_t reps, double *ms, int32_t *best, void *stream);
 
-/* Device address of four uint64 words in the workspace: the pair count K
+/* Device address of four uint64 words in the workspace (the per-tile lists
+ * of Sec. 3.2.1): the pair count K
  * of the last render, the overflow word (K when K > pair_capacity, else 0),
  * the pair count actually binned and the number of surfel records that bin
  * into at least one tile. */
 slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
                               const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                               size_t workspace_bytes, const uint64_t **counters);
+
+/* Device views into a batch workspace after slr_batch_render, for inspection
+ * and tests.  Indices are global to the batch: record r of frame f is
+ * item_off(f) + surfel index, where item_off(f) sums the surfel counts of the
+ * sets of frames 0..f-1; tile t of frame f is tile_off(f) + ty*tiles_x + tx
+ * (tile_off(f) sums the tile counts of frames 0..f-1); pixel (i, j) of frame f
+ * is pix_off(f) + i*W + j (pix_off sums H*W of frames 0..f-1).  keys, counts
+ * and pixbox are per record; sorted_tile / sorted_id hold (global tile,
+ * record) of the K pairs; ranges is per global tile; T_final, n_proc and
+ * census are per global pixel (census rows are the total pixel count apart).
+ * tiles_x holds the batch's total tile count and tiles_y is 1. */
+slr_status slr_batch_views(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                           const slr_tiling *tiling, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                           slr_views *views);
 
 /* Adam over the raw surfel parameters (the map refinement of Sec. 3.3.2
  * optimises them with Adam), PyTorch's single-tensor form:

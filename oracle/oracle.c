@@ -20,6 +20,10 @@
  *                        formulas read as the exact chain rule, the opacity
  *                        channel added, and the se(3) pose gradient for the
  *                        update T <- T exp(delta) of Sec. 3.3.3.
+ *   *_mode(cull = 1)     the same render / backward with an angular cull that
+ *                        skips only pairs whose support test must fail (the
+ *                        ray's line misses the bounding sphere of the 3-sigma
+ *                        square); pinned identical to brute force.
  *   or_bin               Sec. 3.2.1 (16x16 tiles, per-tile lists sorted by
  *                        range) and Sec. 3.2.3 / Supp. B (3-sigma splat box,
  *                        centre-relative azimuth extent, seam propagation),
@@ -237,18 +241,158 @@ static void list_push(pair_list *L, const or_pair *p)
     L->p[L->n++] = *p;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Angular-cull mode: the same lists as brute force, found faster.           */
+/*                                                                          */
+/* A pair passes the support test only if the ray meets the splat square     */
+/* {b_c + a b_alpha + b b_beta : |a|, |b| <= 3} (Sec. 3.2.3), whose points lie */
+/* within r = 3 sqrt(s_alpha^2 + s_beta^2) of b_c (b_alpha, b_beta are       */
+/* orthogonal).  The support test meets the plane along the whole line of   */
+/* the ray (in front of or behind the sensor), so the line's direction +-v    */
+/* lies in the cone of half-angle asin(r / |b_c|) around b_c when |b_c| > r: */
+/* the test |v . c_hat| >= sqrt(1 - (r/|b_c|)^2) can only drop pairs whose   */
+/* support test fails.                                                       */
+/* r is taken 0.1 % larger (plus 1e-9 m) so that no pair near the support    */
+/* threshold, which the guard band reports, is dropped either.  Directions    */
+/* are bucketed in 2-degree azimuth x elevation bins: a surfel goes into every */
+/* bin its cone's elevation interval [el_c - th, el_c + th] and azimuth      */
+/* interval [az_c - asin(sin th / cos el_c), az_c + ...] (the extent of a     */
+/* spherical cap) overlap, both widened by 1e-6 rad for rounding; caps that  */
+/* reach a pole span every azimuth.  Angular distance bounds the elevation    */
+/* difference, so the bin of a ray holds every surfel whose cone holds it;   */
+/* a surfel also goes into the mirrored bins of the antipodal cone (the bin  */
+/* grid is symmetric under v -> -v: elevation bin e -> NEL-1-e, azimuth bin  */
+/* a -> a + NAZ/2), each bin at most once.                                   */
+/* ------------------------------------------------------------------------ */
+#define CULL_NAZ 180
+#define CULL_NEL 90
+#define CULL_MARGIN 1e-6
+typedef struct cull_index {
+    int64_t *start;   /* [CULL_NAZ * CULL_NEL + 1] */
+    int32_t *ids;
+    double *cone;     /* [n, 4]: c_hat, cosine limit (-2: no cull) */
+} cull_index;
+
+static int64_t cull_bin(const cull_index *cx, const double *v)
+{
+    (void)cx;
+    const double PI = 3.14159265358979323846;
+    double az = atan2(v[1], v[0]), el = atan2(v[2], hypot(v[0], v[1]));
+    int ia = (int)floor((az + PI) / (2.0 * PI / CULL_NAZ));
+    int ie = (int)floor((el + 0.5 * PI) / (PI / CULL_NEL));
+    ia = ia < 0 ? 0 : (ia >= CULL_NAZ ? CULL_NAZ - 1 : ia);
+    ie = ie < 0 ? 0 : (ie >= CULL_NEL ? CULL_NEL - 1 : ie);
+    return (int64_t)ie * CULL_NAZ + ia;
+}
+
+/* Bin ranges of one surfel's cone: elevation bins [*e0, *e1], azimuth bins
+ * [*a0, *a1] taken modulo CULL_NAZ (*a1 - *a0 + 1 >= CULL_NAZ: all). */
+static void cull_ranges(const double *c, double sin_th, int *e0, int *e1, int *a0, int *a1)
+{
+    const double PI = 3.14159265358979323846;
+    const double del = PI / CULL_NEL, daz = 2.0 * PI / CULL_NAZ;
+    double th = asin(sin_th);
+    double el_c = atan2(c[2], hypot(c[0], c[1])), az_c = atan2(c[1], c[0]);
+    double lo = el_c - th - CULL_MARGIN, hi = el_c + th + CULL_MARGIN;
+    *e0 = (int)floor((lo + 0.5 * PI) / del);
+    *e1 = (int)floor((hi + 0.5 * PI) / del);
+    if (*e0 < 0) *e0 = 0;
+    if (*e1 >= CULL_NEL) *e1 = CULL_NEL - 1;
+    if (lo <= -0.5 * PI || hi >= 0.5 * PI || !(cos(el_c) > sin_th)) { *a0 = 0; *a1 = CULL_NAZ - 1; return; }
+    double r = sin_th / cos(el_c);
+    double dz = (r >= 1.0 ? 0.5 * PI : asin(r)) * (1.0 + 1e-9) + CULL_MARGIN;
+    *a0 = (int)floor((az_c - dz + PI) / daz);
+    *a1 = (int)floor((az_c + dz + PI) / daz);
+    if (*a1 - *a0 + 1 >= CULL_NAZ) { *a0 = 0; *a1 = CULL_NAZ - 1; }
+}
+
+static void cull_build(const or_frame *F, int64_t n, cull_index *cx)
+{
+    const int64_t NB = (int64_t)CULL_NAZ * CULL_NEL;
+    cx->start = (int64_t *)calloc((size_t)NB + 1, sizeof(int64_t));
+    cx->cone = (double *)malloc((size_t)(n > 0 ? n : 1) * 4 * sizeof(double));
+    double *sth = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t k = 0; k < n; ++k) {
+        double *c = cx->cone + 4 * k;
+        c[0] = c[1] = c[2] = 0.0; c[3] = -2.0; sth[k] = -1.0;
+        if (!F[k].valid) continue;
+        const double *b = F[k].bc;
+        double d = sqrt(dot3(b, b));
+        double r = 3.0 * sqrt(F[k].s[0] * F[k].s[0] + F[k].s[1] * F[k].s[1]) * 1.001 + 1e-9;
+        for (int q = 0; q < 3; ++q) c[q] = b[q] / d;
+        if (d > r) {
+            sth[k] = r / d;
+            c[3] = sqrt(1.0 - sth[k] * sth[k]) - 1e-12;
+        } else {
+            sth[k] = 2.0;   /* the sensor lies inside the ball: every direction */
+        }
+    }
+    /* two passes: count the bins of every surfel, then fill */
+    unsigned char *mark = (unsigned char *)calloc((size_t)NB, 1);
+    int64_t *touched = (int64_t *)malloc((size_t)NB * sizeof(int64_t));
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t *fill = NULL;
+        if (pass == 1) {
+            for (int64_t b = 0; b < NB; ++b) cx->start[b + 1] += cx->start[b];
+            cx->ids = (int32_t *)malloc((size_t)(cx->start[NB] > 0 ? cx->start[NB] : 1) * sizeof(int32_t));
+            fill = (int64_t *)malloc((size_t)NB * sizeof(int64_t));
+            memcpy(fill, cx->start, (size_t)NB * sizeof(int64_t));
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            if (!(sth[k] >= 0.0)) continue;
+            int e0, e1, a0, a1;
+            if (sth[k] >= 1.0) { e0 = 0; e1 = CULL_NEL - 1; a0 = 0; a1 = CULL_NAZ - 1; }
+            else cull_ranges(cx->cone + 4 * k, sth[k], &e0, &e1, &a0, &a1);
+            int64_t nt = 0;
+            for (int mirror = 0; mirror < 2; ++mirror)
+                for (int e = e0; e <= e1; ++e)
+                    for (int a = a0; a <= a1; ++a) {
+                        int ee = mirror ? CULL_NEL - 1 - e : e;
+                        int aa = (((a + (mirror ? CULL_NAZ / 2 : 0)) % CULL_NAZ) + CULL_NAZ) % CULL_NAZ;
+                        int64_t b = (int64_t)ee * CULL_NAZ + aa;
+                        if (mark[b]) continue;
+                        mark[b] = 1;
+                        touched[nt++] = b;
+                        if (pass == 0) cx->start[b + 1] += 1;
+                        else cx->ids[fill[b]++] = (int32_t)k;
+                    }
+            for (int64_t t = 0; t < nt; ++t) mark[touched[t]] = 0;
+        }
+        free(fill);
+    }
+    free(mark);
+    free(touched);
+    free(sth);
+}
+
+static void cull_free(cull_index *cx) { free(cx->start); free(cx->ids); free(cx->cone); }
+
 /* Gather and sort the contributors of one pixel ray; returns the number of
  * pairs kept after the front-to-back stop rule (T_before * (1 - alpha) < 1e-4
  * ends the list before that pair). */
 static int64_t pixel_list(const or_frame *F, int64_t n, const double *v, const double *hx,
                           const double *hy, double near_m, const double *guard, pair_list *L,
-                          int *flags)
+                          int *flags, const struct cull_index *cx)
 {
     L->n = 0;
-    for (int64_t k = 0; k < n; ++k) {
-        if (!F[k].valid) continue;
-        or_pair p;
-        if (pair_eval(&F[k], v, hx, hy, near_m, guard, &p, flags)) { p.id = (int32_t)k; list_push(L, &p); }
+    if (cx) {
+        /* angular-cull mode: only the surfels of the pixel's direction bin whose
+         * bounding cone holds the ray (a superset of the pairs that can pass the
+         * support test, so the list below is the brute-force list) */
+        int64_t b = cull_bin(cx, v), e = cx->start[b + 1];
+        for (int64_t q = cx->start[b]; q < e; ++q) {
+            int32_t k = cx->ids[q];
+            const double *c = cx->cone + 4 * (int64_t)k;
+            if (fabs(v[0] * c[0] + v[1] * c[1] + v[2] * c[2]) < c[3]) continue;
+            or_pair p;
+            if (pair_eval(&F[k], v, hx, hy, near_m, guard, &p, flags)) { p.id = k; list_push(L, &p); }
+        }
+    } else {
+        for (int64_t k = 0; k < n; ++k) {
+            if (!F[k].valid) continue;
+            or_pair p;
+            if (pair_eval(&F[k], v, hx, hy, near_m, guard, &p, flags)) { p.id = (int32_t)k; list_push(L, &p); }
+        }
     }
     qsort(L->p, (size_t)L->n, sizeof(or_pair), pair_cmp);
     for (int64_t c = 1; c < L->n; ++c)
@@ -279,14 +423,17 @@ static or_frame *build_frames(int64_t n, const double *means, const double *quat
 /* guard (nullable): widths of the guard bands {support, near [m],          */
 /* alpha (relative), T-stop (relative)}.                                     */
 /* ------------------------------------------------------------------------ */
-int or_render_pixels(int64_t n, const double *means, const double *quats, const double *log_scales,
-                     const double *logits, const double *pose, const or_sensor *s,
-                     int64_t P, const int32_t *pix, const double *guard,
-                     double *depth, double *normal, double *alpha, double *T_final,
-                     int32_t *n_contrib, int32_t *flags)
+/* cull = 1: the angular-cull mode (identical results, fewer pairs tested). */
+int or_render_pixels_mode(int64_t n, const double *means, const double *quats, const double *log_scales,
+                          const double *logits, const double *pose, const or_sensor *s,
+                          int64_t P, const int32_t *pix, const double *guard,
+                          double *depth, double *normal, double *alpha, double *T_final,
+                          int32_t *n_contrib, int32_t *flags, int32_t cull)
 {
     if (n < 0 || P < 0 || !s) return -1;
     or_frame *F = build_frames(n, means, quats, log_scales, logits, pose, s->near_m);
+    cull_index cxs, *cx = NULL;
+    if (cull) { cull_build(F, n, &cxs); cx = &cxs; }
     #pragma omp parallel
     {
         pair_list L = {0, 0, 0};
@@ -295,7 +442,7 @@ int or_render_pixels(int64_t n, const double *means, const double *quats, const 
             double v[3], hx[3], hy[3];
             or_pixel_basis(s, pix[2 * q], pix[2 * q + 1], v, hx, hy);
             int fl = 0;
-            int64_t m = pixel_list(F, n, v, hx, hy, s->near_m, guard, &L, &fl);
+            int64_t m = pixel_list(F, n, v, hx, hy, s->near_m, guard, &L, &fl, cx);
             double T = 1.0, D = 0.0, N[3] = {0, 0, 0}, O = 0.0;
             for (int64_t c = 0; c < m; ++c) {
                 const or_pair *p = &L.p[c];
@@ -313,8 +460,19 @@ int or_render_pixels(int64_t n, const double *means, const double *quats, const 
         }
         free(L.p);
     }
+    if (cx) cull_free(cx);
     free(F);
     return 0;
+}
+
+int or_render_pixels(int64_t n, const double *means, const double *quats, const double *log_scales,
+                     const double *logits, const double *pose, const or_sensor *s,
+                     int64_t P, const int32_t *pix, const double *guard,
+                     double *depth, double *normal, double *alpha, double *T_final,
+                     int32_t *n_contrib, int32_t *flags)
+{
+    return or_render_pixels_mode(n, means, quats, log_scales, logits, pose, s, P, pix, guard, depth, normal,
+                                 alpha, T_final, n_contrib, flags, 0);
 }
 
 /* Supp. D, last block: gradients w.r.t. the raw parameters of one surfel from
@@ -367,15 +525,17 @@ static void raw_from_frame(const or_frame *f, const double *Rc, const double *g,
 /* per surfel the sum over pixels of |per-pixel contribution| to each raw    */
 /* parameter gradient: the scale an FP32 accumulation error is measured by.  */
 /* ------------------------------------------------------------------------ */
-int or_backward_pixels(int64_t n, const double *means, const double *quats, const double *log_scales,
-                       const double *logits, const double *pose, const or_sensor *s,
-                       int64_t P, const int32_t *pix,
-                       const double *dL_dD, const double *dL_dN, const double *dL_dO,
-                       double *g_means, double *g_quats, double *g_log_scales, double *g_logits,
-                       double *g_pose, double *g_abs)
+int or_backward_pixels_mode(int64_t n, const double *means, const double *quats, const double *log_scales,
+                            const double *logits, const double *pose, const or_sensor *s,
+                            int64_t P, const int32_t *pix,
+                            const double *dL_dD, const double *dL_dN, const double *dL_dO,
+                            double *g_means, double *g_quats, double *g_log_scales, double *g_logits,
+                            double *g_pose, double *g_abs, int32_t cull)
 {
     if (n < 0 || P < 0 || !s) return -1;
     or_frame *F = build_frames(n, means, quats, log_scales, logits, pose, s->near_m);
+    cull_index cxs, *cx = NULL;
+    if (cull) { cull_build(F, n, &cxs); cx = &cxs; }
     /* per-surfel sensor-frame accumulators: g_alpha, g_beta, g_c, g_n (3 each), g_o */
     double *acc = (double *)calloc((size_t)(n > 0 ? n : 1) * 13, sizeof(double));
     if (g_abs) memset(g_abs, 0, (size_t)(n > 0 ? n : 0) * 10 * sizeof(double));
@@ -391,7 +551,7 @@ int or_backward_pixels(int64_t n, const double *means, const double *quats, cons
             double v[3], hx[3], hy[3];
             or_pixel_basis(s, pix[2 * q], pix[2 * q + 1], v, hx, hy);
             int fl = 0;
-            int64_t m = pixel_list(F, n, v, hx, hy, s->near_m, NULL, &L, &fl);
+            int64_t m = pixel_list(F, n, v, hx, hy, s->near_m, NULL, &L, &fl, cx);
             if (m + 1 > Acap) { Acap = 2 * (m + 1); Apre = (double *)realloc(Apre, (size_t)Acap * sizeof(double)); }
             /* A_k = prod_{i<k} (1 - alpha_i), by definition (forward prefix products) */
             Apre[0] = 1.0;
@@ -486,8 +646,20 @@ int or_backward_pixels(int64_t n, const double *means, const double *quats, cons
     }
     if (g_pose) memcpy(g_pose, gpose, sizeof(gpose));
     free(acc);
+    if (cx) cull_free(cx);
     free(F);
     return 0;
+}
+
+int or_backward_pixels(int64_t n, const double *means, const double *quats, const double *log_scales,
+                       const double *logits, const double *pose, const or_sensor *s,
+                       int64_t P, const int32_t *pix,
+                       const double *dL_dD, const double *dL_dN, const double *dL_dO,
+                       double *g_means, double *g_quats, double *g_log_scales, double *g_logits,
+                       double *g_pose, double *g_abs)
+{
+    return or_backward_pixels_mode(n, means, quats, log_scales, logits, pose, s, P, pix, dL_dD, dL_dN, dL_dO,
+                                   g_means, g_quats, g_log_scales, g_logits, g_pose, g_abs, 0);
 }
 
 /* ======================================================================== */

@@ -44,6 +44,8 @@ def lib():
         L.or_pixel_basis.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.or_render_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         L.or_backward_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
+        L.or_render_pixels_mode.argtypes = L.or_render_pixels.argtypes + [C.c_int32]
+        L.or_backward_pixels_mode.argtypes = L.or_backward_pixels.argtypes + [C.c_int32]
         L.or_bin.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                              P, P, P, P, C.c_int64, P, P, P, P]
         L.or_pair_support.argtypes = [P, P, P, C.c_double, P, P, C.c_int32, C.c_int32, P]
@@ -52,7 +54,8 @@ def lib():
         L.or_box_exp.restype = C.c_double
         L.or_support_radius.argtypes = [C.c_double]
         L.or_support_radius.restype = C.c_double
-        for f in ("or_render_pixels", "or_backward_pixels", "or_bin", "or_pair_support", "or_frames"):
+        for f in ("or_render_pixels", "or_backward_pixels", "or_render_pixels_mode", "or_backward_pixels_mode",
+                  "or_bin", "or_pair_support", "or_frames"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -112,8 +115,10 @@ def all_pixels(sensor):
     return np.ascontiguousarray(np.stack([ii.ravel(), jj.ravel()], 1))
 
 
-def render_pixels(means, quats, log_scales, logits, T_cw, sensor, pix=None, guard=DEFAULT_GUARD, exact=False):
+def render_pixels(means, quats, log_scales, logits, T_cw, sensor, pix=None, guard=DEFAULT_GUARD, exact=False,
+                  cull=False):
     """Brute-force FP64 render of the listed pixels ([P,2] int32 (row, col); default: all).
+    cull=True: the angular-cull mode (identical results, faster on large maps).
 
     Returns dict of depth [P], normal [P,3], alpha [P], T_final [P], n_contrib [P], flags [P].
     """
@@ -127,24 +132,24 @@ def render_pixels(means, quats, log_scales, logits, T_cw, sensor, pix=None, guar
     g = None if guard is None else np.ascontiguousarray(guard, dtype=np.float64)
     s = _sensor(sensor)
     pose = _pose12(T_cw)
-    rc = lib().or_render_pixels(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix), _p(g),
-                                _p(out["depth"]), _p(out["normal"]), _p(out["alpha"]), _p(out["T_final"]),
-                                _p(out["n_contrib"]), _p(out["flags"]))
+    rc = lib().or_render_pixels_mode(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix), _p(g),
+                                     _p(out["depth"]), _p(out["normal"]), _p(out["alpha"]), _p(out["T_final"]),
+                                     _p(out["n_contrib"]), _p(out["flags"]), 1 if cull else 0)
     if rc != 0:
         raise RuntimeError("or_render_pixels failed")
     return out
 
 
-def render_image(means, quats, log_scales, logits, T_cw, sensor, guard=DEFAULT_GUARD, exact=False):
+def render_image(means, quats, log_scales, logits, T_cw, sensor, guard=DEFAULT_GUARD, exact=False, cull=False):
     H, W = int(sensor["height"]), int(sensor["width"])
-    o = render_pixels(means, quats, log_scales, logits, T_cw, sensor, None, guard, exact)
+    o = render_pixels(means, quats, log_scales, logits, T_cw, sensor, None, guard, exact, cull)
     return dict(depth=o["depth"].reshape(H, W), normal=o["normal"].reshape(H, W, 3),
                 alpha=o["alpha"].reshape(H, W), T_final=o["T_final"].reshape(H, W),
                 n_contrib=o["n_contrib"].reshape(H, W), flags=o["flags"].reshape(H, W))
 
 
 def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, dL_dN, dL_dO, exact=False,
-                    with_abs=False):
+                    with_abs=False, cull=False):
     """Analytic FP64 gradients of sum_p (dL_dD D + dL_dN . N + dL_dO O) over the listed pixels.
 
     Returns dict of means [n,3], quats [n,4], log_scales [n,2], logits [n], pose [6] (rho; phi);
@@ -163,10 +168,10 @@ def backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix, dL_dD, 
         out["abs"] = np.zeros((n, 10))
     s = _sensor(sensor)
     pose = _pose12(T_cw)
-    rc = lib().or_backward_pixels(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix),
-                                  _p(gD), _p(gN), _p(gO), _p(out["means"]), _p(out["quats"]),
-                                  _p(out["log_scales"]), _p(out["logits"]), _p(out["pose"]),
-                                  _p(out.get("abs")))
+    rc = lib().or_backward_pixels_mode(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix),
+                                       _p(gD), _p(gN), _p(gO), _p(out["means"]), _p(out["quats"]),
+                                       _p(out["log_scales"]), _p(out["logits"]), _p(out["pose"]),
+                                       _p(out.get("abs")), 1 if cull else 0)
     if rc != 0:
         raise RuntimeError("or_backward_pixels failed")
     return out

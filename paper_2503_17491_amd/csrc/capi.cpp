@@ -59,6 +59,9 @@ slr_status check_sensor(const slr_sensor *s)
     if (!s) return fail(SLR_E_INVALID, "sensor is NULL");
     if (s->height <= 0 || s->width <= 0 || s->height > 32767 || s->width > 32767)
         return fail(SLR_E_INVALID, "image size %d x %d out of range [1, 32767]", s->height, s->width);
+    // the kernels index pixels and the three normal channels with 32-bit integers
+    if (3 * (int64_t)s->height * s->width >= (int64_t(1) << 31))
+        return fail(SLR_E_INVALID, "image size %d x %d: 3 H W must stay below 2^31", s->height, s->width);
     if (!(s->fu < 0.0) || !(s->fv < 0.0) || !std::isfinite(s->fu) || !std::isfinite(s->fv) ||
         !std::isfinite(s->cu) || !std::isfinite(s->cv))
         return fail(SLR_E_INVALID, "camera matrix must be finite with fu < 0 and fv < 0");
@@ -957,6 +960,31 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
     v->census = reinterpret_cast<const int32_t *>(ws + L.census);
     v->tiles_x = (sensor->width + tiling->tile_w - 1) / tiling->tile_w;
     v->tiles_y = (sensor->height + tiling->tile_h - 1) / tiling->tile_h;
+    return SLR_OK;
+}
+
+slr_status slr_batch_views(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
+                           const slr_tiling *tiling, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
+                           slr_views *v)
+{
+    if (!v) return fail(SLR_E_INVALID, "views is NULL");
+    Batch B;
+    slr_status st = check_batch(n_sets, sets, n_frames, frames, tiling, pair_capacity, &B);
+    if (st != SLR_OK) return st;
+    if ((st = check_ws(B.L, workspace, workspace_bytes)) != SLR_OK) return st;
+    const Layout &L = B.L;
+    char *ws = reinterpret_cast<char *>(workspace);
+    v->keys = reinterpret_cast<const uint32_t *>(ws + L.skey);
+    v->counts = reinterpret_cast<const int32_t *>(ws + L.cnt);
+    v->pixbox = reinterpret_cast<const int16_t *>(ws + L.box);
+    v->sorted_tile = reinterpret_cast<const int32_t *>(ws + (L.tile_in_1 ? L.pt1 : L.pt0));
+    v->sorted_id = reinterpret_cast<const int32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    v->ranges = reinterpret_cast<const int32_t *>(ws + L.ranges);
+    v->T_final = reinterpret_cast<const float *>(ws + L.stateT);
+    v->n_proc = reinterpret_cast<const int32_t *>(ws + L.stateN);
+    v->census = reinterpret_cast<const int32_t *>(ws + L.census);
+    v->tiles_x = L.tiles;
+    v->tiles_y = 1;
     return SLR_OK;
 }
 

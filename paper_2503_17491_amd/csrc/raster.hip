@@ -910,7 +910,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         census[2 * total_pixels + p] = n_eval;
         census[3 * total_pixels + p] = n_con;
     }
-    // block reduction of the pose partials, then FP64 atomics
+    // block reduction of the pose partials into this workgroup's own row (summed per
+    // keyframe in a fixed order by k_pose_reduce; no atomics)
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         double v = pacc[c];

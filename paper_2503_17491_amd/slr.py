@@ -64,7 +64,7 @@ class LossFrame(C.Structure):
 
 EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-           "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames", "slr_adam_step",
+           "slr_batch_counters", "slr_batch_views", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames", "slr_adam_step",
            "slr_stage_timer_enable", "slr_stage_times",
            "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
            "slr_scale_reg", "slr_init_workspace_size", "slr_init_splats", "slr_status_string", "slr_last_error"]
@@ -100,6 +100,7 @@ def lib():
         L.slr_batch_render.argtypes = BATCH + [P]
         L.slr_batch_backward.argtypes = [I32, P, P, I32, P, P, I64, P, C.c_size_t, C.c_uint32, P]
         L.slr_batch_counters.argtypes = BATCH + [P]
+        L.slr_batch_views.argtypes = BATCH + [P]
         L.slr_batch_autotune.argtypes = [I32, P, P, I32, P, P, I32, I64, P, C.c_size_t, I32, P, P, P]
         L.slr_loss_l1_normal.argtypes = [I64, P, P, P, P, C.c_float, C.c_float, P, P, P, P]
         L.slr_loss_l1_normal_frames.argtypes = [I32, P, P, P]
@@ -111,7 +112,8 @@ def lib():
         L.slr_last_error.restype = C.c_char_p
         for f in ("slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backward", "slr_workspace_views",
                   "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
-                  "slr_batch_counters", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames",
+                  "slr_batch_counters", "slr_batch_views", "slr_batch_autotune", "slr_loss_l1_normal",
+                  "slr_loss_l1_normal_frames",
                   "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
                   "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg",
                   "slr_init_workspace_size", "slr_init_splats"):
@@ -188,6 +190,9 @@ class Renderer:
         self.n = -1
         self.ws = None
         self.K = 0
+        # bumped by every forward: the workspace holds the binning and per-pixel
+        # state of the last render only, which a pending backward must match
+        self.generation = 0
 
     def _ensure(self, n):
         need = workspace_size(self.sensor, self.tiling, n, self.capacity)
@@ -215,6 +220,7 @@ class Renderer:
                 continue
             _check(st, "slr_render")
             self.K = int(K.value)
+            self.generation += 1
             return depth, normal, alpha
         raise SlrError(SLR_E_CAPACITY, "slr_render")
 
@@ -405,6 +411,37 @@ class BatchRenderer:
         _check(lib().slr_batch_backward(a[0], a[1], None if pose_only else self._c_grads, a[2], a[3], a[4], a[5],
                                         _ptr(self.ws), self.ws.numel(), flags, _stream()), "slr_batch_backward")
 
+    def views(self):
+        """Copies of the batch's binning results and per-pixel state (global
+        record, tile and pixel indices; see slr_batch_views) plus the
+        per-frame offsets item_off, tile_off, pix_off (host lists)."""
+        v = Views()
+        _check(lib().slr_batch_views(*self._args(), _ptr(self.ws), self.ws.numel(), C.byref(v)), "slr_batch_views")
+        base = self.ws.data_ptr()
+
+        def take(ptr, count, dtype):
+            off = ptr - base
+            nbytes = count * torch.tensor([], dtype=dtype).element_size()
+            return self.ws[off:off + nbytes].view(dtype).clone()
+
+        th, tw = int(self.tiling[0]), int(self.tiling[1])
+        item_off, tile_off, pix_off = [], [], []
+        it = tl = px = 0
+        for f in self.frames:
+            H, W = int(f["sensor"]["height"]), int(f["sensor"]["width"])
+            item_off.append(it); tile_off.append(tl); pix_off.append(px)
+            it += int(self.sets[int(f["set"])]["means"].shape[0])
+            tl += ((H + th - 1) // th) * ((W + tw - 1) // tw)
+            px += H * W
+        K, _ = self.pairs()
+        return dict(keys=take(v.keys, it, torch.int32), counts=take(v.counts, it, torch.int32),
+                    pixbox=take(v.pixbox, 8 * it, torch.int16).view(it, 8),
+                    sorted_tile=take(v.sorted_tile, K, torch.int32), sorted_id=take(v.sorted_id, K, torch.int32),
+                    ranges=take(v.ranges, 2 * tl, torch.int32).view(tl, 2),
+                    T_final=take(v.T_final, px, torch.float32), n_proc=take(v.n_proc, px, torch.int32),
+                    census=take(v.census, 4 * px, torch.int32).view(4, px), item_off=item_off, tile_off=tile_off,
+                    pix_off=pix_off, K=K)
+
     def pairs(self):
         """(K, overflow) of the last render (synchronises)."""
         c = self.counters.cpu().tolist()
@@ -571,6 +608,7 @@ class _RenderFn(torch.autograd.Function):
         D, N, O = renderer.forward(means, quats, log_scales, logits, T_cw)
         ctx.save_for_backward(means, quats, log_scales, logits, T_cw)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
         ctx.surfel_grad = any(ctx.needs_input_grad[:4])
         return D, N, O
 
@@ -578,6 +616,10 @@ class _RenderFn(torch.autograd.Function):
     def backward(ctx, gD, gN, gO):
         means, quats, log_scales, logits, T_cw = ctx.saved_tensors
         r = ctx.renderer
+        if r.generation != ctx.generation:
+            raise RuntimeError("the Renderer rendered again after this render and before its backward: its "
+                               "workspace no longer holds this render's binning and per-pixel state (use one "
+                               "Renderer per differentiable render in a graph)")
         gD = None if gD is None else gD.contiguous().float()
         gN = None if gN is None else gN.contiguous().float()
         gO = None if gO is None else gO.contiguous().float()
@@ -595,7 +637,12 @@ def render(means, quats, log_scales, logits, T_cw, renderer, xi=None):
     T_cw: float64 [4,4] CUDA tensor (world -> sensor).  xi: optional float64
     [6] CUDA leaf standing for the local pose perturbation delta = (rho; phi)
     of T_wc <- T_wc exp(delta), taken at delta = 0; its .grad is dL/ddelta.
+    Raises if xi is not zero.  One Renderer holds the state of its last render
+    only: a backward through an earlier render of the same Renderer raises.
     """
     if xi is None:
         xi = torch.zeros(6, dtype=torch.float64, device=means.device)
+    elif xi.shape != (6,) or bool((xi != 0).any()):
+        # the render is taken at delta = 0: a stepped xi would be silently ignored
+        raise ValueError("xi must be a zero [6] tensor (fold a pose step into T_cw and reset xi)")
     return _RenderFn.apply(means, quats, log_scales, logits, xi, T_cw, renderer)

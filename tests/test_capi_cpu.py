@@ -98,6 +98,19 @@ def test_render_rejects_bad_arguments_without_gpu():
     assert st == slr.SLR_E_INVALID
 
 
+def test_sensor_rejects_images_beyond_32bit_pixel_indices():
+    """The compositing kernels index the three normal channels of a pixel with
+    32-bit integers: images with 3 H W >= 2^31 are rejected up front."""
+    L = slr.lib()
+    t = slr.Tiling(16, 16)
+    b = C.c_size_t(0)
+    ok = slr._sensor(slr.make_sensor(26000, 27000))    # 3 H W = 2.106e9 < 2^31
+    assert L.slr_workspace_size(C.byref(ok), C.byref(t), 10, 100, C.byref(b)) == slr.SLR_OK
+    big = slr._sensor(slr.make_sensor(27000, 27000))   # 3 H W = 2.187e9 >= 2^31
+    assert L.slr_workspace_size(C.byref(big), C.byref(t), 10, 100, C.byref(b)) == slr.SLR_E_INVALID
+    assert b"2^31" in L.slr_last_error()
+
+
 def test_backward_rejects_inconsistent_gradient_outputs():
     L = slr.lib()
     s, t, buf = _args()

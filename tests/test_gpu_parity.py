@@ -374,6 +374,31 @@ def test_autograd_function(slr):
     np.testing.assert_allclose(xi.grad.cpu().numpy(), dp.cpu().numpy(), rtol=1e-6)
 
 
+def test_autograd_stale_render_raises(slr):
+    """Two differentiable renders through one Renderer before backward: the
+    workspace holds the second render's state, so the first one's backward
+    must raise instead of returning gradients of the wrong binning; the second
+    one's backward still works.  A non-zero xi is rejected."""
+    say("autograd: stale render, non-zero xi")
+    sc = synth.shell_scene(1500, 7)
+    sensor = slr.make_sensor(64, 512)
+    d = to_dev(sc)
+    for k in d:
+        d[k].requires_grad_(True)
+    r = slr.Renderer(sensor)
+    D1, _, _ = slr.render(d["means"], d["quats"], d["log_scales"], d["logits"], pose_dev(synth.perturbed_pose(3)), r)
+    D2, _, _ = slr.render(d["means"], d["quats"], d["log_scales"], d["logits"], pose_dev(synth.perturbed_pose(4)), r)
+    with pytest.raises(RuntimeError, match="rendered again"):
+        D1.sum().backward(retain_graph=True)
+    for k in d:
+        d[k].grad = None
+    D2.sum().backward()
+    assert torch.isfinite(d["means"].grad).all() and d["means"].grad.abs().sum() > 0
+    xi = torch.full((6,), 1e-3, dtype=torch.float64, device=DEV, requires_grad=True)
+    with pytest.raises(ValueError, match="xi"):
+        slr.render(d["means"], d["quats"], d["log_scales"], d["logits"], pose_dev(np.eye(4)), r, xi)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_edge_cases(slr):
     say("edge: empty, all culled, capacity overflow")
