@@ -24,6 +24,9 @@
  *                        skips only pairs whose support test must fail (the
  *                        ray's line misses the bounding sphere of the 3-sigma
  *                        square); pinned identical to brute force.
+ *   or_render_variants   the admissible results of a pixel whose decisions lie
+ *                        within rounding distance of a threshold: each such
+ *                        decision taken both ways (Sec. 3.2.1 blending rules).
  *   or_bin               Sec. 3.2.1 (16x16 tiles, per-tile lists sorted by
  *                        range) and Sec. 3.2.3 / Supp. B (3-sigma splat box,
  *                        centre-relative azimuth extent, seam propagation),
@@ -473,6 +476,181 @@ int or_render_pixels(int64_t n, const double *means, const double *quats, const 
 {
     return or_render_pixels_mode(n, means, quats, log_scales, logits, pose, s, P, pix, guard, depth, normal,
                                  alpha, T_final, n_contrib, flags, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Guard-band variants of a pixel.                                          */
+/*                                                                          */
+/* Where the FP64 value of a decision lies within rounding distance of its  */
+/* threshold (the guard band: the 3-sigma support, the near range, the      */
+/* 1/255 alpha floor, the 1e-4 transmittance stop), an FP32 evaluation may   */
+/* take it either way, and both outcomes are results of the method.  For a  */
+/* pixel, the pairs whose inclusion hangs on such decisions and the stop    */
+/* tests that fall in the band are branched on, both ways, in list order (a */
+/* depth-first walk of Eqs. ab_depth / ab_normal / ab_opacity); every leaf  */
+/* is one admissible (D, N, O).  The walk with no branch taken is the plain */
+/* render of or_render_pixels, bit for bit (slot 0).  At most max_flips     */
+/* branches are taken along a path; a pixel that needs more reports         */
+/* overflow.  The alpha clamp is continuous in the forward and not branched. */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t id;
+    float key;
+    int contrib;     /* the decisions as evaluated */
+    int flip_inc;    /* a flagged decision can turn the inclusion around */
+    double alpha, d;
+} ext_pair;
+
+static int ext_cmp(const void *a, const void *b)
+{
+    const ext_pair *x = (const ext_pair *)a, *y = (const ext_pair *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;   /* near to far, then by index */
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+/* Evaluates every decision of one pair; returns 1 if the pair contributes or
+ * a flagged decision could make it contribute (then *e is filled). */
+static int pair_eval_ext(const or_frame *f, const double *v, const double *hx, const double *hy, double near_m,
+                         const double *guard, ext_pair *e)
+{
+    double ha[3], hb[3], ph[3], sh[2], nu[3];
+    ha[0] = dot3(hx, f->ba); ha[1] = dot3(hx, f->bb); ha[2] = dot3(hx, f->bc);
+    hb[0] = dot3(hy, f->ba); hb[1] = dot3(hy, f->bb); hb[2] = dot3(hy, f->bc);
+    cross3(ha, hb, ph);
+    if (ph[2] == 0.0) return 0;
+    sh[0] = ph[0] / ph[2];
+    sh[1] = ph[1] / ph[2];
+    double m = fmax(fabs(sh[0]), fabs(sh[1]));
+    int sup = m <= OR_SUPPORT, fsup = fabs(m - OR_SUPPORT) < guard[0];
+    for (int k = 0; k < 3; ++k) nu[k] = sh[0] * f->ba[k] + sh[1] * f->bb[k] + f->bc[k];
+    double t = dot3(nu, v);
+    int nr = t > near_m, fnr = fabs(t - near_m) < guard[1];
+    double d = sqrt(dot3(nu, nu));
+    double G = exp(-0.5 * (sh[0] * sh[0] + sh[1] * sh[1]));
+    double a = f->o * G;
+    int am = !(a < OR_ALPHA_MIN), fam = fabs(a - OR_ALPHA_MIN) < guard[2] * OR_ALPHA_MIN;
+    e->contrib = sup && nr && am;
+    if (e->contrib)
+        e->flip_inc = fsup || fnr || fam;
+    else
+        e->flip_inc = (sup || fsup) && (nr || fnr) && (am || fam);
+    if (!e->contrib && !e->flip_inc) return 0;
+    e->alpha = a > OR_ALPHA_MAX ? OR_ALPHA_MAX : a;
+    e->d = d;
+    e->key = f->key;
+    return 1;
+}
+
+typedef struct {
+    const ext_pair *p;
+    int64_t n;
+    const or_frame *F;
+    double gT;
+    int max_flips, cap, nout, overflow;
+    double *D, *N, *O;   /* [cap], [cap, 3], [cap]; slot 0 = no branch taken */
+    int have_base;
+} vwalk_ctx;
+
+static void vwalk_emit(vwalk_ctx *c, int flips, double D, const double *N, double O)
+{
+    int slot;
+    if (flips == 0) { slot = 0; c->have_base = 1; }
+    else {
+        if (c->nout >= c->cap) { c->overflow = 1; return; }
+        slot = c->nout;
+    }
+    c->D[slot] = D; c->O[slot] = O;
+    for (int k = 0; k < 3; ++k) c->N[3 * slot + k] = N[k];
+    if (flips != 0) c->nout++;
+}
+
+/* Composites from list position i with state (T, D, N, O); force_inc /
+ * force_stop (-1: none) impose the outcome of pair i's decisions. */
+static void vwalk(vwalk_ctx *c, int64_t i, double T, double D, const double *N0, double O, int flips,
+                  int force_inc, int force_stop)
+{
+    double N[3] = {N0[0], N0[1], N0[2]};
+    for (; i < c->n; ++i) {
+        const ext_pair *p = &c->p[i];
+        int inc = p->contrib;
+        if (force_inc >= 0) {
+            inc = force_inc;
+            force_inc = -1;
+        } else if (p->flip_inc) {
+            if (flips < c->max_flips) vwalk(c, i, T, D, N, O, flips + 1, !inc, -1);
+            else c->overflow = 1;
+        }
+        if (!inc) continue;
+        double tT = T * (1.0 - p->alpha);
+        int stop = tT < OR_T_MIN;
+        if (force_stop >= 0) {
+            stop = force_stop;
+            force_stop = -1;
+        } else if (fabs(tT - OR_T_MIN) < c->gT * OR_T_MIN) {
+            if (flips < c->max_flips) vwalk(c, i, T, D, N, O, flips + 1, 1, !stop);
+            else c->overflow = 1;
+        }
+        if (stop) break;
+        double w = p->alpha * T;
+        D += w * p->d;
+        for (int k = 0; k < 3; ++k) N[k] += w * c->F[p->id].n[k];
+        O += w;
+        T = tT;
+    }
+    vwalk_emit(c, flips, D, N, O);
+}
+
+/* For each listed pixel: nvar[q] admissible results (slot 0 = the plain
+ * render) in depth [P, cap], normal [P, cap, 3], alpha [P, cap], with
+ * cap = 2^max_flips (max_flips in [0, 6]); overflow[q] = 1 when a path needed
+ * more than max_flips branches or more than cap results. */
+int or_render_variants(int64_t n, const double *means, const double *quats, const double *log_scales,
+                       const double *logits, const double *pose, const or_sensor *s, int64_t P, const int32_t *pix,
+                       const double *guard, int32_t max_flips, double *depth, double *normal, double *alpha,
+                       int32_t *nvar, int32_t *overflow, int32_t cull)
+{
+    if (n < 0 || P < 0 || !s || !guard || max_flips < 0 || max_flips > 6) return -1;
+    const int cap = 1 << max_flips;
+    or_frame *F = build_frames(n, means, quats, log_scales, logits, pose, s->near_m);
+    cull_index cxs, *cx = NULL;
+    if (cull) { cull_build(F, n, &cxs); cx = &cxs; }
+    #pragma omp parallel
+    {
+        ext_pair *buf = NULL;
+        int64_t nb = 0, cb = 0;
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < P; ++q) {
+            double v[3], hx[3], hy[3];
+            or_pixel_basis(s, pix[2 * q], pix[2 * q + 1], v, hx, hy);
+            nb = 0;
+            int64_t b0 = 0, b1 = n;
+            if (cx) { int64_t b = cull_bin(cx, v); b0 = cx->start[b]; b1 = cx->start[b + 1]; }
+            for (int64_t r = b0; r < b1; ++r) {
+                int32_t k = cx ? cx->ids[r] : (int32_t)r;
+                if (!F[k].valid) continue;
+                if (cx) {
+                    const double *c = cx->cone + 4 * (int64_t)k;
+                    if (fabs(v[0] * c[0] + v[1] * c[1] + v[2] * c[2]) < c[3]) continue;
+                }
+                ext_pair e;
+                if (!pair_eval_ext(&F[k], v, hx, hy, s->near_m, guard, &e)) continue;
+                e.id = k;
+                if (nb == cb) { cb = cb ? 2 * cb : 64; buf = (ext_pair *)realloc(buf, (size_t)cb * sizeof(ext_pair)); }
+                buf[nb++] = e;
+            }
+            qsort(buf, (size_t)nb, sizeof(ext_pair), ext_cmp);
+            vwalk_ctx c = {buf, nb, F, guard[3], max_flips, cap, 1, 0,
+                           depth + (int64_t)cap * q, normal + 3 * (int64_t)cap * q, alpha + (int64_t)cap * q, 0};
+            const double N0[3] = {0.0, 0.0, 0.0};
+            vwalk(&c, 0, 1.0, 0.0, N0, 0.0, 0, -1, -1);
+            nvar[q] = c.nout;
+            overflow[q] = c.overflow || !c.have_base;
+        }
+        free(buf);
+    }
+    if (cx) cull_free(cx);
+    free(F);
+    return 0;
 }
 
 /* Supp. D, last block: gradients w.r.t. the raw parameters of one surfel from

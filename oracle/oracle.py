@@ -45,6 +45,8 @@ def lib():
         L.or_render_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         L.or_backward_pixels.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
         L.or_render_pixels_mode.argtypes = L.or_render_pixels.argtypes + [C.c_int32]
+        L.or_render_variants.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int64, P, P, C.c_int32, P, P, P, P, P,
+                                         C.c_int32]
         L.or_backward_pixels_mode.argtypes = L.or_backward_pixels.argtypes + [C.c_int32]
         L.or_bin.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                              P, P, P, P, C.c_int64, P, P, P, P]
@@ -55,6 +57,7 @@ def lib():
         L.or_support_radius.argtypes = [C.c_double]
         L.or_support_radius.restype = C.c_double
         for f in ("or_render_pixels", "or_backward_pixels", "or_render_pixels_mode", "or_backward_pixels_mode",
+                  "or_render_variants",
                   "or_bin", "or_pair_support", "or_frames"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -137,6 +140,31 @@ def render_pixels(means, quats, log_scales, logits, T_cw, sensor, pix=None, guar
                                      _p(out["n_contrib"]), _p(out["flags"]), 1 if cull else 0)
     if rc != 0:
         raise RuntimeError("or_render_pixels failed")
+    return out
+
+
+def render_variants(means, quats, log_scales, logits, T_cw, sensor, pix, guard=DEFAULT_GUARD, max_flips=4,
+                    cull=False, exact=False):
+    """Every admissible result of the listed pixels: the decisions whose FP64
+    value lies in the guard band of its threshold are taken both ways.
+
+    Returns dict of depth [P,V], normal [P,V,3], alpha [P,V] (V = 2**max_flips;
+    slot 0 is the plain render), nvar [P] (filled slots), overflow [P] (the
+    pixel needs more than max_flips branches: not all results are listed)."""
+    n, m, q, ls, lo = _surfels(means, quats, log_scales, logits, exact)
+    pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 2)
+    P = pix.shape[0]
+    V = 1 << int(max_flips)
+    out = dict(depth=np.zeros((P, V)), normal=np.zeros((P, V, 3)), alpha=np.zeros((P, V)),
+               nvar=np.zeros(P, np.int32), overflow=np.zeros(P, np.int32))
+    g = np.ascontiguousarray(guard, dtype=np.float64)
+    s = _sensor(sensor)
+    pose = _pose12(T_cw)
+    rc = lib().or_render_variants(n, _p(m), _p(q), _p(ls), _p(lo), _p(pose), C.byref(s), P, _p(pix), _p(g),
+                                  int(max_flips), _p(out["depth"]), _p(out["normal"]), _p(out["alpha"]),
+                                  _p(out["nvar"]), _p(out["overflow"]), 1 if cull else 0)
+    if rc != 0:
+        raise RuntimeError("or_render_variants failed")
     return out
 
 

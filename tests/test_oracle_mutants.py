@@ -14,6 +14,8 @@ SRC = os.path.join(ROOT, "oracle", "oracle.c")
 F = "tests/test_oracle_forward.py"
 B = "tests/test_oracle_backward.py"
 N = "tests/test_oracle_bin.py"
+V = "tests/test_oracle_variants.py"
+C = "tests/test_oracle_cull.py"
 
 MUTANTS = [
     ("camera matrix uses W instead of W-1", "out[0] = -((double)W - 1.0) / fov_h;", "out[0] = -((double)W) / fov_h;", [F]),
@@ -35,6 +37,17 @@ MUTANTS = [
      "double lx = V[klo][0] * T->cm + V[klo][1] * T->sm, ly = V[klo][1] * T->cm - V[klo][0] * T->sm;",
      "double lx = V[klo][0] * T->cm - 200.0 * V[klo][1] * T->sm, ly = V[klo][1] * T->cm + 200.0 * V[klo][0] * T->sm;",
      [N]),
+    ("variants never branch on the stop rule", "} else if (fabs(tT - OR_T_MIN) < c->gT * OR_T_MIN) {",
+     "} else if (0) {", [V]),
+    ("variants ignore the alpha-floor band", "fam = fabs(a - OR_ALPHA_MIN) < guard[2] * OR_ALPHA_MIN;", "fam = 0;", [V]),
+    ("variant branch keeps the inclusion", "vwalk(c, i, T, D, N, O, flips + 1, !inc, -1);",
+     "vwalk(c, i, T, D, N, O, flips + 1, inc, -1);", [V]),
+    ("cull sphere radius without the 3-sigma factor",
+     "double r = 3.0 * sqrt(F[k].s[0] * F[k].s[0] + F[k].s[1] * F[k].s[1]) * 1.001 + 1e-9;",
+     "double r = sqrt(F[k].s[0] * F[k].s[0] + F[k].s[1] * F[k].s[1]) * 1.001 + 1e-9;", [C]),
+    ("cull tests only the forward half of the line",
+     "if (fabs(v[0] * c[0] + v[1] * c[1] + v[2] * c[2]) < c[3]) continue;\n            or_pair p;",
+     "if ((v[0] * c[0] + v[1] * c[1] + v[2] * c[2]) < c[3]) continue;\n            or_pair p;", [C]),
 ]
 
 
