@@ -239,7 +239,10 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
  * so that a whole optimisation iteration can be captured in a HIP graph and
  * replayed.  Frames reference surfel sets; several frames may share one set
  * (one map seen from several keyframes), in which case the set's gradients
- * are summed over those frames.  One tile shape serves the whole batch.
+ * are summed over those frames.  Each frame is binned and composited with its
+ * own tile shape (slr_frame.tile_h, tile_w; by default the tiling's), so
+ * wide and narrow range images can share one launch; the compositing forms,
+ * schedule, box mode and backward batch size are the batch's.
  *
  * Usage: size the workspace, call slr_batch_prepare once (it uploads the
  * sensor tables and the per-frame descriptors, i.e. every pointer below, into
@@ -257,6 +260,8 @@ typedef struct slr_frame {
     float *depth, *normal, *alpha;    /* device outputs [H,W], [H,W,3], [H,W] */
     const float *dL_ddepth, *dL_dnormal, *dL_dalpha; /* device upstream gradients, nullable */
     double *d_pose;                   /* device [6] FP64 pose gradient, nullable */
+    int32_t tile_h, tile_w;           /* this frame's tile shape (one of the shapes slr_tiling
+                                         accepts), or 0, 0 for the batch tiling's shape */
 } slr_frame;
 
 typedef struct slr_surfel_grads {

@@ -77,12 +77,15 @@ slr_status check_sensor(const slr_sensor *s)
     return SLR_OK;
 }
 
+bool tile_shape_ok(int32_t th, int32_t tw)
+{
+    return (th == 16 && tw == 16) || (th == 8 && tw == 32) || (th == 32 && tw == 8) || (th == 4 && tw == 64);
+}
+
 slr_status check_tiling(const slr_tiling *t)
 {
     if (!t) return fail(SLR_E_INVALID, "tiling is NULL");
-    const bool ok = (t->tile_h == 16 && t->tile_w == 16) || (t->tile_h == 8 && t->tile_w == 32) ||
-                    (t->tile_h == 32 && t->tile_w == 8) || (t->tile_h == 4 && t->tile_w == 64);
-    if (!ok) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
+    if (!tile_shape_ok(t->tile_h, t->tile_w)) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
     if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
     if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE)
@@ -201,10 +204,13 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
         if ((st = check_sensor(&fr.sensor)) != SLR_OK) return st;
         if (!fr.pose_cw || !aligned(fr.pose_cw, 8))
             return fail(SLR_E_INVALID, "frame %d: pose must be a non-NULL, 8-byte aligned device pointer", f);
-        const int64_t ftiles = (int64_t)((fr.sensor.height + tiling->tile_h - 1) / tiling->tile_h) *
-                               ((fr.sensor.width + tiling->tile_w - 1) / tiling->tile_w);
+        // the frame's own tile shape, or the batch's
+        const int32_t th = (fr.tile_h || fr.tile_w) ? fr.tile_h : tiling->tile_h;
+        const int32_t tw = (fr.tile_h || fr.tile_w) ? fr.tile_w : tiling->tile_w;
+        if (!tile_shape_ok(th, tw)) return fail(SLR_E_INVALID, "frame %d: unsupported tile shape %dx%d", f, th, tw);
+        const int64_t ftiles = (int64_t)((fr.sensor.height + th - 1) / th) * ((fr.sensor.width + tw - 1) / tw);
         if (ftiles > 65535) return fail(SLR_E_INVALID, "frame %d has %lld tiles, limit 65535", f, (long long)ftiles);
-        b->geom[f] = FrameGeom{fr.sensor.height, fr.sensor.width, fr.set};
+        b->geom[f] = FrameGeom{fr.sensor.height, fr.sensor.width, fr.set, th, tw};
         items += sets[fr.set].n;
         if (sets[fr.set].n > b->max_n) b->max_n = sets[fr.set].n;
     }
@@ -248,7 +254,7 @@ std::vector<FrameDesc> make_descs(const Batch &B, const slr_surfels *sets, const
         x.fu = fr.sensor.fu; x.cu = fr.sensor.cu; x.fv = fr.sensor.fv; x.cv = fr.sensor.cv;
         x.near_m = fr.sensor.near_m;
         x.H = fr.sensor.height; x.W = fr.sensor.width;
-        x.th = tiling->tile_h; x.tw = tiling->tile_w;
+        x.th = B.geom[f].th; x.tw = B.geom[f].tw;
         x.tiles_x = (x.W + x.tw - 1) / x.tw;
         x.tiles_y = (x.H + x.th - 1) / x.th;
         x.tile_off = (int32_t)tile;
@@ -360,7 +366,7 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     Layout L{};
     L.frames = nframes; L.sets = nsets; L.th = th; L.tw = tw; L.cap = cap;
     for (int32_t f = 0; f < nframes; ++f) {
-        const int64_t tx = (frames[f].W + tw - 1) / tw, ty = (frames[f].H + th - 1) / th;
+        const int64_t tx = (frames[f].W + frames[f].tw - 1) / frames[f].tw, ty = (frames[f].H + frames[f].th - 1) / frames[f].th;
         L.tiles += tx * ty;
         L.pixels += (int64_t)frames[f].H * frames[f].W;
         L.tab_entries += frames[f].W + 3 * frames[f].H;
@@ -464,7 +470,7 @@ slr_status slr_workspace_size(const slr_sensor *sensor, const slr_tiling *tiling
     if (!bytes) return fail(SLR_E_INVALID, "bytes is NULL");
     if (n < 0 || pair_capacity < 0 || pair_capacity > 0x7fffffffLL || n > (int64_t(1) << 30))
         return fail(SLR_E_INVALID, "n and pair_capacity out of range");
-    FrameGeom g{sensor->height, sensor->width, 0};
+    FrameGeom g{sensor->height, sensor->width, 0, tiling->tile_h, tiling->tile_w};
     *bytes = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w).total;
     return SLR_OK;
 }
@@ -945,7 +951,7 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
     if ((st = check_tiling(tiling)) != SLR_OK) return st;
     if (!workspace || !v) return fail(SLR_E_INVALID, "workspace and views must be non-NULL");
     if (n < 0 || pair_capacity < 0) return fail(SLR_E_INVALID, "negative size");
-    FrameGeom g{sensor->height, sensor->width, 0};
+    FrameGeom g{sensor->height, sensor->width, 0, tiling->tile_h, tiling->tile_w};
     Layout L = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w);
     if (workspace_bytes < L.total) return fail(SLR_E_INVALID, "workspace too small");
     char *ws = reinterpret_cast<char *>(workspace);

@@ -61,6 +61,7 @@ __device__ __forceinline__ double bcast(double v, int l)
 struct PairEval {
     float sa, sb, t, rc, G, alpha;
     bool clamped;
+    double c;   // M.v in FP64 (the backward refines the range with it)
 };
 
 // Shared by forward and backward so both take identical decisions.
@@ -81,7 +82,7 @@ __device__ __forceinline__ bool eval_pair(const RasterRec &r, double vx, double 
     const float G = __builtin_amdgcn_exp2f(kNegHalfLog2e * q);
     const float ag = r.opac * G;
     if (ag < kAlphaMin) return false;
-    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G;
+    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G; e.c = c;
     e.clamped = ag > kAlphaMax;
     e.alpha = e.clamped ? kAlphaMax : ag;
     return true;
@@ -106,7 +107,7 @@ __device__ __forceinline__ bool eval_pair_flat(const RasterRec &r, double vx, do
     const float q = fmaf(sa, sa, sb * sb);
     const float G = __builtin_amdgcn_exp2f(kNegHalfLog2e * q);
     const float ag = r.opac * G;
-    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G;
+    e.sa = sa; e.sb = sb; e.t = t; e.rc = rc; e.G = G; e.c = c;
     e.clamped = ag > kAlphaMax;
     e.alpha = e.clamped ? kAlphaMax : ag;
     return sup && (t > near_m) && !(ag < kAlphaMin);
@@ -177,7 +178,6 @@ __device__ __forceinline__ float wave_sum18(const float (&g)[18], int lane)
 
 __device__ __forceinline__ int bitrev6(int l) { return (int)(__builtin_bitreverse32((uint32_t)l) >> 26); }
 
-template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -185,11 +185,12 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
              int32_t *__restrict__ census_all, int64_t total_pixels)
 {
-    constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[256];
     __shared__ __align__(4) uint8_t slist[4][256];
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -199,14 +200,14 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     int32_t *census = census_all + fd.pix_off;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
     const int2 rg = ranges[tile];
     const int wid = threadIdx.x >> 6;
-    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
@@ -370,7 +371,6 @@ __device__ __forceinline__ bool strip_of_block(int64_t ntiles, int &strip, int &
 // each of them in turn takes the wave and the lanes evaluate their own
 // records for that pixel.  Same arithmetic and order as k_raster_fwd, hence
 // bit-identical results.
-template <int TW>
 __global__ void __launch_bounds__(64)
 k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
                const uint32_t *__restrict__ order,
@@ -378,13 +378,14 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
                int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles)
 {
-    constexpr int TH = 256 / TW, SR = 64 / TW;   // tile rows, strip rows
     __shared__ RasterRec sbuf[64];
     __shared__ uint8_t sidx[64];
     int strip, tslot;
     if (!strip_of_block(ntiles, strip, tslot)) return;
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two, strips of SR rows
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw), SR = 64 >> tws;
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -395,7 +396,7 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lane = threadIdx.x;
-    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const int i = ty * TH + strip * SR + (lane >> tws), j = tx * TW + (lane & (TW - 1));
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
@@ -535,7 +536,6 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
 // The record index and the record itself are wave-uniform, so they are read
 // with scalar loads into SGPRs and feed the VALU as scalar operands; no LDS,
 // no workgroup barrier, and a wave leaves as soon as its 64 pixels are done.
-template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -543,22 +543,23 @@ k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
                int32_t *__restrict__ census_all, int64_t total_pixels)
 {
-    constexpr int TH = 256 / TW;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
     const int2 rg = ranges[tile];
     const int wid = threadIdx.x >> 6;
-    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
@@ -639,8 +640,19 @@ struct BwdScalars {
     float da, db, dcs, tt, dop, w;
 };
 
+// The range of a pair to FP64 accuracy as t + t_lo: t = tau * rcp(c) carries
+// the FP32 rounding of tau, which is the same for every pixel of a record, so
+// coplanar surfels (whose exact ranges at a pixel coincide) would differ by a
+// systematic 1e-7 relative error and the depth channel's dL/dalpha, which is a
+// difference of such ranges, would be off by that much.  One correction step
+// with the record's FP64 tau and the FP64 c removes it.
+__device__ __forceinline__ float range_low(const PairEval &e, double tau)
+{
+    return (float)fma(-(double)e.t, e.c, tau) * e.rc;
+}
+
 __device__ __forceinline__ BwdScalars bwd_step(BwdState &st, const PairEval &e, float n0, float n1, float n2,
-                                               const BwdUpstream &u)
+                                               const BwdUpstream &u, float tlo)
 {
     const float r1 = __builtin_amdgcn_rcpf(1.0f - e.alpha);
     const float A = st.T * r1;  // transmittance in front of this pair
@@ -649,7 +661,10 @@ __device__ __forceinline__ BwdScalars bwd_step(BwdState &st, const PairEval &e, 
         st.tref = e.t; st.nr0 = n0; st.nr1 = n1; st.nr2 = n2;
         st.Kref = u.gd * st.tref + u.gn0 * st.nr0 + u.gn1 * st.nr1 + u.gn2 * st.nr2 + u.go;
     }
-    const float ck = u.gd * (e.t - st.tref) + u.gn0 * (n0 - st.nr0) + u.gn1 * (n1 - st.nr1) + u.gn2 * (n2 - st.nr2);
+    // t_ref is the FP32 value of the reference's range (any fixed value is exact
+    // algebra), t_k = t + t_lo to FP64 accuracy
+    const float ck = u.gd * ((e.t - st.tref) + tlo) + u.gn0 * (n0 - st.nr0) + u.gn1 * (n1 - st.nr1) +
+                     u.gn2 * (n2 - st.nr2);
     const float dA = ck * A + (st.Kref * u.Tfin - st.Bs) * r1;
     const float w = e.alpha * A;
     st.Bs = fmaf(ck, w, st.Bs);
@@ -668,10 +683,11 @@ __device__ __forceinline__ BwdScalars bwd_step(BwdState &st, const PairEval &e, 
 }
 
 __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
-                                         const double *ch, const BwdUpstream &u, double vx, double vy, double vz,
+                                         const ChatRec &chr, const BwdUpstream &u, double vx, double vy, double vz,
                                          float (&g)[18])
 {
-    const BwdScalars q = bwd_step(st, e, n0, n1, n2, u);
+    const BwdScalars q = bwd_step(st, e, n0, n1, n2, u, range_low(e, chr.tau));
+    const double *ch = chr.c;
     const float da = q.da, db = q.db, dcs = q.dcs, tt = q.tt, dop = q.dop, w = q.w;
     const float ex = (float)(vx - ch[0]), ey = (float)(vy - ch[1]), ez = (float)(vz - ch[2]);
     const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
@@ -704,9 +720,20 @@ __device__ __forceinline__ void centre_dir(const RasterRec &r, ChatRec &ch)
 {
     double pq[3];
     dcross(r.P, r.Q, pq);
-    const double sg = (r.tau < 0.0f ? -1.0 : 1.0) / sqrt((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2]);
+    const double sgn = r.tau < 0.0f ? -1.0 : 1.0;
+    const double sg = sgn / sqrt((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) ch.c[c] = pq[c] * sg;
+    ch.tau = sgn * sqrt((r.M[0] * pq[0] + r.M[1] * pq[1]) + r.M[2] * pq[2]);
+}
+
+// tau = b_c . M in FP64 from the cofactors (tau^2 = M . (P x Q)), with the sign
+// of the record's FP32 tau.
+__device__ __forceinline__ double record_tau(const RasterRec &r)
+{
+    double pq[3];
+    dcross(r.P, r.Q, pq);
+    return (r.tau < 0.0f ? -1.0 : 1.0) * sqrt((r.M[0] * pq[0] + r.M[1] * pq[1]) + r.M[2] * pq[2]);
 }
 
 // The axes of a staged record for its flush.
@@ -774,7 +801,7 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
 }
 
 
-template <int TW, int BATCH>
+template <int BATCH>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -784,7 +811,6 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
              double *__restrict__ pose_part, int pose_only)
 {
-    constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[BATCH];
     __shared__ ChatRec schat[BATCH];
     __shared__ float sred[kNg][BATCH];   // wave sums of the four waves, added in LDS
@@ -795,6 +821,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -806,7 +834,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     float *acc = fd.acc;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
@@ -814,7 +842,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     const int2 rg = ranges[tile];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int red_val = bitrev6(lane);  // the wave sum this lane holds after wave_sum18
-    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
     const int p = inside ? i * W + j : 0;
     float T = inside ? stT[p] : 1.0f;
     const int last = inside ? stN[p] : 0;
@@ -883,7 +911,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
                 if (act) {
                     ++n_con;
-                    bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k].c, up, vx, vy, vz, g);
+                    bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k], up, vx, vy, vz, g);
                 }
                 static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                 const float tot = wave_sum18(g, lane);
@@ -943,7 +971,6 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 // list): each of them in turn takes the wave, the lanes evaluate their own
 // records for it and the contributing ones are visited in reverse order.  At
 // the end of a chunk every lane flushes its own record's sums.
-template <int TW>
 __global__ void __launch_bounds__(64)
 k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
                const uint32_t *__restrict__ order,
@@ -952,7 +979,6 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
                double *__restrict__ pose_part, int pose_only, int64_t ntiles)
 {
-    constexpr int TH = 256 / TW, SR = 64 / TW;
     __shared__ RasterRec sbuf[64];
     __shared__ ChatRec schat[64];
     __shared__ float sred[kNg][64];
@@ -964,6 +990,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     }
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two, strips of SR rows
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw), SR = 64 >> tws;
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -973,7 +1001,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lane = threadIdx.x;
-    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const int i = ty * TH + strip * SR + (lane >> tws), j = tx * TW + (lane & (TW - 1));
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
@@ -1054,7 +1082,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                     for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
                     if (act) {
                         ++n_con;
-                        bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k].c, up, vx, vy, vz, g);
+                        bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k], up, vx, vy, vz, g);
                     }
                     static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                     const float tot = wave_sum18(g, lane);
@@ -1089,8 +1117,9 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                     ej.sa = bcast(ev.sa, jl); ej.sb = bcast(ev.sb, jl); ej.t = bcast(ev.t, jl);
                     ej.rc = bcast(ev.rc, jl); ej.G = bcast(ev.G, jl); ej.alpha = bcast(ev.alpha, jl);
                     ej.clamped = bcast(ev.clamped ? 1 : 0, jl) != 0;
+                    ej.c = bcast(ev.c, jl);
                     float g[kNg];
-                    bwd_pair(ps, ej, sbuf[jl].n[0], sbuf[jl].n[1], sbuf[jl].n[2], schat[jl].c, pu, pvx, pvy, pvz, g);
+                    bwd_pair(ps, ej, sbuf[jl].n[0], sbuf[jl].n[1], sbuf[jl].n[2], schat[jl], pu, pvx, pvy, pvz, g);
                     if (lane == jl) {
 #pragma unroll
                         for (int v = 0; v < kNg; ++v) sred[v][jl] += g[v];
@@ -1152,7 +1181,6 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
 // m w r J and m rho(r) (r = D - D_target, w the Huber IRLS weight, m the
 // caller's weight) in FP64; the workgroup's sums go to a row of their own,
 // summed per keyframe in a fixed order by k_gn_reduce.
-template <int TW>
 __global__ void __launch_bounds__(256)
 k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
             const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
@@ -1160,15 +1188,17 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
             const double2 *__restrict__ tables, const float *__restrict__ stT_all,
             const int32_t *__restrict__ stN_all, double *__restrict__ gn_part)
 {
-    constexpr int TH = 256 / TW;
     __shared__ RasterRec srec[kBwdBatch];
     __shared__ float sab[kBwdBatch][6];   // b_alpha, b_beta in FP32
+    __shared__ double stau[kBwdBatch];    // tau in FP64
     __shared__ uint8_t slist[4][kBwdBatch];
     __shared__ int s_last;
     __shared__ double s_red[4][kGnVals];
 
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -1176,7 +1206,7 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
     const int32_t *stN = stN_all + fd.pix_off;
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
     const int i = ty * TH + ly, j = tx * TW + lx;
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
@@ -1184,7 +1214,7 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
     const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
     const int2 rg = ranges[tile];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int wr0 = ty * TH + (wid * 64) / TW, wr1 = ty * TH + (wid * 64 + 63) / TW;
+    const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
     const int p = inside ? i * W + j : 0;
     const float Tfin = inside ? stT[p] : 1.0f;
     const int last = inside ? stN[p] : 0;
@@ -1215,6 +1245,7 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
                 sab[threadIdx.x][c] = (float)ba[c];
                 sab[threadIdx.x][3 + c] = (float)bb[c];
             }
+            stau[threadIdx.x] = record_tau(srec[threadIdx.x]);
         }
         __syncthreads();
         int nact = 0;
@@ -1238,7 +1269,7 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
             const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
             if (act) {
                 const RasterRec &r = srec[k];
-                const BwdScalars s = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up);
+                const BwdScalars s = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up, range_low(e, stau[k]));
                 const float ax = sab[k][0], ay = sab[k][1], az = sab[k][2];
                 const float bx = sab[k][3], by = sab[k][4], bz = sab[k][5];
                 const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
@@ -1315,7 +1346,6 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
 // (up to the compiler's choice of fused multiply-adds); the wave's sums are
 // written to row 4 tile slot + strip, and k_gn_reduce adds a tile's four
 // strip rows in the order k_raster_gn adds its four waves.
-template <int TW>
 __global__ void __launch_bounds__(64)
 k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
               const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
@@ -1323,14 +1353,16 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
               const double2 *__restrict__ tables, const float *__restrict__ stT_all,
               const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, int64_t ntiles)
 {
-    constexpr int TH = 256 / TW, SR = 64 / TW;
     __shared__ RasterRec sbuf[64];
     __shared__ float sab[64][6];   // b_alpha, b_beta in FP32
+    __shared__ double stau[64];    // tau in FP64
     __shared__ uint8_t slist[64];
     int strip, tslot;
     if (!strip_of_block(ntiles, strip, tslot)) return;
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
+    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two, strips of SR rows
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw), SR = 64 >> tws;
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
     const float near_m = (float)fd.near_m;
     const double2 *col = tables + fd.tab_off, *rowc = col + W;
@@ -1339,7 +1371,7 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
     const int ltile = tile - fd.tile_off;
     const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
     const int lane = threadIdx.x;
-    const int i = ty * TH + strip * SR + lane / TW, j = tx * TW + lane % TW;
+    const int i = ty * TH + strip * SR + (lane >> tws), j = tx * TW + (lane & (TW - 1));
     const bool inside = (i < H) && (j < W);
     const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
     const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
@@ -1370,6 +1402,7 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
                 sab[lane][q] = (float)ba[q];
                 sab[lane][3 + q] = (float)bb[q];
             }
+            stau[lane] = record_tau(sbuf[lane]);
         }
         const uint64_t m = __ballot(meets);
         const int nact = __popcll(m);
@@ -1386,7 +1419,7 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
             const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
             if (act) {
                 const RasterRec &r = sbuf[k];
-                const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up);
+                const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up, range_low(e, stau[k]));
                 const float ax = sab[k][0], ay = sab[k][1], az = sab[k][2];
                 const float bx = sab[k][3], by = sab[k][4], bz = sab[k][5];
                 const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
@@ -1453,13 +1486,12 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
     if (lane == 0) row[kGnVals] = (double)tile_frame[tile];
 }
 
-template <int TW>
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
     if (wave) {
-        hipLaunchKernelGGL(k_raster_fwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        hipLaunchKernelGGL(k_raster_fwd_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                            L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
@@ -1469,7 +1501,7 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles);
         return;
     }
-    hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s<TW> : k_raster_fwd<TW>,
+    hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s : k_raster_fwd,
                        dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
@@ -1478,14 +1510,13 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
                        reinterpret_cast<int32_t *>(ws + L.stateN), reinterpret_cast<int32_t *>(ws + L.census), L.pixels);
 }
 
-template <int TW>
 void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (wave) {
-        hipLaunchKernelGGL(k_raster_bwd_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        hipLaunchKernelGGL(k_raster_bwd_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
                            reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
@@ -1495,7 +1526,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                            reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles);
         return;
     }
-    auto kern = L.bwd_batch == 128 ? k_raster_bwd<TW, 128> : k_raster_bwd<TW, kBwdBatch>;
+    auto kern = L.bwd_batch == 128 ? k_raster_bwd<128> : k_raster_bwd<kBwdBatch>;
     hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
@@ -1505,13 +1536,12 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        pose_only ? 1 : 0);
 }
 
-template <int TW>
 void gn_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (L.bwd_variant == SLR_VARIANT_WAVE) {
-        hipLaunchKernelGGL(k_raster_gn_w<TW>, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        hipLaunchKernelGGL(k_raster_gn_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
                            reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
@@ -1520,7 +1550,7 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
                            reinterpret_cast<double *>(ws + L.gn_part), L.tiles);
         return;
     }
-    hipLaunchKernelGGL(k_raster_gn<TW>, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_raster_gn, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
@@ -1532,34 +1562,19 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.tiles == 0) return;
-    switch (L.tw) {
-    case 16: fwd_launch<16>(L, ws, stream); break;
-    case 32: fwd_launch<32>(L, ws, stream); break;
-    case 8: fwd_launch<8>(L, ws, stream); break;
-    default: fwd_launch<64>(L, ws, stream); break;
-    }
+    fwd_launch(L, ws, stream);
 }
 
 void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     if (L.tiles == 0) return;
-    switch (L.tw) {
-    case 16: bwd_launch<16>(L, ws, pose_only, stream); break;
-    case 32: bwd_launch<32>(L, ws, pose_only, stream); break;
-    case 8: bwd_launch<8>(L, ws, pose_only, stream); break;
-    default: bwd_launch<64>(L, ws, pose_only, stream); break;
-    }
+    bwd_launch(L, ws, pose_only, stream);
 }
 
 void launch_raster_gn(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.tiles == 0) return;
-    switch (L.tw) {
-    case 16: gn_launch<16>(L, ws, stream); break;
-    case 32: gn_launch<32>(L, ws, stream); break;
-    case 8: gn_launch<8>(L, ws, stream); break;
-    default: gn_launch<64>(L, ws, stream); break;
-    }
+    gn_launch(L, ws, stream);
 }
 
 }  // namespace slr

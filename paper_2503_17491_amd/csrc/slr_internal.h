@@ -43,10 +43,11 @@ struct __align__(16) FrameRec {
 static_assert(sizeof(FrameRec) == 96, "FrameRec layout");
 
 // Unit direction of b_c of a record (FP64), the reference the backward
-// subtracts from pixel rays before accumulating (derived from the record when
-// it is staged).
+// subtracts from pixel rays before accumulating, and tau = b_c . M in FP64
+// (both derived from the record when it is staged).
 struct ChatRec {
     double c[3];
+    double tau;
 };
 
 // Pixel box: rows [r0, r1], columns [c0, c1] and optionally [c2, c3]; frame
@@ -110,6 +111,7 @@ struct Layout {
 
 struct FrameGeom {
     int32_t H, W, set;
+    int32_t th, tw;   // the frame's tile shape
 };
 
 Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, const int64_t *set_n, int64_t cap,

@@ -49,7 +49,7 @@ class Views(C.Structure):
 class Frame(C.Structure):
     _fields_ = [("set", C.c_int32), ("pose_cw", C.c_void_p), ("sensor", Sensor), ("depth", C.c_void_p),
                 ("normal", C.c_void_p), ("alpha", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dnormal", C.c_void_p),
-                ("dL_dalpha", C.c_void_p), ("d_pose", C.c_void_p)]
+                ("dL_dalpha", C.c_void_p), ("d_pose", C.c_void_p), ("tile_h", C.c_int32), ("tile_w", C.c_int32)]
 
 
 class SurfelGrads(C.Structure):
@@ -317,7 +317,8 @@ class BatchRenderer:
     surfel gradients) are owned here and stay at fixed addresses.
 
     sets:   list of dicts with means, quats, log_scales, logits (CUDA tensors)
-    frames: list of dicts with set (index), T_cw (float64 [4,4] CUDA), sensor
+    frames: list of dicts with set (index), T_cw (float64 [4,4] CUDA), sensor,
+            optionally tile = (tile_h, tile_w): the frame's own tile shape
     """
 
     def __init__(self, sets, frames, tiling=(16, 16), capacity=1 << 22, device="cuda"):
@@ -348,14 +349,61 @@ class BatchRenderer:
         self._c_grads = (SurfelGrads * max(len(sets), 1))(*[SurfelGrads(g["means"].data_ptr(), g["quats"].data_ptr(),
                                                                          g["log_scales"].data_ptr(),
                                                                          g["logits"].data_ptr()) for g in self.grads])
-        self._c_frames = (Frame * max(len(frames), 1))(*[
-            Frame(int(f["set"]), f["T_cw"].data_ptr(), _sensor(f["sensor"]), o[0].data_ptr(), o[1].data_ptr(),
-                  o[2].data_ptr(), u[0].data_ptr(), u[1].data_ptr(), u[2].data_ptr(), dp.data_ptr())
-            for f, o, u, dp in zip(frames, self.out, self.up, self.dpose)])
+        self._make_frames()
         self.ws = None
         self.prepare()
         if auto and self._key not in _tuned:
             self.autotune()
+
+    def _make_frames(self):
+        self._c_frames = (Frame * max(len(self.frames), 1))(*[
+            Frame(int(f["set"]), f["T_cw"].data_ptr(), _sensor(f["sensor"]), o[0].data_ptr(), o[1].data_ptr(),
+                  o[2].data_ptr(), u[0].data_ptr(), u[1].data_ptr(), u[2].data_ptr(), dp.data_ptr(),
+                  *(tuple(f.get("tile") or (0, 0))))
+            for f, o, u, dp in zip(self.frames, self.out, self.up, self.dpose)])
+
+    def frame_tile(self, f):
+        """(tile_h, tile_w) of frame f: its own shape or the batch tiling's."""
+        t = self.frames[f].get("tile")
+        return (int(t[0]), int(t[1])) if t else (int(self.tiling[0]), int(self.tiling[1]))
+
+    def set_frame_tiles(self, tiles):
+        """Give frame f the tile shape tiles[f] ((tile_h, tile_w), or None for the
+        batch tiling's) and re-prepare the workspace."""
+        for f, t in zip(self.frames, tiles):
+            f["tile"] = None if t is None else (int(t[0]), int(t[1]))
+        self._make_frames()
+        self.prepare()
+
+    def tune_frame_tiles(self, shapes=((16, 16), (8, 32), (32, 8), (4, 64)), reps=3):
+        """Tile shape per image-size class: for each class of frames with the same
+        (H, W), in turn, every shape is timed on the whole batch (render +
+        backward, the batch's other settings fixed) and the fastest kept.
+        Returns {(H, W): (tile_h, tile_w)}."""
+        classes = {}
+        for k, f in enumerate(self.frames):
+            classes.setdefault((int(f["sensor"]["height"]), int(f["sensor"]["width"])), []).append(k)
+        cur = [self.frame_tile(k) for k in range(len(self.frames))]
+        arr = (Tiling * 1)(Tiling(*self.tiling))
+        ms = (C.c_double * 1)()
+        best_i = C.c_int32(-1)
+        for cls, members in classes.items():
+            timed = {}
+            for sh in shapes:
+                trial = list(cur)
+                for k in members:
+                    trial[k] = sh
+                self.set_frame_tiles(trial)
+                _check(lib().slr_batch_autotune(len(self.sets), self._c_sets, self._c_grads, len(self.frames),
+                                                self._c_frames, arr, 1, self.capacity, _ptr(self.ws), self.ws.numel(),
+                                                int(reps), ms, C.byref(best_i), _stream()), "slr_batch_autotune")
+                if ms[0] > 0:
+                    timed[sh] = ms[0]
+            best = min(timed, key=timed.get)
+            for k in members:
+                cur[k] = best
+        self.set_frame_tiles(cur)
+        return {cls: cur[members[0]] for cls, members in classes.items()}
 
     def autotune(self, candidates=None, reps=3):
         """Time render + backward of this batch for each candidate tiling (median
@@ -424,10 +472,10 @@ class BatchRenderer:
             nbytes = count * torch.tensor([], dtype=dtype).element_size()
             return self.ws[off:off + nbytes].view(dtype).clone()
 
-        th, tw = int(self.tiling[0]), int(self.tiling[1])
         item_off, tile_off, pix_off = [], [], []
         it = tl = px = 0
-        for f in self.frames:
+        for k, f in enumerate(self.frames):
+            th, tw = self.frame_tile(k)
             H, W = int(f["sensor"]["height"]), int(f["sensor"]["width"])
             item_off.append(it); tile_off.append(tl); pix_off.append(px)
             it += int(self.sets[int(f["set"])]["means"].shape[0])
