@@ -31,7 +31,8 @@ def dev_set(sc):
     return {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in sc.items()}
 
 
-def make_batch(slr, tiling=(16, 16), capacity=4 << 20):
+def make_batch(slr, tiling=(16, 16), capacity=4 << 20, tiles=None):
+    """tiles: per-frame tile shapes (None: the batch tiling's for every frame)."""
     shared, _ = synth.structured_scene(40000, 21)
     own = synth.shell_scene(5000, 22)
     sets = [dev_set(shared), dev_set(own)]
@@ -41,7 +42,7 @@ def make_batch(slr, tiling=(16, 16), capacity=4 << 20):
     for k, (H, W) in enumerate(sizes):
         T = poses[k % 3] if k < 3 else synth.perturbed_pose(5)
         frames.append(dict(set=0 if k < 3 else 1, T_cw=torch.from_numpy(T).to(DEV), T_np=T,
-                           sensor=slr.make_sensor(H, W)))
+                           sensor=slr.make_sensor(H, W), tile=None if tiles is None else tiles[k]))
     return sets, frames, [shared, own], slr.BatchRenderer(sets, frames, tiling, capacity)
 
 
@@ -92,6 +93,82 @@ def test_batched_matches_plain(slr, tiling):
         a, b = br.grads[0][key].cpu().numpy(), sum_g[key].cpu().numpy()
         scale = np.abs(b).max()
         assert np.abs(a - b).max() <= 1e-4 * scale, key
+
+
+MIXED_TILES = [(8, 32), (4, 64), (32, 8), (16, 16)]
+
+
+@pytest.mark.parametrize("bwd", [1, 3])
+def test_batched_mixed_tiles(slr, bwd):
+    """Every frame with its own tile shape in one batch (one compositing launch
+    over tiles of four shapes): each frame's sorted (tile, surfel) lists and
+    tile ranges equal the oracle's binning at that shape, its images equal the
+    plain form's at that shape bit for bit, its pose gradient and the set
+    gradients match the plain form's; the images also match the oracle."""
+    from tests import gpu_checks as GC
+    say("mixed tile shapes, backward form", bwd)
+    sets, frames, host_sets, br = make_batch(slr, (16, 16, 3, 2, bwd), tiles=MIXED_TILES)
+    upstream(br, 3)
+    br.render()
+    br.backward()
+    torch.cuda.synchronize()
+    K, over = br.pairs()
+    assert over == 0 and K > 0
+    v = br.views()
+    st, sid, rg = v["sorted_tile"].cpu().numpy(), v["sorted_id"].cpu().numpy(), v["ranges"].cpu().numpy()
+    sum_g = {k: torch.zeros_like(x) for k, x in br.grads[0].items()}
+    p0 = 0
+    for k, f in enumerate(frames):
+        th, tw = MIXED_TILES[k]
+        assert br.frame_tile(k) == (th, tw)
+        sc = host_sets[f["set"]]
+        ref = O.bin_surfels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], f["T_np"], f["sensor"], th, tw)
+        n, t0, i0 = ref["K"], v["tile_off"][k], v["item_off"][k]
+        nt = ref["ranges"].shape[0]
+        np.testing.assert_array_equal(st[p0:p0 + n] - t0, ref["sorted_tile"])
+        np.testing.assert_array_equal(sid[p0:p0 + n] - i0, ref["sorted_id"])
+        mine = rg[t0:t0 + nt].copy()
+        full = mine[:, 1] > mine[:, 0]
+        mine[full] -= p0
+        np.testing.assert_array_equal(mine, ref["ranges"])
+        p0 += n
+        (D, N, A), g, dp, r = plain_frame(slr, sets[f["set"]], f, (th, tw, 3, 2, bwd), br.up[k])
+        for a, b in zip((D, N, A), br.out[k]):
+            assert torch.equal(a, b), f"frame {k}"
+        np.testing.assert_allclose(br.dpose[k].cpu().numpy(), dp.cpu().numpy(), rtol=1e-6, atol=1e-9)
+        if f["set"] == 0:
+            for key in sum_g:
+                sum_g[key] += g[key]
+        else:   # the same sums up to the order of the float atomics
+            for key in g:
+                a, b = br.grads[1][key].cpu().numpy(), g[key].cpu().numpy()
+                assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max(), key
+        GC.forward_verdict(br.out[k][0].cpu().numpy(), br.out[k][1].cpu().numpy(), br.out[k][2].cpu().numpy(),
+                           sc, f["T_np"], f["sensor"], label=f"mixed-tile frame {k} ({th}x{tw})")
+    assert p0 == K
+    for key in sum_g:
+        a, b = br.grads[0][key].cpu().numpy(), sum_g[key].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max(), key
+
+
+def test_tune_frame_tiles(slr):
+    """The per-class tile tuner gives every frame a supported shape, frames of
+    one image size the same one, and the batch still renders what the plain
+    form renders at those shapes."""
+    say("per-class tile tuning")
+    sets, frames, _, br = make_batch(slr, (16, 16, 3, 2, 1))
+    upstream(br, 4)
+    chosen = br.tune_frame_tiles(reps=1)
+    shapes = {(16, 16), (8, 32), (32, 8), (4, 64)}
+    for k, f in enumerate(frames):
+        hw = (f["sensor"]["height"], f["sensor"]["width"])
+        assert chosen[hw] in shapes and br.frame_tile(k) == chosen[hw]
+    br.render()
+    torch.cuda.synchronize()
+    for k, f in enumerate(frames):
+        (D, N, A), _, _, _ = plain_frame(slr, sets[f["set"]], f, br.frame_tile(k) + (3, 2, 1), br.up[k])
+        for a, b in zip((D, N, A), br.out[k]):
+            assert torch.equal(a, b), f"frame {k}"
 
 
 def test_batched_forward_matches_oracle(slr):
