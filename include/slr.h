@@ -224,6 +224,21 @@ slr_status slr_photo_gn(const slr_sensor *sensor, const float *depth, const floa
                         const double *pose_qm, double huber_k, void *workspace, size_t workspace_bytes,
                         double *normal_eq, void *stream);
 
+/* slr_photo_gn without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight registration loops, harnesses
+ * that forbid allocation): the workgroup rows live in a static device array
+ * of the library (1 MiB per GPU, held until the process ends), so the call
+ * allocates nothing and takes images of at most 1,048,576 pixels (H * W;
+ * larger ones return SLR_E_INVALID and launch nothing).  Same arguments,
+ * output and errors as slr_photo_gn otherwise, and the same result bit for
+ * bit (the same kernels in the same order).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  Nothing in the array needs to
+ * start at zero (each call writes every row it reads). */
+slr_status slr_photo_gn_noalloc(const slr_sensor *sensor, const float *depth, const float *query,
+                                const float *weight, const double *pose_qm, double huber_k, double *normal_eq,
+                                void *stream);
+
 /* Device pointers into a workspace filled by slr_render (for inspection and
  * tests). */
 slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tiling, int64_t n,

@@ -601,6 +601,32 @@ slr_status slr_photo_gn(const slr_sensor *sensor, const float *depth, const floa
     return SLR_OK;
 }
 
+slr_status slr_photo_gn_noalloc(const slr_sensor *sensor, const float *depth, const float *query,
+                                const float *weight, const double *pose_qm, double huber_k, double *normal_eq,
+                                void *stream)
+{
+    slr_status st;
+    if ((st = check_sensor(sensor)) != SLR_OK) return st;
+    if (!depth || !query || !pose_qm || !normal_eq)
+        return fail(SLR_E_INVALID, "depth, query, pose_qm and normal_eq must be set");
+    if (std::isnan(huber_k)) return fail(SLR_E_INVALID, "huber_k is NaN");
+    const int64_t npix = (int64_t)sensor->height * sensor->width;
+    if (npix > slr::photo_static_max_pixels())
+        return fail(SLR_E_INVALID, "image of %lld pixels exceeds the %lld pixels of the static scratch; use "
+                                   "slr_photo_gn with a workspace", (long long)npix,
+                    (long long)slr::photo_static_max_pixels());
+    double *part = nullptr;
+    HIP_TRY(slr::photo_static_scratch(&part));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        StageScope t(9, s);
+        slr::launch_photo_gn(sensor->height, sensor->width, sensor->fu, sensor->cu, sensor->fv, sensor->cv, huber_k,
+                             depth, query, weight, pose_qm, part, normal_eq, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SLR_OK;
+}
+
 slr_status slr_cloud_to_range(const slr_sensor *sensor, int64_t n, const float *points, float *range, void *stream)
 {
     slr_status st;

@@ -19,6 +19,8 @@
 // the rows in a fixed order.
 #include "slr_internal.h"
 
+#include <mutex>
+
 namespace slr {
 namespace {
 
@@ -154,9 +156,40 @@ k_photo_reduce(const double *__restrict__ part, int64_t nparts, double *__restri
     }
 }
 
+// Scratch of the allocation-free entry point: the workgroup rows of
+// k_photo_gn for images of up to kPhotoStaticBlocks * 256 pixels (1 MiB per
+// GPU, held for the life of the process).  Host code never passes this name
+// to a kernel: it is a host-side stand-in for the array; the device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kPhotoStaticBlocks = 4096;
+static __device__ __align__(256) double scratch[kPhotoStaticBlocks * kPhotoRow];
+
 }  // namespace
 
 int64_t photo_blocks(int32_t H, int32_t W) { return ((int64_t)H * W + 255) / 256; }
+
+int64_t photo_static_max_pixels() { return kPhotoStaticBlocks * 256; }
+
+hipError_t photo_static_scratch(double **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        // the current device is `dev`: its copy of the array is looked up
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(a);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 size_t photo_workspace_bytes(int32_t H, int32_t W)
 {

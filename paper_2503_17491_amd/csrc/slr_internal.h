@@ -147,6 +147,10 @@ struct LossPack {
 void launch_loss_frames(int32_t n_frames, const slr_loss_frame *frames, double *loss, hipStream_t stream);
 void launch_fill_u32(void *p, uint32_t v, int64_t count, hipStream_t stream);
 size_t photo_workspace_bytes(int32_t H, int32_t W);
+// Largest image (pixels) of the allocation-free photometric entry point, and
+// the calling device's address of its static scratch (looked up once per device).
+int64_t photo_static_max_pixels();
+hipError_t photo_static_scratch(double **ptr);
 void launch_cloud_to_range(int32_t H, int32_t W, double fu, double cu, double fv, double cv, int64_t n,
                            const float *pts, float *range, hipStream_t stream);
 void launch_range_normals(int32_t H, int32_t W, double fu, double cu, double fv, double cv, const float *range,

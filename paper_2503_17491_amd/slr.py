@@ -66,7 +66,7 @@ EXPORTS = ["slr_camera_matrix", "slr_workspace_size", "slr_render", "slr_backwar
            "slr_batch_workspace_size", "slr_batch_prepare", "slr_batch_render", "slr_batch_backward",
            "slr_batch_counters", "slr_batch_views", "slr_batch_autotune", "slr_loss_l1_normal", "slr_loss_l1_normal_frames", "slr_adam_step",
            "slr_stage_timer_enable", "slr_stage_times",
-           "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
+           "slr_pose_gn", "slr_photo_workspace_size", "slr_photo_gn", "slr_photo_gn_noalloc", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map",
            "slr_scale_reg", "slr_init_workspace_size", "slr_init_splats", "slr_status_string", "slr_last_error"]
 
 _lib = None
@@ -88,6 +88,7 @@ def lib():
         L.slr_pose_gn.argtypes = [P, P, P, P, P, C.c_size_t, I64, P, P, P, D, P, P]
         L.slr_photo_workspace_size.argtypes = [P, P]
         L.slr_photo_gn.argtypes = [P, P, P, P, P, D, P, C.c_size_t, P, P]
+        L.slr_photo_gn_noalloc.argtypes = [P, P, P, P, P, D, P, P]
         L.slr_cloud_to_range.argtypes = [P, I64, P, P, P]
         L.slr_range_normals.argtypes = [P, P, P, P]
         L.slr_loss_map.argtypes = [I64, P, P, P, P, P, C.c_float, C.c_float, C.c_float, P, P, P, P, P]
@@ -115,7 +116,7 @@ def lib():
                   "slr_batch_counters", "slr_batch_views", "slr_batch_autotune", "slr_loss_l1_normal",
                   "slr_loss_l1_normal_frames",
                   "slr_adam_step", "slr_stage_timer_enable", "slr_stage_times", "slr_pose_gn", "slr_photo_workspace_size",
-                  "slr_photo_gn", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg",
+                  "slr_photo_gn", "slr_photo_gn_noalloc", "slr_cloud_to_range", "slr_range_normals", "slr_loss_map", "slr_scale_reg",
                   "slr_init_workspace_size", "slr_init_splats"):
             getattr(L, f).restype = I32
         _lib = L
@@ -623,6 +624,22 @@ def photo_gn(sensor, depth, query, pose_qm, weight=None, huber_k=0.0, ws=None, o
     _check(lib().slr_photo_gn(C.byref(s), _ptr(depth), _ptr(query), _ptr(weight), _ptr(pose_qm), float(huber_k),
                               _ptr(ws), ws.numel(), _ptr(buf), _stream()), "slr_photo_gn")
     return buf[:36].view(6, 6), buf[36:42], buf[42], buf[43]
+
+
+def photo_gn_noalloc(sensor, depth, query, pose_qm, out, weight=None, huber_k=0.0):
+    """slr_photo_gn_noalloc: photo_gn without a workspace (the library's static
+    scratch; images of at most 2^20 pixels; calls that overlap on one GPU race).
+    out: FP64 CUDA tensor of 44 values, overwritten (H [0..35], g, cost, count)."""
+    for name, a in (("depth", depth), ("query", query), ("weight", weight)):
+        if a is not None and (a.dtype != torch.float32 or not a.is_contiguous()):
+            raise ValueError(f"{name} must be contiguous float32")
+    if out.dtype != torch.float64 or out.numel() < 44 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of at least 44 values")
+    _pose(pose_qm)
+    s = _sensor(sensor)
+    _check(lib().slr_photo_gn_noalloc(C.byref(s), _ptr(depth), _ptr(query), _ptr(weight), _ptr(pose_qm),
+                                      float(huber_k), _ptr(out), _stream()), "slr_photo_gn_noalloc")
+    return out[:36].view(6, 6), out[36:42], out[42], out[43]
 
 
 def adam_step(params, grads, m, v, lr, step, betas=(0.9, 0.999), eps=1e-15):

@@ -183,6 +183,24 @@ def test_photo_gn_rejects_bad_arguments_without_gpu():
     assert st == slr.SLR_E_INVALID
 
 
+def test_photo_gn_noalloc_rejects_bad_arguments_without_gpu():
+    """Argument checks of the allocation-free form run before any device call."""
+    L = slr.lib()
+    s = slr._sensor(slr.make_sensor(64, 512))
+    img = np.zeros(64 * 512, np.float32)
+    ip = C.c_void_p(img.ctypes.data)
+    T = np.eye(4)
+    tp = C.c_void_p(T.ctypes.data)
+    out = np.zeros(44)
+    op = C.c_void_p(out.ctypes.data)
+    for d, q, t, o, k in ((None, ip, tp, op, 0.0), (ip, None, tp, op, 0.0), (ip, ip, None, op, 0.0),
+                          (ip, ip, tp, None, 0.0), (ip, ip, tp, op, float("nan"))):
+        assert L.slr_photo_gn_noalloc(C.byref(s), d, q, None, t, k, o, None) == slr.SLR_E_INVALID
+    big = slr._sensor(slr.make_sensor(1024, 1025))   # 1,049,600 pixels: more than the static scratch holds
+    assert L.slr_photo_gn_noalloc(C.byref(big), ip, ip, None, tp, 0.0, op, None) == slr.SLR_E_INVALID
+    assert b"static scratch" in L.slr_last_error()
+
+
 def test_loss_frames_rejects_bad_arguments_without_gpu():
     L = slr.lib()
     buf = np.zeros(3 * 64, np.float32)
