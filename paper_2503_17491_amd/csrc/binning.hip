@@ -471,7 +471,8 @@ __device__ __forceinline__ int order_bucket(int len)
 }
 
 __global__ void __launch_bounds__(1024)
-k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restrict__ order)
+k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restrict__ order,
+             uint32_t *__restrict__ nquad)
 {
     __shared__ uint32_t hist[kOrderBuckets];
     for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
@@ -482,8 +483,20 @@ k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int b = kOrderBuckets - 1; b >= 0; --b) { const uint32_t c = hist[b]; hist[b] = acc; acc += c; }
+        // the tiles whose list reaches kQuadMinList entries fill the first slots of
+        // the order (their buckets come first); the forward's quad mode takes them,
+        // rounded up to whole runs of 8 slots, at most quad_tile_cap
+        uint32_t acc = 0, nl = 0;
+        const int qb = order_bucket(kQuadMinList);
+        for (int b = kOrderBuckets - 1; b >= 0; --b) {
+            const uint32_t c = hist[b];
+            hist[b] = acc;
+            acc += c;
+            if (b == qb) nl = acc;
+        }
+        const uint64_t cap = (uint64_t)quad_tile_cap(tiles);
+        const uint64_t n8 = ((uint64_t)nl + 7) & ~uint64_t(7);
+        *nquad = (uint32_t)(n8 < cap ? n8 : cap);
     }
     __syncthreads();
     for (int64_t t = threadIdx.x; t < tiles; t += blockDim.x) {
@@ -569,7 +582,8 @@ static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.schedule != SLR_SCHEDULE_LONGEST || L.tiles == 0) return;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, reinterpret_cast<const int2 *>(ws + L.ranges),
-                       L.tiles, reinterpret_cast<uint32_t *>(ws + L.order));
+                       L.tiles, reinterpret_cast<uint32_t *>(ws + L.order),
+                       reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQuadTiles));
 }
 
 void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream)

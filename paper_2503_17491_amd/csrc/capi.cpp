@@ -401,7 +401,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
     L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
     // per Gauss-Newton workgroup (one per tile) or strip wave (four per tile): its partial normal equations
-    L.gn_part = take(sizeof(double) * kGnRow * 4 * (size_t)L.tiles);   // up to four strip rows per tile
+    // four strip rows per tile, sixteen for the tiles composited in quad mode
+    L.gn_part = take(sizeof(double) * kGnRow * (4 * (size_t)L.tiles + 12 * (size_t)quad_tile_cap(L.tiles)));
     L.ranges = take(8 * (size_t)L.tiles);
     L.order = take(4 * (size_t)L.tiles);
     L.hist = take(4 * 256 * (size_t)(nb_n > nb_k ? nb_n : nb_k));

@@ -371,17 +371,147 @@ __device__ __forceinline__ bool strip_of_block(int64_t ntiles, int &strip, int &
 // each of them in turn takes the wave and the lanes evaluate their own
 // records for that pixel.  Same arithmetic and order as k_raster_fwd, hence
 // bit-identical results.
+// Quad mode of the one-wave forward, for the longest lists: the wave takes 16
+// pixels of the tile (a sub-strip: pixels 16 sub .. 16 sub + 15 in row-major
+// tile order), four lanes per pixel (lane = 4 pixel + slot).  The chunk's
+// records that meet the sub-strip's rows are compacted as in the strip mode;
+// each step the four lanes of a pixel evaluate four consecutive compacted
+// records for that pixel's ray, and all four blend the four results in list
+// order (the values travel by DPP quad broadcasts).  A strip of a long list is
+// thus walked by four waves at a quarter of the records each, and each walks
+// only the records that meet its fewer rows.  Same evaluation and blending
+// arithmetic in the same order as the strip mode: identical images and state.
+__device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub, const RasterRec *__restrict__ rec,
+                                         const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+                                         const double2 *__restrict__ tables, float *__restrict__ stT_all,
+                                         int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all,
+                                         int64_t total_pixels, RasterRec *sbuf, uint8_t *sidx)
+{
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x, px = lane >> 2, slot = lane & 3;
+    const int q16 = 16 * sub + px;   // pixel index within the tile, row-major
+    const int i = ty * TH + (q16 >> tws), j = tx * TW + (q16 & (TW - 1));
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + ((16 * sub) >> tws), wr1 = ty * TH + ((16 * sub + 15) >> tws);
+    float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
+    int last = 0, n_eval = 0, n_con = 0;
+    bool done = !inside;
+    RasterRec nxt;
+    if (rg.x + lane < rg.y) nxt = rec[pval[rg.x + lane]];
+    for (int c = rg.x; c < rg.y; c += 64) {
+        if (__ballot(!done) == 0) break;
+        const RasterRec r = nxt;   // list entry c + lane
+        const bool inchunk = c + lane < rg.y;
+        if (c + 64 + lane < rg.y) nxt = rec[pval[c + 64 + lane]];
+        bool meets = false;
+        if (inchunk) {
+            const uint32_t rows = r.rows;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (meets) { sbuf[rank] = r; sidx[rank] = (uint8_t)lane; }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = 0; q < nact; q += 4) {
+            if (__ballot(!done) == 0) break;
+            const int k = q + slot;
+            PairEval e;
+            const bool ok = eval_pair_flat(sbuf[min(k, nact - 1)], vx, vy, vz, near_m, e) && k < nact;
+            const uint32_t okq = (uint32_t)(__ballot(ok) >> (lane & ~3)) & 0xfu;
+            const float a4[4] = {dpp_perm<0x00>(e.alpha), dpp_perm<0x55>(e.alpha), dpp_perm<0xAA>(e.alpha),
+                                 dpp_perm<0xFF>(e.alpha)};
+            const float t4[4] = {dpp_perm<0x00>(e.t), dpp_perm<0x55>(e.t), dpp_perm<0xAA>(e.t), dpp_perm<0xFF>(e.t)};
+            const int nu = min(4, nact - q);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u < nu && !done) {
+                    ++n_eval;
+                    if ((okq >> u) & 1u) {
+                        const float tT = T * (1.0f - a4[u]);
+                        if (tT < kTMin) {
+                            done = true;
+                        } else {
+                            const float w = a4[u] * T;
+                            D = fmaf(w, t4[u], D);
+                            N0 = fmaf(w, sbuf[q + u].n[0], N0);
+                            N1 = fmaf(w, sbuf[q + u].n[1], N1);
+                            N2 = fmaf(w, sbuf[q + u].n[2], N2);
+                            O += w;
+                            T = tT;
+                            last = c + sidx[q + u] + 1 - rg.x;
+                            ++n_con;
+                        }
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();   // sbuf is rewritten by the next chunk
+    }
+    if (inside && slot == 0) {
+        const int p = i * W + j;
+        census_all[fd.pix_off + p] = n_eval;
+        census_all[total_pixels + fd.pix_off + p] = n_con;
+        fd.depth[p] = D;
+        fd.alpha[p] = O;
+        fd.normal[3 * p] = N0; fd.normal[3 * p + 1] = N1; fd.normal[3 * p + 2] = N2;
+        stT_all[fd.pix_off + p] = T;
+        stN_all[fd.pix_off + p] = last;
+    }
+}
+
+// Work of a one-wave forward workgroup.  The first 16 * nquad workgroups take
+// the nquad longest tiles (the first slots of the longest-first order) in quad
+// mode, 16 sub-strips each, in runs of 128 = 8 tiles x 16 sub-strips arranged
+// so that a tile's sub-strips share one XCD (see strip_of_block); the rest take
+// one 64-pixel strip of the remaining tiles each.  Returns 0 for padding
+// workgroups, 1 for a strip (strip, tslot), 2 for a sub-strip (sub, tslot).
+__device__ __forceinline__ int fwd_work_of_block(int64_t ntiles, int64_t nquad, int &part, int &tslot)
+{
+    const int64_t b = blockIdx.x;
+    if (b < 16 * nquad) {
+        const int j = (int)(b & 127);
+        part = j >> 3;
+        tslot = (int)(b >> 7) * 8 + (j & 7);
+        return 2;
+    }
+    const int64_t b2 = b - 16 * nquad;
+    const int j = (int)(b2 & 31);
+    part = j >> 3;
+    tslot = (int)nquad + (int)(b2 >> 5) * 8 + (j & 7);
+    return tslot < ntiles ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(64)
 k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
                const uint32_t *__restrict__ order,
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
-               int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles)
+               int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
+               const uint32_t *__restrict__ nquad_dev)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ uint8_t sidx[64];
     int strip, tslot;
-    if (!strip_of_block(ntiles, strip, tslot)) return;
+    const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
+    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    if (kind == 0) return;
+    if (kind == 2) {
+        const int qt = (int)order[tslot];
+        fwd_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all, census_all,
+                 total_pixels, sbuf, sidx);
+        return;
+    }
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
     // the frame's tile shape: TH x TW = 256 pixels, TW a power of two, strips of SR rows
@@ -682,12 +812,10 @@ __device__ __forceinline__ BwdScalars bwd_step(BwdState &st, const PairEval &e, 
     return {da, db, dcs, tt, dop, w};
 }
 
-__device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
-                                         const ChatRec &chr, const BwdUpstream &u, double vx, double vy, double vz,
-                                         float (&g)[18])
+// The 18 partials of a pair from its reverse step's scalars.
+__device__ __forceinline__ void bwd_partials(const BwdScalars &q, const PairEval &e, const double *ch,
+                                             const BwdUpstream &u, double vx, double vy, double vz, float (&g)[18])
 {
-    const BwdScalars q = bwd_step(st, e, n0, n1, n2, u, range_low(e, chr.tau));
-    const double *ch = chr.c;
     const float da = q.da, db = q.db, dcs = q.dcs, tt = q.tt, dop = q.dop, w = q.w;
     const float ex = (float)(vx - ch[0]), ey = (float)(vy - ch[1]), ez = (float)(vz - ch[2]);
     const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
@@ -698,6 +826,14 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
     g[11] = tt * e.sa; g[12] = tt * e.sb; g[13] = tt;
     g[14] = dop;
     g[15] = u.gn0 * w; g[16] = u.gn1 * w; g[17] = u.gn2 * w;
+}
+
+__device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float n0, float n1, float n2,
+                                         const ChatRec &chr, const BwdUpstream &u, double vx, double vy, double vz,
+                                         float (&g)[18])
+{
+    const BwdScalars q = bwd_step(st, e, n0, n1, n2, u, range_low(e, chr.tau));
+    bwd_partials(q, e, chr.c, u, vx, vy, vz, g);
 }
 
 // The splat axes from a record: P, Q, M are the cofactors of (b_alpha b_beta
@@ -1337,28 +1473,243 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
     if (threadIdx.x == kGnVals) row[kGnVals] = (double)tile_frame[tile];
 }
 
+// The pixel's Gauss-Newton terms (m w J J^T, m w r J, m rho(r); Huber in IRLS
+// form) summed over the wave by FP64 butterflies into one partial row.
+__device__ __forceinline__ void gn_row(const FrameDesc &fd, bool take, int p, const float (&J)[6], double *row,
+                                       int lane, int frame)
+{
+    double Jd[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Jd[q] = J[q];
+    double wgt = 0.0, wr = 0.0, cost = 0.0;
+    if (take) {
+        const float mw = fd.gn_weight ? fd.gn_weight[p] : 1.0f;
+        if (mw != 0.0f) {
+            const double r = (double)fd.depth[p] - (double)fd.gn_target[p];
+            const double k = fd.huber_k, a = fabs(r);
+            const bool lin = k > 0.0 && a > k;
+            wgt = (double)mw * (lin ? k / a : 1.0);
+            wr = wgt * r;
+            cost = (double)mw * (lin ? k * (a - 0.5 * k) : 0.5 * r * r);
+        }
+    }
+    int cidx = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+#pragma unroll
+        for (int b = a; b < 6; ++b) {
+            double v = wgt * Jd[a] * Jd[b];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) row[cidx] = v;
+            ++cidx;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        double v = wr * Jd[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) row[21 + a] = v;
+    }
+    {
+        double v = cost;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) row[27] = v;
+    }
+    if (lane == 0) row[kGnVals] = (double)frame;
+}
+
+// The Jacobian row dD/d(rho, phi) of one contributing pair (see k_raster_gn).
+__device__ __forceinline__ void gn_pair_row(const BwdScalars &sc, const RasterRec &r, const float *ab, float t,
+                                            float fvx, float fvy, float fvz, float (&jc)[6])
+{
+    const float ax = ab[0], ay = ab[1], az = ab[2];
+    const float bx = ab[3], by = ab[4], bz = ab[5];
+    const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
+    jc[0] = sc.da * (by * fvz - bz * fvy) + sc.db * (fvy * az - fvz * ay) - sc.tt * Mx;
+    jc[1] = sc.da * (bz * fvx - bx * fvz) + sc.db * (fvz * ax - fvx * az) - sc.tt * My;
+    jc[2] = sc.da * (bx * fvy - by * fvx) + sc.db * (fvx * ay - fvy * ax) - sc.tt * Mz;
+    const float km = sc.dcs - sc.tt * t;
+    const float gx = sc.da * (float)r.P[0] + sc.db * (float)r.Q[0] + km * Mx;
+    const float gy = sc.da * (float)r.P[1] + sc.db * (float)r.Q[1] + km * My;
+    const float gz = sc.da * (float)r.P[2] + sc.db * (float)r.Q[2] + km * Mz;
+    jc[3] = fvy * gz - fvz * gy;
+    jc[4] = fvz * gx - fvx * gz;
+    jc[5] = fvx * gy - fvy * gx;
+}
+
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The evaluations of the four lanes of this lane's quad (every lane active).
+__device__ __forceinline__ void quad_evals(const PairEval &e, int lane, PairEval (&eu)[4])
+{
+    eu[0].sa = dpp_perm<0x00>(e.sa); eu[1].sa = dpp_perm<0x55>(e.sa);
+    eu[2].sa = dpp_perm<0xAA>(e.sa); eu[3].sa = dpp_perm<0xFF>(e.sa);
+    eu[0].sb = dpp_perm<0x00>(e.sb); eu[1].sb = dpp_perm<0x55>(e.sb);
+    eu[2].sb = dpp_perm<0xAA>(e.sb); eu[3].sb = dpp_perm<0xFF>(e.sb);
+    eu[0].t = dpp_perm<0x00>(e.t); eu[1].t = dpp_perm<0x55>(e.t);
+    eu[2].t = dpp_perm<0xAA>(e.t); eu[3].t = dpp_perm<0xFF>(e.t);
+    eu[0].rc = dpp_perm<0x00>(e.rc); eu[1].rc = dpp_perm<0x55>(e.rc);
+    eu[2].rc = dpp_perm<0xAA>(e.rc); eu[3].rc = dpp_perm<0xFF>(e.rc);
+    eu[0].G = dpp_perm<0x00>(e.G); eu[1].G = dpp_perm<0x55>(e.G);
+    eu[2].G = dpp_perm<0xAA>(e.G); eu[3].G = dpp_perm<0xFF>(e.G);
+    eu[0].alpha = dpp_perm<0x00>(e.alpha); eu[1].alpha = dpp_perm<0x55>(e.alpha);
+    eu[2].alpha = dpp_perm<0xAA>(e.alpha); eu[3].alpha = dpp_perm<0xFF>(e.alpha);
+    eu[0].c = dpp_perm_d<0x00>(e.c); eu[1].c = dpp_perm_d<0x55>(e.c);
+    eu[2].c = dpp_perm_d<0xAA>(e.c); eu[3].c = dpp_perm_d<0xFF>(e.c);
+    const uint32_t clq = (uint32_t)(__ballot(e.clamped) >> (lane & ~3)) & 0xfu;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) eu[u].clamped = (clq >> u) & 1u;
+}
+
+// Quad mode of the one-wave Gauss-Newton kernel (the counterpart of fwd_quad):
+// 16 pixels of the tile, four lanes per pixel.  Each step the four lanes of a
+// pixel evaluate four consecutive compacted records (slot 0 the latest in list
+// order); every lane then advances the pixel's reverse state through the four
+// in reverse list order with the broadcast evaluations, keeping its own
+// record's step, forms its own record's Jacobian row, and all four add the
+// four rows in reverse list order.  The same steps and sums in the same order
+// as the strip mode: each pixel's J is identical.
+__device__ __forceinline__ void gn_quad(const FrameDesc &fd, int tile, int sub, const RasterRec *__restrict__ rec,
+                                        const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+                                        const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+                                        const int32_t *__restrict__ stN_all, double *row, int frame,
+                                        RasterRec *sbuf, float (*sab)[6], double *stau, uint8_t *slist)
+{
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x, slot = lane & 3;
+    const int q16 = 16 * sub + (lane >> 2);
+    const int i = ty * TH + (q16 >> tws), j = tx * TW + (q16 & (TW - 1));
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + ((16 * sub) >> tws), wr1 = ty * TH + ((16 * sub + 15) >> tws);
+    const int p = inside ? i * W + j : 0;
+    const float Tfin = inside ? stT[p] : 1.0f;
+    const int last = inside ? stN[p] : 0;
+    int wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+    BwdState st = {Tfin, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    const BwdUpstream up = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, Tfin};   // dL/dD = 1
+    float J[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const int end = rg.x + wlast;
+    for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
+        bool meets = false;
+        if (c + lane < end) {
+            sbuf[lane] = rec[pval[c + lane]];
+            const uint32_t rows = sbuf[lane].rows;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+            double ba[3], bb[3], bc[3];
+            record_axes(sbuf[lane], ba, bb, bc);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                sab[lane][q] = (float)ba[q];
+                sab[lane][3 + q] = (float)bb[q];
+            }
+            stau[lane] = record_tau(sbuf[lane]);
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        if (meets)
+            slist[__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = nact - 1; q >= 0; q -= 4) {
+            const int kq = q - slot;   // this lane's compacted index: slot 0 the latest in list order
+            const int k = slist[kq >= 0 ? kq : 0];
+            PairEval e;
+            const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && kq >= 0 && c + k - rg.x < last;
+            const uint32_t actq = (uint32_t)(__ballot(act) >> (lane & ~3)) & 0xfu;
+            PairEval eu[4];
+            quad_evals(e, lane, eu);
+            BwdScalars mine = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if ((actq >> u) & 1u) {
+                    const int ku = slist[q - u];
+                    const RasterRec &r = sbuf[ku];
+                    const BwdScalars sc = bwd_step(st, eu[u], r.n[0], r.n[1], r.n[2], up, range_low(eu[u], stau[ku]));
+                    if (u == slot) mine = sc;
+                }
+            }
+            float jc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (act) gn_pair_row(mine, sbuf[k], sab[k], e.t, fvx, fvy, fvz, jc);
+            float j4[4][6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                j4[0][a] = dpp_perm<0x00>(jc[a]); j4[1][a] = dpp_perm<0x55>(jc[a]);
+                j4[2][a] = dpp_perm<0xAA>(jc[a]); j4[3][a] = dpp_perm<0xFF>(jc[a]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if ((actq >> u) & 1u) {
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) J[a] += j4[u][a];
+                }
+            }
+        }
+        // every lane is done with this chunk's records before they are replaced
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    gn_row(fd, inside && slot == 0, p, J, row, lane, frame);
+}
+
 // Gauss-Newton terms, one wave per 64-pixel strip (the counterpart of
 // k_raster_gn without its workgroup barrier).  The strip's list is read from
 // its wave's last contributor backwards in chunks of 64 records, one per lane;
 // the records that meet the strip's rows are compacted and every lane runs the
 // reverse step for its pixel over them in reverse order.  A pixel sees the
-// same records in the same order with the same arithmetic as in k_raster_gn
-// (up to the compiler's choice of fused multiply-adds); the wave's sums are
-// written to row 4 tile slot + strip, and k_gn_reduce adds a tile's four
-// strip rows in the order k_raster_gn adds its four waves.
+// same records in the same order with the same arithmetic as in k_raster_gn;
+// the wave's sums go to a row of their own.  The tiles the forward took in
+// quad mode are taken in quad mode here too (gn_quad), 16 rows each; rows
+// 16 nquad + 4 (slot - nquad) + strip hold the other tiles' strips, and
+// k_gn_reduce adds a tile's rows in a fixed order.
 __global__ void __launch_bounds__(64)
 k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
               const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
               const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
               const double2 *__restrict__ tables, const float *__restrict__ stT_all,
-              const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, int64_t ntiles)
+              const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, int64_t ntiles,
+              const uint32_t *__restrict__ nquad_dev)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ float sab[64][6];   // b_alpha, b_beta in FP32
     __shared__ double stau[64];    // tau in FP64
     __shared__ uint8_t slist[64];
     int strip, tslot;
-    if (!strip_of_block(ntiles, strip, tslot)) return;
+    const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
+    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    if (kind == 0) return;
+    if (kind == 2) {   // 16 rows per quad tile, in sub-strip order
+        const int qt = (int)order[tslot];
+        gn_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all,
+                gn_part + (size_t)kGnRow * (16 * (size_t)tslot + strip), tile_frame[qt], sbuf, sab, stau, slist);
+        return;
+    }
     const int tile = order ? (int)order[tslot] : tslot;
     const FrameDesc &fd = descs[tile_frame[tile]];
     // the frame's tile shape: TH x TW = 256 pixels, TW a power of two, strips of SR rows
@@ -1420,19 +1771,10 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
             if (act) {
                 const RasterRec &r = sbuf[k];
                 const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up, range_low(e, stau[k]));
-                const float ax = sab[k][0], ay = sab[k][1], az = sab[k][2];
-                const float bx = sab[k][3], by = sab[k][4], bz = sab[k][5];
-                const float Mx = (float)r.M[0], My = (float)r.M[1], Mz = (float)r.M[2];
-                J[0] += sc.da * (by * fvz - bz * fvy) + sc.db * (fvy * az - fvz * ay) - sc.tt * Mx;
-                J[1] += sc.da * (bz * fvx - bx * fvz) + sc.db * (fvz * ax - fvx * az) - sc.tt * My;
-                J[2] += sc.da * (bx * fvy - by * fvx) + sc.db * (fvx * ay - fvy * ax) - sc.tt * Mz;
-                const float km = sc.dcs - sc.tt * e.t;
-                const float gx = sc.da * (float)r.P[0] + sc.db * (float)r.Q[0] + km * Mx;
-                const float gy = sc.da * (float)r.P[1] + sc.db * (float)r.Q[1] + km * My;
-                const float gz = sc.da * (float)r.P[2] + sc.db * (float)r.Q[2] + km * Mz;
-                J[3] += fvy * gz - fvz * gy;
-                J[4] += fvz * gx - fvx * gz;
-                J[5] += fvx * gy - fvy * gx;
+                float jc[6];
+                gn_pair_row(sc, r, sab[k], e.t, fvx, fvy, fvz, jc);
+#pragma unroll
+                for (int a = 0; a < 6; ++a) J[a] += jc[a];
             }
         }
         // every lane is done with this chunk's records before they are replaced
@@ -1440,65 +1782,29 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-
-    // this pixel's terms and the wave's sums (FP64 butterflies), as in k_raster_gn
-    double Jd[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) Jd[q] = J[q];
-    double wgt = 0.0, wr = 0.0, cost = 0.0;
-    if (inside) {
-        const float mw = fd.gn_weight ? fd.gn_weight[p] : 1.0f;
-        if (mw != 0.0f) {
-            const double r = (double)fd.depth[p] - (double)fd.gn_target[p];
-            const double k = fd.huber_k, a = fabs(r);
-            const bool lin = k > 0.0 && a > k;
-            wgt = (double)mw * (lin ? k / a : 1.0);
-            wr = wgt * r;
-            cost = (double)mw * (lin ? k * (a - 0.5 * k) : 0.5 * r * r);
-        }
-    }
-    double *row = gn_part + (size_t)kGnRow * (4 * (size_t)tslot + strip);
-    int cidx = 0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-#pragma unroll
-        for (int b = a; b < 6; ++b) {
-            double v = wgt * Jd[a] * Jd[b];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) row[cidx] = v;
-            ++cidx;
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        double v = wr * Jd[a];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) row[21 + a] = v;
-    }
-    {
-        double v = cost;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) row[27] = v;
-    }
-    if (lane == 0) row[kGnVals] = (double)tile_frame[tile];
+    // this pixel's terms and the wave's sums (FP64 butterflies), as in k_raster_gn;
+    // the strip rows follow the quad tiles' 16 rows each
+    gn_row(fd, inside, p, J, gn_part + (size_t)kGnRow * (16 * (size_t)nquad + 4 * (size_t)(tslot - nquad) + strip), lane,
+           tile_frame[tile]);
 }
+
 
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
     if (wave) {
-        hipLaunchKernelGGL(k_raster_fwd_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        const bool longest = L.schedule == SLR_SCHEDULE_LONGEST;
+        const int64_t grid = wave_blocks(L.tiles) + (longest ? 16 * quad_tile_cap(L.tiles) : 0);
+        hipLaunchKernelGGL(k_raster_fwd_w, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame),
-                           L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
+                           longest ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                            reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
-                           reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles);
+                           reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles,
+                           longest ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
         return;
     }
     hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s : k_raster_fwd,
@@ -1541,13 +1847,15 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (L.bwd_variant == SLR_VARIANT_WAVE) {
-        hipLaunchKernelGGL(k_raster_gn_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        const int64_t grid = wave_blocks(L.tiles) + (ord ? 16 * quad_tile_cap(L.tiles) : 0);
+        hipLaunchKernelGGL(k_raster_gn_w, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
                            reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
-                           reinterpret_cast<double *>(ws + L.gn_part), L.tiles);
+                           reinterpret_cast<double *>(ws + L.gn_part), L.tiles,
+                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
         return;
     }
     hipLaunchKernelGGL(k_raster_gn, dim3((unsigned)L.tiles), dim3(256), 0, stream,

@@ -91,6 +91,26 @@ constexpr int kMaxDigitBits = 8;
 // runs of 8 (see strip_of_block).
 inline int64_t wave_blocks(int64_t tiles) { return 32 * ((tiles + 7) / 8); }
 
+// Quad mode of the one-wave forward and Gauss-Newton kernels: the longest
+// tiles whose list has at least kQuadMinList entries (at most quad_tile_cap of
+// them, a multiple of 8) are composited as 16 sub-strips of 16 pixels, four
+// records per step.  It shortens the longest strips about twofold at about
+// 1.6 times their work, which pays while the chip has room: the cap keeps the
+// launch within kQuadBudget workgroups (twice the 4096 waves the chip holds at
+// four waves per SIMD), so a single 128x1024 frame (512 tiles) may take every
+// long tile in quad mode, a 128x2048 frame (1024 tiles) about a third of them
+// and a batch of eight 128x1024 frames none.  The count is decided on the
+// device after binning (a u32 at misc + kMiscQuadTiles).
+constexpr int kQuadMinList = 1536;   // a boundary of the half-octave length buckets of the tile order
+constexpr int64_t kQuadBudget = 8192;
+constexpr size_t kMiscQuadTiles = 32;
+__host__ __device__ inline int64_t quad_tile_cap(int64_t tiles)
+{
+    const int64_t by_budget = (kQuadBudget - 4 * tiles) / 12;
+    const int64_t c = tiles < by_budget ? tiles : by_budget;
+    return c > 0 ? (c & ~int64_t(7)) : 0;
+}
+
 // Compositing variant and tile schedule used when the caller asks for the default.
 constexpr int kDefaultVariant = SLR_VARIANT_WAVE;
 constexpr int kDefaultSchedule = SLR_SCHEDULE_LONGEST;

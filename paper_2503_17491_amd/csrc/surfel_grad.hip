@@ -43,7 +43,8 @@ k_pose_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ pa
 // and the keyframe index) in a fixed order, written out as H (6x6, both
 // triangles), g (6) and the cost.  Frames without an output pointer are skipped.
 __global__ void __launch_bounds__(128)
-k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts, int strips)
+k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part, int64_t nparts, int strips,
+            const uint32_t *__restrict__ nquad_dev)
 {
     __shared__ double red[kGnVals][128];
     const int f = blockIdx.x;
@@ -53,14 +54,32 @@ k_gn_reduce(const FrameDesc *__restrict__ descs, const double *__restrict__ part
 #pragma unroll
     for (int c = 0; c < kGnVals; ++c) v[c] = 0.0;
     // one row per tile slot, or (strips = 4) four strip rows per tile slot,
-    // added in strip order first
+    // added in strip order first; with strips = 4 the first nquad slots (the
+    // tiles composited in quad mode) have 16 sub-strip rows each, added in
+    // groups of four
+    const int64_t nquad = (strips == 4 && nquad_dev) ? (int64_t)*nquad_dev : 0;
     for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
-        const double *pp = part + (size_t)kGnRow * strips * b;
-        if ((int)pp[kGnVals] != f) continue;
         if (strips == 1) {
+            const double *pp = part + (size_t)kGnRow * b;
+            if ((int)pp[kGnVals] != f) continue;
 #pragma unroll
             for (int c = 0; c < kGnVals; ++c) v[c] += pp[c];
+        } else if (b < nquad) {
+            const double *pp = part + (size_t)kGnRow * 16 * b;
+            if ((int)pp[kGnVals] != f) continue;
+#pragma unroll
+            for (int c = 0; c < kGnVals; ++c) {
+                double s4 = 0.0;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const double *pg = pp + (size_t)kGnRow * 4 * g;
+                    s4 += ((pg[c] + pg[kGnRow + c]) + pg[2 * kGnRow + c]) + pg[3 * kGnRow + c];
+                }
+                v[c] += s4;
+            }
         } else {
+            const double *pp = part + (size_t)kGnRow * (16 * nquad + 4 * (b - nquad));
+            if ((int)pp[kGnVals] != f) continue;
 #pragma unroll
             for (int c = 0; c < kGnVals; ++c)
                 v[c] += ((pp[c] + pp[kGnRow + c]) + pp[2 * kGnRow + c]) + pp[3 * kGnRow + c];
@@ -170,7 +189,9 @@ void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream)
     if (L.frames == 0) return;
     hipLaunchKernelGGL(k_gn_reduce, dim3((unsigned)L.frames), dim3(128), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.gn_part),
-                       L.tiles, L.bwd_variant == SLR_VARIANT_WAVE ? 4 : 1);
+                       L.tiles, L.bwd_variant == SLR_VARIANT_WAVE ? 4 : 1,
+                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles)
+                                                          : nullptr);
 }
 
 void launch_surfel_grad(const float *quats, const float *lsc, const float *logits, int64_t n, const float *acc,

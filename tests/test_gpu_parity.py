@@ -154,22 +154,32 @@ def test_forward_identical_across_tilings_and_runs(slr):
 
 
 def test_forward_state_identical_across_variants(slr):
-    """Same tiling, the two compositing kernels (records from LDS, with the
-    few-pixels-left mode, or through the scalar cache): identical per-pixel
-    state and work census, not only identical images."""
+    """Same tiling, the compositing kernels (records staged in LDS by the
+    workgroup, with the few-pixels-left mode; through the scalar cache; one
+    wave per strip, whose longest tiles take the quad mode): identical
+    per-pixel state and contribution counts, not only identical images.  The
+    evaluated-entry count is the same where both walk the same rows; the quad
+    mode walks only the records that meet its sub-strip's rows, never more."""
     say("forward variants: per-pixel state and census")
-    sensor = slr.make_sensor(64, 512)
-    for sc in (synth.shell_scene(4000, 2), synth.structured_scene(30000, 3)[0]):
-        for group in ([(16, 16, 1), (16, 16, 2), (16, 16, 3)], [(8, 32, 1), (8, 32, 3)]):
+    cases = [(synth.shell_scene(4000, 2), (64, 512), np.eye(4)),
+             (synth.structured_scene(30000, 3)[0], (64, 512), np.eye(4)),
+             # lists of several thousand entries: the quad mode takes the longest tiles
+             (synth.structured_scene(300000, 3)[0], (128, 1024), synth.circle_poses(8, 0)[1])]
+    for sc, hw, T in cases:
+        sensor = slr.make_sensor(*hw)
+        for group in ([(16, 16, 1), (16, 16, 2), (16, 16, 3)], [(8, 32, 1), (8, 32, 3)], [(32, 8, 1), (32, 8, 3)]):
             views = []
             for tiling in group:
-                r, _, _, D, N, A = gpu_render(slr, sc, np.eye(4), sensor, tiling, 1 << 20)
+                r, _, _, D, N, A = gpu_render(slr, sc, T, sensor, tiling, 1 << 22)
                 v = r.views()
                 views.append((D, N, A, v["T_final"].cpu().numpy(), v["n_proc"].cpu().numpy(),
-                              v["census"][:2].cpu().numpy()))
+                              v["census"][1].cpu().numpy(), v["census"][0].cpu().numpy()))
             for other in views[1:]:
-                for a, b in zip(views[0], other):
+                for a, b in zip(views[0][:6], other[:6]):
                     np.testing.assert_array_equal(a, b)
+                assert (other[6] <= views[0][6]).all()
+            say(f"   {hw} {group[0][:2]}: evaluated entries {int(views[0][6].sum())} (workgroup form), "
+                f"{int(views[-1][6].sum())} (one wave per strip)")
 
 
 def test_forward_parity_fullsize_sampled(slr):
