@@ -36,6 +36,13 @@ BWD_CONTRIB_FLOPS = 70   # recompute alpha, transmittance recovery, dL/dalpha, 1
 GN_CONTRIB_FLOPS = 96    # recompute alpha, reverse step with a unit range gradient, 6-vector Jacobian update
 PEAK_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), unpacked FP32 / FP64
 PEAK_HBM_GBS = 8000.0
+TUNE_MARGIN = 0.01       # autotune times closer than this are a tie (run-to-run spread is about 1 %)
+# Algorithmic HBM bytes of the compositing launches: per (tile, surfel) pair the
+# 4-B id and the 64-B compositing record are gathered (+52 B of gradient
+# accumulation in the backward); per pixel the forward writes 20 B of outputs
+# and 8 B of state, the backward reads 20 B of upstream gradients and 8 B of state.
+FWD_PAIR_BYTES, FWD_PIXEL_BYTES = 68, 28
+BWD_PAIR_BYTES, BWD_PIXEL_BYTES = 120, 28
 
 
 def log(*a):
@@ -111,6 +118,56 @@ def counted_traffic(kernel, tiling):
     if fields.get("tiling") != tiling:
         return None
     return int(float(fields["traffic bytes per launch"]))
+
+
+def profiled_tiling(kernel):
+    """Tiling label of the committed counter summary of `kernel`, if it was
+    taken on the current compositing source, else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_8x128x1024_1M.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(os.path.join(ROOT, "paper_2503_17491_amd", "csrc", "raster.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return fields.get("tiling") if fields.get("raster.hip sha256") == sha else None
+
+
+def tiling_label(th, tw, var, bvar, bbatch):
+    vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
+    return f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}" + (
+        f" batch {bbatch}" if bvar == 1 and bbatch not in (0, 192) else "")
+
+
+def roofline(kernel, flops, nbytes, ms, traffic):
+    """Roofline of one compositing launch from its algorithmic work: the bound
+    is the one the arithmetic intensity (FLOP per algorithmic byte) puts it
+    under, against the ridge PEAK_TFLOPS / PEAK_HBM_GBS = 9.8 FLOP/B; both
+    fractions are reported.  traffic: counted HBM bytes per launch or None."""
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    tfs = flops / (ms * 1e-3) / 1e12
+    intensity = flops / max(nbytes, 1)
+    ridge = PEAK_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfs / PEAK_TFLOPS, 4)}
+    roof.update({"traffic": traffic, "kernel": kernel, "avg_launch_ms": round(ms, 4),
+                 "algorithmic_bytes_per_launch": int(nbytes), "flops_per_launch": int(flops),
+                 "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 2),
+                 "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                 "alu_tflops": round(tfs, 3), "alu_frac": round(tfs / PEAK_TFLOPS, 4)})
+    if traffic is not None:   # the counted bytes over the same launch time
+        roof["counted_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+        roof["counted_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    return roof
 
 
 def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
@@ -226,7 +283,8 @@ def measure_mapping(torch, slr, sensor, kf, d, steps):
 
 
 def cpu_baseline(sc, sensor, kfs, budget_s):
-    """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0."""
+    """The FP64 oracle on a bounded sample: fwd+bwd of random pixels of keyframe 0,
+    in the angular-cull mode (identical results to the brute force, faster)."""
     import numpy as np
 
     import oracle as O
@@ -238,24 +296,26 @@ def cpu_baseline(sc, sensor, kfs, budget_s):
     def run(P):
         pix = np.stack([g.integers(0, H, P), g.integers(0, W, P)], 1).astype(np.int32)
         t = time.perf_counter()
-        r = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix)
+        r = O.render_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix, cull=True)
         valid = Dt[pix[:, 0], pix[:, 1]] > 0
         gD = np.where(valid, np.sign(r["depth"] - Dt[pix[:, 0], pix[:, 1]]), 0.0)
-        O.backward_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix, gD, None, None)
+        O.backward_pixels(sc["means"], sc["quats"], sc["log_scales"], sc["logits"], T, sensor, pix, gD, None, None,
+                          cull=True)
         return time.perf_counter() - t
 
     # grow the sample until it takes about budget_s (at most three tries)
     P, t1 = 4 * threads, 0.0
-    for _ in range(3):
+    for k in range(3):
         t1 = run(P)
-        if t1 >= 0.6 * budget_s:
+        if t1 >= 0.6 * budget_s or P >= H * W * N_KF or k == 2:
             break
-        P = max(P + 1, int(P * budget_s / max(t1, 1e-3)))
+        P = min(H * W * N_KF, max(P + 1, int(P * budget_s / max(t1, 1e-3))))
     per_pixel = t1 / P
     s_per_iter = per_pixel * H * W * N_KF
     return {"value": 1.0 / s_per_iter, "unit": "iter/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle fwd+bwd of {P} random pixels of keyframe 0 (brute force over {N_SURFELS} "
-                      f"surfels) in {t1:.1f}s, scaled to {N_KF}x{H}x{W} pixels per iteration"}
+            "sample": f"FP64 oracle fwd+bwd of {P} random pixels of keyframe 0 (every pixel ray against the "
+                      f"{N_SURFELS} surfels, in its result-identical angular-cull mode; each call builds its cull "
+                      f"index) in {t1:.1f}s, scaled to {N_KF}x{H}x{W} pixels per iteration"}
 
 
 def main():
@@ -286,12 +346,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--bwd-batch", type=int, choices=[0, 128, 192], default=0,
                     help="records per LDS batch of the workgroup backward (0: library default)")
+    ap.add_argument("--config", choices=["headline", "fwd-2k", "map-200k", "odometry-300k", "batch-uneven", "map-2m-adam", "n-sweep"], default="headline",
+                    help="workload: the headline (default) or one of the other configurations (bench_configs.py)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: sharding keyframes over several GPUs (with an all-reduce of the "
               "surfel gradients) is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.config != "headline":
+        import bench_configs
+        bench_configs.run(args.config, args)
+        return
 
     import torch
 
@@ -324,6 +390,22 @@ def main():
             for t in u:
                 t.fill_(1.0)
         tune_ms = br.autotune(reps=5)
+        for u in br.up:   # the step's upstream gradients come from the loss; the opacity channel has none
+            for t in u:
+                t.zero_()
+        # candidates within TUNE_MARGIN of the fastest are a tie within timing
+        # noise: among them the one whose HBM counters are committed is taken,
+        # so that the line can carry the counted traffic of the launch it times
+        prof = profiled_tiling("raster_bwd")
+        best_ms = min(v for v in tune_ms.values() if v > 0)
+        for c, v in tune_ms.items():
+            if prof and 0 < v <= best_ms * (1 + TUNE_MARGIN) and \
+                    tiling_label(c[0], c[1], c[2], c[4], c[6] if len(c) > 6 else 0) == prof:
+                if tuple(c) != tuple(br.tiling):
+                    log(f"autotune: {c} is within {TUNE_MARGIN:.0%} of the fastest and has committed counters")
+                    br.tiling = tuple(c)
+                    br.prepare()
+                break
         th, tw, var, sch, bvar, box = br.tiling[:6]
         bbatch = br.tiling[6] if len(br.tiling) > 6 else 0
         log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}" + (f"/{c[6]}" if len(c) > 6 else ""):
@@ -436,21 +518,16 @@ def main():
     bwd_ms = stages["raster_bwd"][0] / max(stages["raster_bwd"][1], 1)
     fwd_flops = FWD_EVAL_FLOPS * ef + FWD_CONTRIB_FLOPS * cf   # one batched launch covers all keyframes
     bwd_flops = BWD_EVAL_FLOPS * eb + BWD_CONTRIB_FLOPS * cb
+    px = N_KF * H * W
+    fwd_bytes = FWD_PAIR_BYTES * pairs + FWD_PIXEL_BYTES * px
+    bwd_bytes = BWD_PAIR_BYTES * pairs + BWD_PIXEL_BYTES * px
     if bwd_ms >= fwd_ms:
-        dom, flops, ms = "raster_bwd", bwd_flops, bwd_ms
+        dom, flops, nbytes, ms = "raster_bwd", bwd_flops, bwd_bytes, bwd_ms
     else:
-        dom, flops, ms = "raster_fwd", fwd_flops, fwd_ms
-    achieved = flops / (ms * 1e-3) / 1e12
-    vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
-    tiling_name = f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}" + (
-        f" batch {bbatch}" if bvar == slr.VARIANT_LDS and bbatch not in (0, 192) else "")
+        dom, flops, nbytes, ms = "raster_fwd", fwd_flops, fwd_bytes, fwd_ms
+    tiling_name = tiling_label(th, tw, var, bvar, bbatch)
     traffic = counted_traffic(dom, tiling_name)
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": traffic,
-            "avg_launch_ms": round(ms, 4), "flops_per_launch": int(flops)}
-    if traffic is not None:   # the same launch against the HBM roofline (8 TB/s)
-        roof["hbm_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
-        roof["hbm_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    roof = roofline(dom, flops, nbytes, ms, traffic)
     stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
     if args.form == "plain" and plain_iters is None:
         raise SystemExit("--form plain needs --only both")
