@@ -462,7 +462,7 @@ def main():
         rend = [slr.Renderer(sensor, tiling, capacity=4 << 20) for _ in kfs]
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
         torch.cuda.synchronize()
-    for r in rend:  # compositing work census (identical in both forms)
+    for r in rend:  # per-keyframe work census (the backward's equals the batched form's)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
         ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
         census0 = c if census0 is None else census0
@@ -501,6 +501,9 @@ def main():
     batched_iters = args.steps / batched_dt
     K, over = br.pairs()
     assert over == 0
+    # the batched launches' own census (a single keyframe may take the forward's
+    # quad mode, which walks fewer entries; the batch does not)
+    ef, cf, eb, cb = br.views()["census"].to(torch.int64).sum(dim=1).tolist()
     # per-kernel durations: HIP events on the launch stream around each stage of
     # the same batched step, run eagerly right after the timed loop (warm GPU)
     nst = max(3, args.steps // 2)

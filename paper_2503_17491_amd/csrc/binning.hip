@@ -580,7 +580,7 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
 
 static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)
 {
-    if (L.schedule != SLR_SCHEDULE_LONGEST || L.tiles == 0) return;
+    if (!longest_order(L) || L.tiles == 0) return;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, reinterpret_cast<const int2 *>(ws + L.ranges),
                        L.tiles, reinterpret_cast<uint32_t *>(ws + L.order),
                        reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQuadTiles));

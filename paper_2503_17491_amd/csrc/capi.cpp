@@ -92,7 +92,7 @@ slr_status check_tiling(const slr_tiling *t)
         return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
     if (t->bwd_batch != 0 && t->bwd_batch != 128 && t->bwd_batch != 192)
         return fail(SLR_E_INVALID, "unsupported backward batch %d (0, 128 or 192)", t->bwd_batch);
-    if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_LONGEST)
+    if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_QUEUE)
         return fail(SLR_E_INVALID, "unknown tile schedule %d", t->schedule);
     if (t->box < SLR_BOX_EXACT || t->box > SLR_BOX_VERTEX) return fail(SLR_E_INVALID, "unknown box mode %d", t->box);
     return SLR_OK;

@@ -937,7 +937,11 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
 }
 
 
-template <int BATCH>
+// QUEUE: the persistent form.  An occupancy-sized grid whose workgroups take
+// the tiles' slots of the longest-first order from a device counter (zeroed
+// before the launch) until the order is exhausted; otherwise workgroup b takes
+// slot b.  Either way slot k writes pose row k, so the results are the same.
+template <int BATCH, bool QUEUE>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -945,7 +949,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-             double *__restrict__ pose_part, int pose_only)
+             double *__restrict__ pose_part, int pose_only, uint32_t *__restrict__ queue, int ntiles)
 {
     __shared__ RasterRec srec[BATCH];
     __shared__ ChatRec schat[BATCH];
@@ -955,146 +959,161 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     __shared__ int s_last;
     __shared__ double s_pose[4][6];
 
-    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    const FrameDesc &fd = descs[tile_frame[tile]];
-    // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
-    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
-    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
-    const float near_m = (float)fd.near_m;
-    const double2 *col = tables + fd.tab_off, *rowc = col + W;
-    const float *stT = stT_all + fd.pix_off;
-    const int32_t *stN = stN_all + fd.pix_off;
-    int32_t *census = census_all + fd.pix_off;
-    const float *gD = fd.gD, *gN = fd.gN, *gO = fd.gO;
-    const double *pose = fd.pose;
-    float *acc = fd.acc;
-    const int ltile = tile - fd.tile_off;
-    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
-    const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
-    const int i = ty * TH + ly, j = tx * TW + lx;
-    const bool inside = (i < H) && (j < W);
-    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
-    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
-    const int2 rg = ranges[tile];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int red_val = bitrev6(lane);  // the wave sum this lane holds after wave_sum18
-    const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
-    const int p = inside ? i * W + j : 0;
-    float T = inside ? stT[p] : 1.0f;
-    const int last = inside ? stN[p] : 0;
-    const float Tfin = T;
-    const float gd = (inside && gD) ? gD[p] : 0.0f;
-    const float go = (inside && gO) ? gO[p] : 0.0f;
-    const float gn0 = (inside && gN) ? gN[3 * p] : 0.0f;
-    const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
-    const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
-    if (threadIdx.x == 0) s_last = 0;
-    for (int e = threadIdx.x; e < kNg * BATCH; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
-    for (int e = threadIdx.x; e < BATCH; e += blockDim.x) sflag[e] = 0;
-    __syncthreads();
-    if (last > 0) atomicMax(&s_last, last);
-    __syncthreads();
-    const int end = rg.x + s_last;
-    int wlast = last;  // the wave's largest contributor count
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
-
-    double pacc[6] = {0, 0, 0, 0, 0, 0};
-    // dL/dalpha_k = c_k A_k - B_k / (1 - alpha_k) + K T_final / (1 - alpha_k), with
-    // c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
-    // and K = gD t_ref + gN . n_ref + gO: the reference (the last contributor, met
-    // first in reverse) removes the cancellation of the unshifted form.
-    BwdState st = {T, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
-    const BwdUpstream up = {gd, go, gn0, gn1, gn2, Tfin};
-    int n_eval = 0, n_con = 0;
-
-    for (int b_end = end; b_end > rg.x; b_end -= BATCH) {
-        const int b0 = max(rg.x, b_end - BATCH);
-        const int cnt = b_end - b0;
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const uint32_t id = pval[b0 + threadIdx.x];
-            srec[threadIdx.x] = rec[id];
-            centre_dir(srec[threadIdx.x], schat[threadIdx.x]);
+    __shared__ int s_item;
+    for (int pass = 0;; ++pass) {
+        int item = (int)blockIdx.x;
+        if (QUEUE) {
+            __syncthreads();   // every thread has read the previous slot
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+            __syncthreads();
+            item = s_item;
+            if (item >= ntiles) break;
+        } else if (pass > 0) {
+            break;
         }
+        const int tile = order ? (int)order[item] : item;
+        const FrameDesc &fd = descs[tile_frame[tile]];
+        // the frame's tile shape: TH x TW = 256 pixels, TW a power of two
+        const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
+        const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+        const float near_m = (float)fd.near_m;
+        const double2 *col = tables + fd.tab_off, *rowc = col + W;
+        const float *stT = stT_all + fd.pix_off;
+        const int32_t *stN = stN_all + fd.pix_off;
+        int32_t *census = census_all + fd.pix_off;
+        const float *gD = fd.gD, *gN = fd.gN, *gO = fd.gO;
+        const double *pose = fd.pose;
+        float *acc = fd.acc;
+        const int ltile = tile - fd.tile_off;
+        const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+        const int lx = threadIdx.x & (TW - 1), ly = threadIdx.x >> tws;
+        const int i = ty * TH + ly, j = tx * TW + lx;
+        const bool inside = (i < H) && (j < W);
+        const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+        const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+        const int2 rg = ranges[tile];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        const int red_val = bitrev6(lane);  // the wave sum this lane holds after wave_sum18
+        const int wr0 = ty * TH + ((wid * 64) >> tws), wr1 = ty * TH + ((wid * 64 + 63) >> tws);
+        const int p = inside ? i * W + j : 0;
+        float T = inside ? stT[p] : 1.0f;
+        const int last = inside ? stN[p] : 0;
+        const float Tfin = T;
+        const float gd = (inside && gD) ? gD[p] : 0.0f;
+        const float go = (inside && gO) ? gO[p] : 0.0f;
+        const float gn0 = (inside && gN) ? gN[3 * p] : 0.0f;
+        const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
+        const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
+        if (threadIdx.x == 0) s_last = 0;
+        for (int e = threadIdx.x; e < kNg * BATCH; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
+        for (int e = threadIdx.x; e < BATCH; e += blockDim.x) sflag[e] = 0;
+        if (threadIdx.x < 24) (&s_pose[0][0])[threadIdx.x] = 0.0;
         __syncthreads();
-        // the batch's records that meet this wave's rows and lie before its last
-        // contributor, in list order; they are walked in reverse
-        int nact = 0;
-        for (int base = 0; base < cnt; base += 64) {
-            const int kk = base + lane;
-            bool meets = false;
-            if (kk < cnt) {
-                const uint32_t rows = srec[kk].rows;
-                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
+        if (last > 0) atomicMax(&s_last, last);
+        __syncthreads();
+        const int end = rg.x + s_last;
+        int wlast = last;  // the wave's largest contributor count
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+
+        // dL/dalpha_k = c_k A_k - B_k / (1 - alpha_k) + K T_final / (1 - alpha_k), with
+        // c_k = gD (t_k - t_ref) + gN . (n_k - n_ref), B_k the suffix sum of c_i alpha_i A_i
+        // and K = gD t_ref + gN . n_ref + gO: the reference (the last contributor, met
+        // first in reverse) removes the cancellation of the unshifted form.
+        BwdState st = {T, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+        const BwdUpstream up = {gd, go, gn0, gn1, gn2, Tfin};
+        int n_eval = 0, n_con = 0;
+
+        for (int b_end = end; b_end > rg.x; b_end -= BATCH) {
+            const int b0 = max(rg.x, b_end - BATCH);
+            const int cnt = b_end - b0;
+            __syncthreads();
+            if ((int)threadIdx.x < cnt) {
+                const uint32_t id = pval[b0 + threadIdx.x];
+                srec[threadIdx.x] = rec[id];
+                centre_dir(srec[threadIdx.x], schat[threadIdx.x]);
             }
-            const uint64_t m = __ballot(meets);
-            if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)kk;
-            nact += __popcll(m);
-        }
-        __syncthreads();
-        for (int q = nact - 1; q >= 0; --q) {
-            const int k = slist[wid][q];
-            const int pos = b0 + k - rg.x;
-            PairEval e;
-            n_eval += pos < last ? 1 : 0;
-            const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
-            // about half of the walked entries meet no lane: they skip the partials
-            if (__any(act)) {
-                float g[kNg];
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
-                if (act) {
-                    ++n_con;
-                    bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k], up, vx, vy, vz, g);
+            __syncthreads();
+            // the batch's records that meet this wave's rows and lie before its last
+            // contributor, in list order; they are walked in reverse
+            int nact = 0;
+            for (int base = 0; base < cnt; base += 64) {
+                const int kk = base + lane;
+                bool meets = false;
+                if (kk < cnt) {
+                    const uint32_t rows = srec[kk].rows;
+                    meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
                 }
-                static_assert(kNg == 18, "wave_sum18 reduces 18 values");
-                const float tot = wave_sum18(g, lane);
-                if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
-                if (lane == 0) sflag[k] = 1;
+                const uint64_t m = __ballot(meets);
+                if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)kk;
+                nact += __popcll(m);
+            }
+            __syncthreads();
+            for (int q = nact - 1; q >= 0; --q) {
+                const int k = slist[wid][q];
+                const int pos = b0 + k - rg.x;
+                PairEval e;
+                n_eval += pos < last ? 1 : 0;
+                const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
+                // about half of the walked entries meet no lane: they skip the partials
+                if (__any(act)) {
+                    float g[kNg];
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                    if (act) {
+                        ++n_con;
+                        bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k], up, vx, vy, vz, g);
+                    }
+                    static_assert(kNg == 18, "wave_sum18 reduces 18 values");
+                    const float tot = wave_sum18(g, lane);
+                    if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
+                    if (lane == 0) sflag[k] = 1;
+                }
+            }
+            __syncthreads();
+            // the pose partials of this batch's flushes, summed over the wave into s_pose
+            double pacc[6] = {0, 0, 0, 0, 0, 0};
+            bool flushed = false;
+            if ((int)threadIdx.x < cnt) {
+                const int k = threadIdx.x;
+                if (sflag[k]) {
+                    flushed = true;
+                    // take the record's sums and leave the slots zeroed for the next batch
+                    float s[kNg];
+#pragma unroll
+                    for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
+                    sflag[k] = 0;
+                    const uint32_t id = pval[b0 + k];
+                    const FrameRec fr = flush_axes(srec[k]);
+                    flush_record(s, fr, srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
+                }
+            }
+            if (__any(flushed)) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    double v = pacc[c];
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                    if (lane == 0) s_pose[wid][c] += v;
+                }
             }
         }
+        if (inside) {
+            census[2 * total_pixels + p] = n_eval;
+            census[3 * total_pixels + p] = n_con;
+        }
+        // the four waves' pose sums into the slot's own row (summed per keyframe in
+        // a fixed order by k_pose_reduce; no atomics)
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const int k = threadIdx.x;
-            if (sflag[k]) {
-                // take the record's sums and leave the slots zeroed for the next batch
-                float s[kNg];
-#pragma unroll
-                for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
-                sflag[k] = 0;
-                const uint32_t id = pval[b0 + k];
-                const FrameRec fr = flush_axes(srec[k]);
-                flush_record(s, fr, srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
-            }
+        if (threadIdx.x < 6) {
+            pose_part[8 * (size_t)item + threadIdx.x] =
+                s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
         }
-    }
-    if (inside) {
-        census[2 * total_pixels + p] = n_eval;
-        census[3 * total_pixels + p] = n_con;
-    }
-    // block reduction of the pose partials into this workgroup's own row (summed per
-    // keyframe in a fixed order by k_pose_reduce; no atomics)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double v = pacc[c];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        pacc[c] = v;
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) s_pose[wid][c] = pacc[c];
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        pose_part[8 * (size_t)blockIdx.x + threadIdx.x] =
-            s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
-    }
-    if (threadIdx.x == 6) {
-        pose_part[8 * (size_t)blockIdx.x + 6] = (double)tile_frame[tile];
+        if (threadIdx.x == 6) {
+            pose_part[8 * (size_t)item + 6] = (double)tile_frame[tile];
+        }
+
     }
 }
 
@@ -1794,7 +1813,7 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
     if (wave) {
-        const bool longest = L.schedule == SLR_SCHEDULE_LONGEST;
+        const bool longest = longest_order(L);
         const int64_t grid = wave_blocks(L.tiles) + (longest ? 16 * quad_tile_cap(L.tiles) : 0);
         hipLaunchKernelGGL(k_raster_fwd_w, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
@@ -1810,7 +1829,7 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s : k_raster_fwd,
                        dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
-                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
+                       longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
                        reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges),
                        reinterpret_cast<const double2 *>(ws + L.tables), reinterpret_cast<float *>(ws + L.stateT),
                        reinterpret_cast<int32_t *>(ws + L.stateN), reinterpret_cast<int32_t *>(ws + L.census), L.pixels);
@@ -1820,7 +1839,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
-    const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
+    const uint32_t *ord = longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (wave) {
         hipLaunchKernelGGL(k_raster_bwd_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
@@ -1832,20 +1851,33 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                            reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles);
         return;
     }
-    auto kern = L.bwd_batch == 128 ? k_raster_bwd<128> : k_raster_bwd<kBwdBatch>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(256), 0, stream,
+    const bool queue = L.schedule == SLR_SCHEDULE_QUEUE;
+    auto kern = L.bwd_batch == 128 ? (queue ? k_raster_bwd<128, true> : k_raster_bwd<128, false>)
+                                   : (queue ? k_raster_bwd<kBwdBatch, true> : k_raster_bwd<kBwdBatch, false>);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQueue);
+    int64_t grid = L.tiles;
+    if (queue) {
+        // as many workgroups as the device holds at once
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) == hipSuccess && cus > 0 && per_cu > 0)
+            grid = std::min<int64_t>(grid, (int64_t)cus * per_cu);
+        launch_fill_u32(counter, 0u, 1, stream);
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<double *>(ws + L.pose_part),
-                       pose_only ? 1 : 0);
+                       pose_only ? 1 : 0, counter, (int)L.tiles);
 }
 
 void gn_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
-    const uint32_t *ord = L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
+    const uint32_t *ord = longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (L.bwd_variant == SLR_VARIANT_WAVE) {
         const int64_t grid = wave_blocks(L.tiles) + (ord ? 16 * quad_tile_cap(L.tiles) : 0);
         hipLaunchKernelGGL(k_raster_gn_w, dim3((unsigned)grid), dim3(64), 0, stream,

@@ -104,6 +104,7 @@ inline int64_t wave_blocks(int64_t tiles) { return 32 * ((tiles + 7) / 8); }
 constexpr int kQuadMinList = 1536;   // a boundary of the half-octave length buckets of the tile order
 constexpr int64_t kQuadBudget = 8192;
 constexpr size_t kMiscQuadTiles = 32;
+constexpr size_t kMiscQueue = 40;   // u32 work-queue head of the persistent backward
 __host__ __device__ inline int64_t quad_tile_cap(int64_t tiles)
 {
     const int64_t by_budget = (kQuadBudget - 4 * tiles) / 12;
@@ -128,6 +129,13 @@ struct Layout {
     size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
+
+// Both longest-first schedules (the plain grid and the work queue) order the
+// tiles on the device after binning.
+inline bool longest_order(const Layout &L)
+{
+    return L.schedule == SLR_SCHEDULE_LONGEST || L.schedule == SLR_SCHEDULE_QUEUE;
+}
 
 struct FrameGeom {
     int32_t H, W, set;

@@ -190,7 +190,7 @@ void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream)
     hipLaunchKernelGGL(k_gn_reduce, dim3((unsigned)L.frames), dim3(128), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.gn_part),
                        L.tiles, L.bwd_variant == SLR_VARIANT_WAVE ? 4 : 1,
-                       L.schedule == SLR_SCHEDULE_LONGEST ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles)
+                       longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles)
                                                           : nullptr);
 }
 

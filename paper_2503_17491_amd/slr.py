@@ -32,7 +32,7 @@ class Tiling(C.Structure):
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
-SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST = 0, 1, 2
+SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST, SCHEDULE_QUEUE = 0, 1, 2, 3
 
 
 class Surfels(C.Structure):
@@ -306,7 +306,8 @@ BOX_EXACT, BOX_OPACITY, BOX_VERTEX = 0, 1, 2
 TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((16, 16), (8, 32), (32, 8))
                    for bv in (VARIANT_WAVE, VARIANT_LDS)] + [(32, 8, VARIANT_LDS, SCHEDULE_LONGEST, VARIANT_LDS),
                                                              (32, 8, VARIANT_WAVE, SCHEDULE_LONGEST, VARIANT_LDS, 128),
-                                                             (16, 16, VARIANT_WAVE, SCHEDULE_LONGEST, VARIANT_LDS, 128)]
+                                                             (16, 16, VARIANT_WAVE, SCHEDULE_LONGEST, VARIANT_LDS, 128),
+                                                             (32, 8, VARIANT_WAVE, SCHEDULE_QUEUE, VARIANT_LDS)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
 
 

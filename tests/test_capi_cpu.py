@@ -53,6 +53,12 @@ def test_workspace_size_and_validation():
     with pytest.raises(slr.SlrError) as e:
         slr.workspace_size(s, (32, 8, 3, 2, 1, 0, 100), 10, 10)
     assert e.value.status == slr.SLR_E_INVALID and "batch" in str(e.value)
+    # schedules 0..3 (3: the work queue of the persistent workgroup backward)
+    for sched in (0, 1, 2, 3):
+        assert slr.workspace_size(s, (32, 8, 3, sched, 1, 0, 0), 10, 10) > 0
+    with pytest.raises(slr.SlrError) as e:
+        slr.workspace_size(s, (32, 8, 3, 4, 1, 0, 0), 10, 10)
+    assert e.value.status == slr.SLR_E_INVALID and "schedule" in str(e.value)
     pole = slr.make_sensor(64, 512, el=(math.radians(-89.5), math.radians(10)))
     with pytest.raises(slr.SlrError) as e:
         slr.workspace_size(pole, (16, 16), 10, 10)

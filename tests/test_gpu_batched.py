@@ -95,6 +95,40 @@ def test_batched_matches_plain(slr, tiling):
         assert np.abs(a - b).max() <= 1e-4 * scale, key
 
 
+@pytest.mark.parametrize("batch", [128, 192])
+def test_queue_schedule_matches_longest(slr, batch):
+    """The persistent workgroup backward (tiles taken from a device work queue
+    by an occupancy-sized grid) against the same kernel launched one
+    workgroup per tile: identical images, gradients equal up to the order of
+    the float atomics, every tile visited once (pose rows and census)."""
+    say("work-queue backward vs one workgroup per tile, batch", batch)
+    res = []
+    for sched in (slr.SCHEDULE_LONGEST, slr.SCHEDULE_QUEUE):
+        tiling = (32, 8, slr.VARIANT_WAVE, sched, slr.VARIANT_LDS, 0, batch)
+        sets, frames, _, br = make_batch(slr, tiling)
+        upstream(br, 3)
+        for _ in range(2):   # a second step: the queue head is reset before every launch
+            for g in br.grads:
+                for t in g.values():
+                    t.zero_()
+            br.render()
+            br.backward()
+        torch.cuda.synchronize()
+        res.append(([tuple(t.clone() for t in o) for o in br.out], [{k: v.clone() for k, v in g.items()} for g in br.grads],
+                    [d.clone() for d in br.dpose], br.views()["census"].clone()))
+    (o0, g0, d0, c0), (o1, g1, d1, c1) = res
+    for a, b in zip(o0, o1):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    assert torch.equal(c0, c1)
+    for ga, gb in zip(g0, g1):
+        for key in ga:
+            a, b = gb[key].cpu().numpy(), ga[key].cpu().numpy()
+            assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), key
+    for a, b in zip(d0, d1):
+        np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=1e-6, atol=1e-12)
+
+
 MIXED_TILES = [(8, 32), (4, 64), (32, 8), (16, 16)]
 
 
