@@ -1050,25 +1050,34 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 nact += __popcll(m);
             }
             __syncthreads();
-            for (int q = nact - 1; q >= 0; --q) {
-                const int k = slist[wid][q];
-                const int pos = b0 + k - rg.x;
-                PairEval e;
-                n_eval += pos < last ? 1 : 0;
-                const bool act = eval_pair_flat(srec[k], vx, vy, vz, near_m, e) && pos < last;
-                // about half of the walked entries meet no lane: they skip the partials
-                if (__any(act)) {
-                    float g[kNg];
+            for (int q = nact - 1; q >= 0; q -= 2) {
+                // two entries per step: both evaluations are independent of the
+                // reverse chain, which then takes them in list order
+                const bool has1 = q >= 1;
+                const int ka = slist[wid][q], kb = slist[wid][has1 ? q - 1 : q];
+                const int posa = b0 + ka - rg.x, posb = b0 + kb - rg.x;
+                PairEval ea, eb;
+                n_eval += (posa < last ? 1 : 0) + (has1 && posb < last ? 1 : 0);
+                const bool acta = eval_pair_flat(srec[ka], vx, vy, vz, near_m, ea) && posa < last;
+                const bool actb = eval_pair_flat(srec[kb], vx, vy, vz, near_m, eb) && posb < last && has1;
 #pragma unroll
-                    for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
-                    if (act) {
-                        ++n_con;
-                        bwd_pair(st, e, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k], up, vx, vy, vz, g);
+                for (int h = 0; h < 2; ++h) {
+                    const int k = h ? kb : ka;
+                    const bool act = h ? actb : acta;
+                    // about half of the walked entries meet no lane: they skip the partials
+                    if (__any(act)) {
+                        float g[kNg];
+#pragma unroll
+                        for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                        if (act) {
+                            ++n_con;
+                            bwd_pair(st, h ? eb : ea, srec[k].n[0], srec[k].n[1], srec[k].n[2], schat[k], up, vx, vy, vz, g);
+                        }
+                        static_assert(kNg == 18, "wave_sum18 reduces 18 values");
+                        const float tot = wave_sum18(g, lane);
+                        if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
+                        if (lane == 0) sflag[k] = 1;
                     }
-                    static_assert(kNg == 18, "wave_sum18 reduces 18 values");
-                    const float tot = wave_sum18(g, lane);
-                    if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
-                    if (lane == 0) sflag[k] = 1;
                 }
             }
             __syncthreads();
@@ -1225,24 +1234,31 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
         uint64_t fmask = 0;   // records of this chunk with partials in sred
         uint64_t live = __ballot(last > c - rg.x);
         if (__popcll(live) > kStragglers) {
-            for (int q = nact - 1; q >= 0; --q) {
-                const int k = slist[q];
-                const int pos = c + k - rg.x;
-                PairEval e;
-                n_eval += pos < last ? 1 : 0;
-                const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
-                if (__any(act)) {
-                    float g[kNg];
+            for (int q = nact - 1; q >= 0; q -= 2) {
+                const bool has1 = q >= 1;
+                const int ka = slist[q], kb = slist[has1 ? q - 1 : q];
+                const int posa = c + ka - rg.x, posb = c + kb - rg.x;
+                PairEval ea, eb;
+                n_eval += (posa < last ? 1 : 0) + (has1 && posb < last ? 1 : 0);
+                const bool acta = eval_pair_flat(sbuf[ka], vx, vy, vz, near_m, ea) && posa < last;
+                const bool actb = eval_pair_flat(sbuf[kb], vx, vy, vz, near_m, eb) && posb < last && has1;
 #pragma unroll
-                    for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
-                    if (act) {
-                        ++n_con;
-                        bwd_pair(st, e, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k], up, vx, vy, vz, g);
+                for (int h = 0; h < 2; ++h) {
+                    const int k = h ? kb : ka;
+                    const bool act = h ? actb : acta;
+                    if (__any(act)) {
+                        float g[kNg];
+#pragma unroll
+                        for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+                        if (act) {
+                            ++n_con;
+                            bwd_pair(st, h ? eb : ea, sbuf[k].n[0], sbuf[k].n[1], sbuf[k].n[2], schat[k], up, vx, vy, vz, g);
+                        }
+                        static_assert(kNg == 18, "wave_sum18 reduces 18 values");
+                        const float tot = wave_sum18(g, lane);
+                        if (red_val < kNg) sred[red_val][k] = tot;
+                        fmask |= 1ull << k;
                     }
-                    static_assert(kNg == 18, "wave_sum18 reduces 18 values");
-                    const float tot = wave_sum18(g, lane);
-                    if (red_val < kNg) sred[red_val][k] = tot;
-                    fmask |= 1ull << k;
                 }
             }
         } else {
@@ -1782,18 +1798,25 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int q = nact - 1; q >= 0; --q) {
-            const int k = slist[q];
-            const int pos = c + k - rg.x;
-            PairEval e;
-            const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && pos < last;
-            if (act) {
-                const RasterRec &r = sbuf[k];
-                const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up, range_low(e, stau[k]));
-                float jc[6];
-                gn_pair_row(sc, r, sab[k], e.t, fvx, fvy, fvz, jc);
+        for (int q = nact - 1; q >= 0; q -= 2) {
+            // two entries per step: both evaluations ahead of the reverse chain
+            const bool has1 = q >= 1;
+            const int ka = slist[q], kb = slist[has1 ? q - 1 : q];
+            PairEval ea, eb;
+            const bool acta = eval_pair_flat(sbuf[ka], vx, vy, vz, near_m, ea) && c + ka - rg.x < last;
+            const bool actb = eval_pair_flat(sbuf[kb], vx, vy, vz, near_m, eb) && c + kb - rg.x < last && has1;
 #pragma unroll
-                for (int a = 0; a < 6; ++a) J[a] += jc[a];
+            for (int h = 0; h < 2; ++h) {
+                if (h ? actb : acta) {
+                    const int k = h ? kb : ka;
+                    const PairEval &e = h ? eb : ea;
+                    const RasterRec &r = sbuf[k];
+                    const BwdScalars sc = bwd_step(st, e, r.n[0], r.n[1], r.n[2], up, range_low(e, stau[k]));
+                    float jc[6];
+                    gn_pair_row(sc, r, sab[k], e.t, fvx, fvy, fvz, jc);
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) J[a] += jc[a];
+                }
             }
         }
         // every lane is done with this chunk's records before they are replaced
