@@ -138,10 +138,10 @@ def profiled_tiling(kernel):
     return fields.get("tiling") if fields.get("raster.hip sha256") == sha else None
 
 
-def tiling_label(th, tw, var, bvar, bbatch):
+def tiling_label(th, tw, var, bvar, bbatch, sch=0):
     vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
     return f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}" + (
-        f" batch {bbatch}" if bvar == 1 and bbatch not in (0, 192) else "")
+        f" batch {bbatch}" if bvar == 1 and bbatch not in (0, 192) else "") + (" queue" if sch == 3 else "")
 
 
 def roofline(kernel, flops, nbytes, ms, traffic):
@@ -332,7 +332,7 @@ def main():
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
     ap.add_argument("--bwd-variant", choices=["default", "lds", "wave"], default="default",
                     help="backward compositing kernel: one workgroup per tile, or one wave per strip")
-    ap.add_argument("--schedule", choices=["default", "tile", "longest"], default="default",
+    ap.add_argument("--schedule", choices=["default", "tile", "longest", "queue"], default="default",
                     help="order in which the compositing kernels take tiles")
     ap.add_argument("--only", choices=["both", "batched"], default="both",
                     help="batched: skip the plain form (short profiling runs)")
@@ -366,7 +366,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     var = {"default": slr.VARIANT_DEFAULT, "lds": slr.VARIANT_LDS, "scalar": slr.VARIANT_SCALAR,
            "wave": slr.VARIANT_WAVE}[args.variant]
-    sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST}[args.schedule]
+    sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST,
+           "queue": slr.SCHEDULE_QUEUE}[args.schedule]
     th = tw = None
     bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
     box = {"exact": slr.BOX_EXACT, "opacity": slr.BOX_OPACITY, "vertex": slr.BOX_VERTEX}[args.box]
@@ -400,7 +401,7 @@ def main():
         best_ms = min(v for v in tune_ms.values() if v > 0)
         for c, v in tune_ms.items():
             if prof and 0 < v <= best_ms * (1 + TUNE_MARGIN) and \
-                    tiling_label(c[0], c[1], c[2], c[4], c[6] if len(c) > 6 else 0) == prof:
+                    tiling_label(c[0], c[1], c[2], c[4], c[6] if len(c) > 6 else 0, c[3]) == prof:
                 if tuple(c) != tuple(br.tiling):
                     log(f"autotune: {c} is within {TUNE_MARGIN:.0%} of the fastest and has committed counters")
                     br.tiling = tuple(c)
@@ -408,8 +409,9 @@ def main():
                 break
         th, tw, var, sch, bvar, box = br.tiling[:6]
         bbatch = br.tiling[6] if len(br.tiling) > 6 else 0
-        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}" + (f"/{c[6]}" if len(c) > 6 else ""):
-                                             round(v, 3) for c, v in tune_ms.items()})
+        log("autotuned tiling:", br.tiling, {f"{c[0]}x{c[1]}/f{c[2]}/b{c[4]}" + (f"/{c[6]}" if len(c) > 6 else "") +
+                                             ("/queue" if c[3] == slr.SCHEDULE_QUEUE else ""): round(v, 3)
+                                             for c, v in tune_ms.items()})
     tiling = (th, tw, var, sch, bvar, box, bbatch)
     grads = {k: None for k in ("means", "quats", "log_scales", "logits")}
     dposes = [torch.zeros(6, dtype=torch.float64, device="cuda") for _ in kfs]
@@ -528,7 +530,7 @@ def main():
         dom, flops, nbytes, ms = "raster_bwd", bwd_flops, bwd_bytes, bwd_ms
     else:
         dom, flops, nbytes, ms = "raster_fwd", fwd_flops, fwd_bytes, fwd_ms
-    tiling_name = tiling_label(th, tw, var, bvar, bbatch)
+    tiling_name = tiling_label(th, tw, var, bvar, bbatch, sch)
     traffic = counted_traffic(dom, tiling_name)
     roof = roofline(dom, flops, nbytes, ms, traffic)
     stage_ms = {k: round(v[0] / nst, 4) for k, v in stages.items()}
@@ -558,7 +560,7 @@ def main():
         "config": {"workload": f"{N_SURFELS} surfels (structured scene), {N_KF} keyframes {H}x{W} sharing the "
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
-                   "schedule": {0: "default", 1: "tile", 2: "longest"}[sch],
+                   "schedule": {0: "default", 1: "tile", 2: "longest", 3: "queue"}[sch],
                    "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar],
                    "bwd_batch": bbatch if bbatch else 192, "autotuned": tune_ms is not None,
                    "box": args.box,

@@ -404,22 +404,39 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
-    RasterRec nxt;
-    if (rg.x + lane < rg.y) nxt = rec[pval[rg.x + lane]];
+    // list entry c + lane travels as six 16-byte words in registers (a record
+    // copied as a struct would be placed in scratch memory)
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 nrec[6];
+    if (rg.x + lane < rg.y) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + pval[rg.x + lane]);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) nrec[f] = src[f];
+    }
     for (int c = rg.x; c < rg.y; c += 64) {
         if (__ballot(!done) == 0) break;
-        const RasterRec r = nxt;   // list entry c + lane
         const bool inchunk = c + lane < rg.y;
-        if (c + 64 + lane < rg.y) nxt = rec[pval[c + 64 + lane]];
         bool meets = false;
         if (inchunk) {
-            const uint32_t rows = r.rows;
+            const uint32_t rows = nrec[5].w;
             meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
         }
         const uint64_t m = __ballot(meets);
         const int nact = __popcll(m);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (meets) { sbuf[rank] = r; sidx[rank] = (uint8_t)lane; }
+        if (meets) {
+            u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[rank]);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) dst[f] = nrec[f];
+            sidx[rank] = (uint8_t)lane;
+        }
+        // the next chunk's loads go out once this one is staged
+        __builtin_amdgcn_sched_barrier(0);
+        if (c + 64 + lane < rg.y) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + pval[c + 64 + lane]);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) nrec[f] = src[f];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
