@@ -399,7 +399,9 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.rcnt = take(4 * nn);
     L.rbox = take(sizeof(PixBox) * nn);
     // per compositing workgroup: its pose partial (6 doubles) and keyframe index
-    L.pose_part = take(sizeof(double) * 8 * (size_t)(wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles));
+    // (the one-wave backward's grid adds 16 quad-mode workgroups per quad tile)
+    L.pose_part = take(sizeof(double) * 8 *
+                       (size_t)((wave_blocks(L.tiles) > L.tiles ? wave_blocks(L.tiles) : L.tiles) + 16 * quad_tile_cap(L.tiles)));
     // per Gauss-Newton workgroup (one per tile) or strip wave (four per tile): its partial normal equations
     // four strip rows per tile, sixteen for the tiles composited in quad mode
     L.gn_part = take(sizeof(double) * kGnRow * (4 * (size_t)L.tiles + 12 * (size_t)quad_tile_cap(L.tiles)));

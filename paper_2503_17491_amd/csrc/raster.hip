@@ -853,6 +853,37 @@ __device__ __forceinline__ void bwd_pair(BwdState &st, const PairEval &e, float 
     bwd_partials(q, e, chr.c, u, vx, vy, vz, g);
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The evaluations of the four lanes of this lane's quad (every lane active).
+__device__ __forceinline__ void quad_evals(const PairEval &e, int lane, PairEval (&eu)[4])
+{
+    eu[0].sa = dpp_perm<0x00>(e.sa); eu[1].sa = dpp_perm<0x55>(e.sa);
+    eu[2].sa = dpp_perm<0xAA>(e.sa); eu[3].sa = dpp_perm<0xFF>(e.sa);
+    eu[0].sb = dpp_perm<0x00>(e.sb); eu[1].sb = dpp_perm<0x55>(e.sb);
+    eu[2].sb = dpp_perm<0xAA>(e.sb); eu[3].sb = dpp_perm<0xFF>(e.sb);
+    eu[0].t = dpp_perm<0x00>(e.t); eu[1].t = dpp_perm<0x55>(e.t);
+    eu[2].t = dpp_perm<0xAA>(e.t); eu[3].t = dpp_perm<0xFF>(e.t);
+    eu[0].rc = dpp_perm<0x00>(e.rc); eu[1].rc = dpp_perm<0x55>(e.rc);
+    eu[2].rc = dpp_perm<0xAA>(e.rc); eu[3].rc = dpp_perm<0xFF>(e.rc);
+    eu[0].G = dpp_perm<0x00>(e.G); eu[1].G = dpp_perm<0x55>(e.G);
+    eu[2].G = dpp_perm<0xAA>(e.G); eu[3].G = dpp_perm<0xFF>(e.G);
+    eu[0].alpha = dpp_perm<0x00>(e.alpha); eu[1].alpha = dpp_perm<0x55>(e.alpha);
+    eu[2].alpha = dpp_perm<0xAA>(e.alpha); eu[3].alpha = dpp_perm<0xFF>(e.alpha);
+    eu[0].c = dpp_perm_d<0x00>(e.c); eu[1].c = dpp_perm_d<0x55>(e.c);
+    eu[2].c = dpp_perm_d<0xAA>(e.c); eu[3].c = dpp_perm_d<0xFF>(e.c);
+    const uint32_t clq = (uint32_t)(__ballot(e.clamped) >> (lane & ~3)) & 0xfu;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) eu[u].clamped = (clq >> u) & 1u;
+}
+
 // The splat axes from a record: P, Q, M are the cofactors of (b_alpha b_beta
 // b_c), so P x Q = tau b_c, Q x M = tau b_alpha, M x P = tau b_beta with
 // tau^2 = M . (P x Q) and the sign of the stored tau (FP64, ~1e-12 relative).
@@ -1143,6 +1174,182 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
     }
 }
 
+// Sum over the 16 lanes of the wave that share lane & 3 (the four rows'
+// lanes of one slot): rotations by 4 and 8 inside each 16-lane row keep the
+// slot, then the rows are folded.  Every lane ends with its slot's total.
+__device__ __forceinline__ float slot_sum16(float x)
+{
+    x = dpp_add<0x124, 0xf>(x);   // row_ror:4
+    x = dpp_add<0x128, 0xf>(x);   // row_ror:8
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
+// Quad mode of the one-wave backward (the counterpart of fwd_quad and gn_quad):
+// 16 pixels of the tile, four lanes per pixel.  Each step the four lanes of a
+// pixel evaluate four consecutive compacted records (slot 0 the latest in list
+// order); every lane advances its pixel's reverse state through the four in
+// reverse list order with the broadcast evaluations, keeping its own record's
+// step, and forms its own pair's 18 partials; the partials of each slot's
+// record are summed over its 16 pixels and stored for the record, which
+// flushes at the end of the chunk as in the strip form.  A pixel's reverse
+// chain sees the same pairs in the same order as in the strip form.
+__device__ __forceinline__ void bwd_quad(const FrameDesc &fd, int tile, int sub, const RasterRec *__restrict__ rec,
+                                         const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+                                         const double2 *__restrict__ tables, const float *__restrict__ stT_all,
+                                         const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all,
+                                         int64_t total_pixels, double *prow, int frame, int pose_only,
+                                         RasterRec *sbuf, ChatRec *schat, float (*sred)[64], uint8_t *slist)
+{
+    const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
+    const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
+    const float near_m = (float)fd.near_m;
+    const double2 *col = tables + fd.tab_off, *rowc = col + W;
+    const float *stT = stT_all + fd.pix_off;
+    const int32_t *stN = stN_all + fd.pix_off;
+    int32_t *census = census_all + fd.pix_off;
+    const int ltile = tile - fd.tile_off;
+    const int ty = ltile / tiles_x, tx = ltile - ty * tiles_x;
+    const int lane = threadIdx.x, slot = lane & 3;
+    const int q16 = 16 * sub + (lane >> 2);   // pixel index within the tile, row-major
+    const int i = ty * TH + (q16 >> tws), j = tx * TW + (q16 & (TW - 1));
+    const bool inside = (i < H) && (j < W);
+    const double2 cr = rowc[min(i, H - 1)], cc = col[min(j, W - 1)];
+    const double vx = cr.x * cc.x, vy = cr.x * cc.y, vz = cr.y;
+    const int2 rg = ranges[tile];
+    const int wr0 = ty * TH + ((16 * sub) >> tws), wr1 = ty * TH + ((16 * sub + 15) >> tws);
+    const int p = inside ? i * W + j : 0;
+    const int last = inside ? stN[p] : 0;
+    const float T0 = inside ? stT[p] : 1.0f;
+    BwdUpstream up;
+    up.gd = (inside && fd.gD) ? fd.gD[p] : 0.0f;
+    up.go = (inside && fd.gO) ? fd.gO[p] : 0.0f;
+    up.gn0 = (inside && fd.gN) ? fd.gN[3 * p] : 0.0f;
+    up.gn1 = (inside && fd.gN) ? fd.gN[3 * p + 1] : 0.0f;
+    up.gn2 = (inside && fd.gN) ? fd.gN[3 * p + 2] : 0.0f;
+    up.Tfin = T0;
+    BwdState st = {T0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, false};
+    int wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+    for (int v = 0; v < kNg; ++v) sred[v][lane] = 0.0f;
+    double pacc[6] = {0, 0, 0, 0, 0, 0};
+    int n_eval = 0, n_con = 0;
+    float *acc_base = pose_only ? nullptr : fd.acc;
+    const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the sub-strip
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
+        bool meets = false;
+        uint32_t id = 0;
+        if (c + lane < end) {
+            id = pval[c + lane];
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + id);
+            u32x4 w[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) w[f] = src[f];
+            const uint32_t rows = w[5].w;
+            meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+            if (meets) {
+                u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[lane]);
+#pragma unroll
+                for (int f = 0; f < 6; ++f) dst[f] = w[f];
+                centre_dir(sbuf[lane], schat[lane]);
+            }
+        }
+        const uint64_t m = __ballot(meets);
+        const int nact = __popcll(m);
+        if (meets)
+            slist[__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t fmask = 0;   // chunk records with sums in sred
+        for (int q = nact - 1; q >= 0; q -= 4) {
+            const int kq = q - slot;   // this lane's compacted index: slot 0 the latest in list order
+            const int k = slist[kq >= 0 ? kq : 0];
+            const bool cand = kq >= 0 && c + k - rg.x < last;
+            n_eval += cand ? 1 : 0;
+            PairEval e;
+            const bool act = eval_pair_flat(sbuf[k], vx, vy, vz, near_m, e) && cand;
+            const uint64_t am = __ballot(act);
+            if (am == 0) continue;
+            const uint32_t actq = (uint32_t)(am >> (lane & ~3)) & 0xfu;
+            PairEval eu[4];
+            quad_evals(e, lane, eu);
+            BwdScalars mine = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if ((actq >> u) & 1u) {
+                    const int ku = slist[q - u];
+                    const RasterRec &r = sbuf[ku];
+                    const BwdScalars sc = bwd_step(st, eu[u], r.n[0], r.n[1], r.n[2], up, range_low(eu[u], schat[ku].tau));
+                    if (u == slot) mine = sc;
+                }
+            }
+            float g[kNg];
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) g[v] = 0.0f;
+            if (act) {
+                ++n_con;
+                bwd_partials(mine, e, schat[k].c, up, vx, vy, vz, g);
+            }
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) g[v] = slot_sum16(g[v]);
+            // lanes 0..3 store the totals of slots 0..3 (records with a contributing pixel)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if ((am & (0x1111111111111111ull << u)) != 0) {
+                    const int ku = slist[q - u];
+                    if (lane == u) {
+#pragma unroll
+                        for (int v = 0; v < kNg; ++v) sred[v][ku] = g[v];
+                    }
+                    fmask |= 1ull << ku;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((fmask >> lane) & 1ull) {
+            float s[kNg];
+#pragma unroll
+            for (int v = 0; v < kNg; ++v) { s[v] = sred[v][lane]; sred[v][lane] = 0.0f; }
+            const FrameRec fr = flush_axes(sbuf[lane]);
+            flush_record(s, fr, sbuf[lane].M, schat[lane].c, fd.pose,
+                         acc_base ? acc_base + (size_t)(id - fd.item_off) * kAccStride : nullptr, pacc);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // a pixel's counts are the sums over its four lanes
+    n_eval += __shfl_xor(n_eval, 1, 64);
+    n_eval += __shfl_xor(n_eval, 2, 64);
+    n_con += __shfl_xor(n_con, 1, 64);
+    n_con += __shfl_xor(n_con, 2, 64);
+    if (inside && slot == 0) {
+        census[2 * total_pixels + p] = n_eval;
+        census[3 * total_pixels + p] = n_con;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double v = pacc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        pacc[k] = v;
+    }
+    if (lane < 6) {
+        double v = pacc[0];
+#pragma unroll
+        for (int k = 1; k < 6; ++k) v = lane == k ? pacc[k] : v;
+        prow[lane] = v;
+    }
+    if (lane == 6) prow[6] = (double)frame;
+}
+
 // Backward, one wave per 64-pixel strip (the counterpart of k_raster_fwd_w).
 // The strip's list is walked in reverse, 64 records per chunk (one per lane,
 // the previous chunk's loads in flight), from its last contributor down.
@@ -1158,15 +1365,24 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-               double *__restrict__ pose_part, int pose_only, int64_t ntiles)
+               double *__restrict__ pose_part, int pose_only, int64_t ntiles,
+               const uint32_t *__restrict__ nquad_dev)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ ChatRec schat[64];
     __shared__ float sred[kNg][64];
     __shared__ uint8_t slist[64];
     int strip, tslot;
-    if (!strip_of_block(ntiles, strip, tslot)) {
+    const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
+    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    if (kind == 0) {
         if (threadIdx.x == 6) pose_part[8 * (size_t)blockIdx.x + 6] = -1.0;   // no keyframe
+        return;
+    }
+    if (kind == 2) {
+        const int qt = (int)order[tslot];
+        bwd_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all, census_all,
+                 total_pixels, pose_part + 8 * (size_t)blockIdx.x, tile_frame[qt], pose_only, sbuf, schat, sred, slist);
         return;
     }
     const int tile = order ? (int)order[tslot] : tslot;
@@ -1593,37 +1809,6 @@ __device__ __forceinline__ void gn_pair_row(const BwdScalars &sc, const RasterRe
 }
 
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_perm_d(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// The evaluations of the four lanes of this lane's quad (every lane active).
-__device__ __forceinline__ void quad_evals(const PairEval &e, int lane, PairEval (&eu)[4])
-{
-    eu[0].sa = dpp_perm<0x00>(e.sa); eu[1].sa = dpp_perm<0x55>(e.sa);
-    eu[2].sa = dpp_perm<0xAA>(e.sa); eu[3].sa = dpp_perm<0xFF>(e.sa);
-    eu[0].sb = dpp_perm<0x00>(e.sb); eu[1].sb = dpp_perm<0x55>(e.sb);
-    eu[2].sb = dpp_perm<0xAA>(e.sb); eu[3].sb = dpp_perm<0xFF>(e.sb);
-    eu[0].t = dpp_perm<0x00>(e.t); eu[1].t = dpp_perm<0x55>(e.t);
-    eu[2].t = dpp_perm<0xAA>(e.t); eu[3].t = dpp_perm<0xFF>(e.t);
-    eu[0].rc = dpp_perm<0x00>(e.rc); eu[1].rc = dpp_perm<0x55>(e.rc);
-    eu[2].rc = dpp_perm<0xAA>(e.rc); eu[3].rc = dpp_perm<0xFF>(e.rc);
-    eu[0].G = dpp_perm<0x00>(e.G); eu[1].G = dpp_perm<0x55>(e.G);
-    eu[2].G = dpp_perm<0xAA>(e.G); eu[3].G = dpp_perm<0xFF>(e.G);
-    eu[0].alpha = dpp_perm<0x00>(e.alpha); eu[1].alpha = dpp_perm<0x55>(e.alpha);
-    eu[2].alpha = dpp_perm<0xAA>(e.alpha); eu[3].alpha = dpp_perm<0xFF>(e.alpha);
-    eu[0].c = dpp_perm_d<0x00>(e.c); eu[1].c = dpp_perm_d<0x55>(e.c);
-    eu[2].c = dpp_perm_d<0xAA>(e.c); eu[3].c = dpp_perm_d<0xFF>(e.c);
-    const uint32_t clq = (uint32_t)(__ballot(e.clamped) >> (lane & ~3)) & 0xfu;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) eu[u].clamped = (clq >> u) & 1u;
-}
-
 // Quad mode of the one-wave Gauss-Newton kernel (the counterpart of fwd_quad):
 // 16 pixels of the tile, four lanes per pixel.  Each step the four lanes of a
 // pixel evaluate four consecutive compacted records (slot 0 the latest in list
@@ -1881,14 +2066,16 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
     const uint32_t *ord = longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (wave) {
-        hipLaunchKernelGGL(k_raster_bwd_w, dim3((unsigned)wave_blocks(L.tiles)), dim3(64), 0, stream,
+        const int64_t grid = wave_blocks(L.tiles) + (ord ? 16 * quad_tile_cap(L.tiles) : 0);
+        hipLaunchKernelGGL(k_raster_bwd_w, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame), ord,
                            reinterpret_cast<const RasterRec *>(ws + L.rec), pval,
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels,
-                           reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles);
+                           reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles,
+                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
         return;
     }
     const bool queue = L.schedule == SLR_SCHEDULE_QUEUE;

@@ -178,7 +178,11 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.frames == 0) return;
-    const int64_t nparts = L.bwd_variant == SLR_VARIANT_WAVE ? wave_blocks(L.tiles) : L.tiles;
+    // one row per compositing workgroup (the one-wave backward's grid includes
+    // its quad-mode workgroups)
+    const int64_t nparts = L.bwd_variant == SLR_VARIANT_WAVE
+                               ? wave_blocks(L.tiles) + (longest_order(L) ? 16 * quad_tile_cap(L.tiles) : 0)
+                               : L.tiles;
     hipLaunchKernelGGL(k_pose_reduce, dim3((unsigned)L.frames), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const double *>(ws + L.pose_part),
                        nparts);
