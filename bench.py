@@ -14,6 +14,7 @@ Prints one JSON line: the metric, per-stage times, the roofline of the dominant
 compositing kernel and the FP64 oracle's CPU baseline.
 """
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -296,20 +297,37 @@ def cpu_baseline(sc, sensor, kfs, budget_s):
                           cull=True)
         return time.perf_counter() - t
 
-    # grow the sample until it takes about budget_s (at most six tries; every try
-    # pays the cull index once, so the early ones understate the per-pixel rate)
-    P, t1 = 4 * threads, 0.0
-    for k in range(6):
-        t1 = run(P)
-        if t1 >= 0.6 * budget_s or P >= H * W * N_KF or k == 5:
-            break
-        P = min(H * W * N_KF, max(P + 1, int(P * min(10.0, budget_s / max(t1, 1e-3)))))
-    per_pixel = t1 / P
-    s_per_iter = per_pixel * H * W * N_KF
-    return {"value": 1.0 / s_per_iter, "unit": "iter/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle fwd+bwd of {P} random pixels of keyframe 0 (every pixel ray against the "
-                      f"{N_SURFELS} surfels, in its result-identical angular-cull mode; each call builds its cull "
-                      f"index) in {t1:.1f}s, scaled to {N_KF}x{H}x{W} pixels per iteration"}
+    def omp_threads(n):   # the oracle's OpenMP regions (libgomp)
+        try:
+            ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        except OSError:
+            pass
+
+    def measure(nthreads, budget):
+        # grow the sample until it takes about `budget` (at most six tries; every try
+        # pays the cull index once, so the early ones understate the per-pixel rate)
+        omp_threads(nthreads)
+        P, t1 = 4 * nthreads, 0.0
+        for k in range(6):
+            t1 = run(P)
+            if t1 >= 0.6 * budget or P >= H * W * N_KF or k == 5:
+                break
+            P = min(H * W * N_KF, max(P + 1, int(P * min(10.0, budget / max(t1, 1e-3)))))
+        return P, t1
+
+    def sample(P, t1):
+        return (f"FP64 oracle fwd+bwd of {P} random pixels of keyframe 0 (every pixel ray against the "
+                f"{N_SURFELS} surfels, in its result-identical angular-cull mode; each call builds its cull "
+                f"index) in {t1:.1f}s, scaled to {N_KF}x{H}x{W} pixels per iteration")
+
+    P, t1 = measure(threads, budget_s)
+    out = {"value": 1.0 / (t1 / P * H * W * N_KF), "unit": "iter/s", "cores": threads, "kind": "oracle",
+           "sample": sample(P, t1)}
+    P1, t11 = measure(1, budget_s / 2)
+    out["one_thread"] = {"value": 1.0 / (t11 / P1 * H * W * N_KF), "unit": "iter/s", "cores": 1,
+                         "sample": sample(P1, t11)}
+    omp_threads(threads)
+    return out
 
 
 def main():
