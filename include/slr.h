@@ -76,10 +76,11 @@ typedef struct slr_sensor {
  * schedule selects the order in which the compositing kernels take tiles:
  * 0 = library default, 1 = tile-id order, 2 = longest surfel list first
  * (computed on the device after binning), 3 = the same order taken from a
- * device work queue by the workgroup backward (bwd_variant 1), which then
- * runs as a persistent kernel: as many workgroups as the device holds at
- * once, each taking the next tile until none is left (the other kernels
- * behave as with 2; results identical to 2).  bwd_variant selects the form of
+ * device work queue by the one-wave forward (variant 3) and the workgroup
+ * backward (bwd_variant 1), which then run as persistent kernels: as many
+ * workgroups as the device holds at once, each taking the next item (strip
+ * or tile) until none is left (the other kernels behave as with 2; results
+ * identical to 2).  bwd_variant selects the form of
  * the compositing backward: 0 = the same as variant (the library default if
  * that is 0), 1 = one workgroup per tile (records staged through LDS, one
  * flush per tile and record), 3 = one wave per 64-pixel strip.  Every variant

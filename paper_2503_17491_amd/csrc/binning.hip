@@ -123,6 +123,8 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
                 const PixBox *__restrict__ box_in, uint32_t *__restrict__ cnt_out, PixBox *__restrict__ box_out)
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
+    // the grid is sized for the capacity: blocks past the items have nothing to move
+    if ((int64_t)blockIdx.x * kSortTile >= n) return;
     __shared__ uint32_t s_base[256], s_start[256], s_gbase[256];
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_wave[kWaves];

@@ -493,9 +493,8 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
 // so that a tile's sub-strips share one XCD (see strip_of_block); the rest take
 // one 64-pixel strip of the remaining tiles each.  Returns 0 for padding
 // workgroups, 1 for a strip (strip, tslot), 2 for a sub-strip (sub, tslot).
-__device__ __forceinline__ int fwd_work_of_block(int64_t ntiles, int64_t nquad, int &part, int &tslot)
+__device__ __forceinline__ int fwd_work_of_block(int64_t b, int64_t ntiles, int64_t nquad, int &part, int &tslot)
 {
-    const int64_t b = blockIdx.x;
     if (b < 16 * nquad) {
         const int j = (int)(b & 127);
         part = j >> 3;
@@ -509,19 +508,18 @@ __device__ __forceinline__ int fwd_work_of_block(int64_t ntiles, int64_t nquad, 
     return tslot < ntiles ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(64)
-k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
-               const uint32_t *__restrict__ order,
-               const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
-               const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
-               int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
-               const uint32_t *__restrict__ nquad_dev)
+// One work item of the one-wave forward (a strip, a quad sub-strip or padding);
+// item b is what workgroup b of the plain grid takes.
+__device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restrict__ descs,
+                                           const int32_t *__restrict__ tile_frame, const uint32_t *__restrict__ order,
+                                           const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval,
+                                           const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
+                                           float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
+                                           int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
+                                           int64_t nquad, RasterRec *sbuf, uint8_t *sidx)
 {
-    __shared__ RasterRec sbuf[64];
-    __shared__ uint8_t sidx[64];
     int strip, tslot;
-    const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
-    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    const int kind = fwd_work_of_block(b, ntiles, nquad, strip, tslot);
     if (kind == 0) return;
     if (kind == 2) {
         const int qt = (int)order[tslot];
@@ -676,6 +674,37 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
         normal[3 * p] = N0; normal[3 * p + 1] = N1; normal[3 * p + 2] = N2;
         stT[p] = T;
         stN[p] = last;
+    }
+}
+
+// Forward, one wave per strip: workgroup b takes item b, or (QUEUE: the
+// persistent form of the work-queue schedule) an occupancy-sized grid takes
+// the items in order from a device counter zeroed before the launch.
+template <bool QUEUE>
+__global__ void __launch_bounds__(64)
+k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
+               const uint32_t *__restrict__ order,
+               const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
+               const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
+               int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
+               const uint32_t *__restrict__ nquad_dev, uint32_t *__restrict__ queue, int64_t nitems)
+{
+    __shared__ RasterRec sbuf[64];
+    __shared__ uint8_t sidx[64];
+    const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
+    if (!QUEUE) {
+        fwd_w_item((int64_t)blockIdx.x, descs, tile_frame, order, rec, pval, ranges, tables, stT_all, stN_all,
+                   census_all, total_pixels, ntiles, nquad, sbuf, sidx);
+        return;
+    }
+    for (;;) {
+        uint32_t v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(queue, 1u);
+        const int64_t item = (int64_t)__shfl(v, 0, 64);
+        if (item >= nitems) break;
+        fwd_w_item(item, descs, tile_frame, order, rec, pval, ranges, tables, stT_all, stN_all, census_all,
+                   total_pixels, ntiles, nquad, sbuf, sidx);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -1374,7 +1403,7 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     __shared__ uint8_t slist[64];
     int strip, tslot;
     const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
-    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    const int kind = fwd_work_of_block((int64_t)blockIdx.x, ntiles, nquad, strip, tslot);
     if (kind == 0) {
         if (threadIdx.x == 6) pose_part[8 * (size_t)blockIdx.x + 6] = -1.0;   // no keyframe
         return;
@@ -1939,7 +1968,7 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
     __shared__ uint8_t slist[64];
     int strip, tslot;
     const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
-    const int kind = fwd_work_of_block(ntiles, nquad, strip, tslot);
+    const int kind = fwd_work_of_block((int64_t)blockIdx.x, ntiles, nquad, strip, tslot);
     if (kind == 0) return;
     if (kind == 2) {   // 16 rows per quad tile, in sub-strip order
         const int qt = (int)order[tslot];
@@ -2033,14 +2062,32 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
 }
 
 
+// Grid of a persistent kernel: as many workgroups of `threads` as the device
+// holds at once (CU count x occupancy), at most `items`.
+template <class K>
+int64_t resident_grid(K kern, int threads, int64_t items)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) == hipSuccess && cus > 0 && per_cu > 0)
+        return std::min<int64_t>(items, (int64_t)cus * per_cu);
+    return items;
+}
+
 void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
     const bool wave = L.variant == SLR_VARIANT_WAVE;
     if (wave) {
         const bool longest = longest_order(L);
-        const int64_t grid = wave_blocks(L.tiles) + (longest ? 16 * quad_tile_cap(L.tiles) : 0);
-        hipLaunchKernelGGL(k_raster_fwd_w, dim3((unsigned)grid), dim3(64), 0, stream,
+        const int64_t items = wave_blocks(L.tiles) + (longest ? 16 * quad_tile_cap(L.tiles) : 0);
+        const bool queue = L.schedule == SLR_SCHEDULE_QUEUE;
+        auto kern = queue ? k_raster_fwd_w<true> : k_raster_fwd_w<false>;
+        uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQueueFwd);
+        const int64_t grid = queue ? resident_grid(kern, 64, items) : items;
+        if (queue) launch_fill_u32(counter, 0u, 1, stream);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                            longest ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr,
@@ -2048,7 +2095,8 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles,
-                           longest ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
+                           longest ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr,
+                           counter, items);
         return;
     }
     hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s : k_raster_fwd,
@@ -2082,16 +2130,8 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
     auto kern = L.bwd_batch == 128 ? (queue ? k_raster_bwd<128, true> : k_raster_bwd<128, false>)
                                    : (queue ? k_raster_bwd<kBwdBatch, true> : k_raster_bwd<kBwdBatch, false>);
     uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQueue);
-    int64_t grid = L.tiles;
-    if (queue) {
-        // as many workgroups as the device holds at once
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) == hipSuccess && cus > 0 && per_cu > 0)
-            grid = std::min<int64_t>(grid, (int64_t)cus * per_cu);
-        launch_fill_u32(counter, 0u, 1, stream);
-    }
+    const int64_t grid = queue ? resident_grid(kern, 256, L.tiles) : L.tiles;
+    if (queue) launch_fill_u32(counter, 0u, 1, stream);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval,

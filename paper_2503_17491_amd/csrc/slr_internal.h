@@ -104,7 +104,8 @@ inline int64_t wave_blocks(int64_t tiles) { return 32 * ((tiles + 7) / 8); }
 constexpr int kQuadMinList = 1536;   // a boundary of the half-octave length buckets of the tile order
 constexpr int64_t kQuadBudget = 8192;
 constexpr size_t kMiscQuadTiles = 32;
-constexpr size_t kMiscQueue = 40;   // u32 work-queue head of the persistent backward
+constexpr size_t kMiscQueue = 40;      // u32 work-queue head of the persistent workgroup backward
+constexpr size_t kMiscQueueFwd = 44;   // u32 work-queue head of the persistent one-wave forward
 __host__ __device__ inline int64_t quad_tile_cap(int64_t tiles)
 {
     const int64_t by_budget = (kQuadBudget - 4 * tiles) / 12;
