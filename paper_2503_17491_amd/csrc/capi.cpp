@@ -411,6 +411,10 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.stateT = take(4 * (size_t)L.pixels);
     L.stateN = take(4 * (size_t)L.pixels);
     L.census = take(16 * (size_t)L.pixels);
+    // one bit per (strip, list entry): four strips' 64-entry chunk words per chunk of the
+    // pair list, plus one spare chunk per tile (a tile's words start at its first chunk)
+    L.cmask_words = 4 * (L.cap / 64 + L.tiles + 2);
+    L.cmask = take(8 * (size_t)L.cmask_words);
     L.acc = take(4 * (size_t)L.acc_floats);
     L.scratch_pose = take(48 * (size_t)(nframes > 0 ? nframes : 1));
     L.misc = take(4096);

@@ -353,6 +353,35 @@ k_raster_fwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
 // have the same workgroup index modulo 8: workgroups are handed to the 8 XCDs
 // in turn, so a tile's strips share one XCD's L2 for the tile's records.
 // Returns false for the padding workgroups past the last tile.
+// Contribution mask: one bit per (strip, list entry), set by the one-wave
+// forward when some pixel of the strip composited the entry.  Word w of the
+// 64-entry chunks of tile t's list, strip s, sits at 4 (floor(start / 64) + t
+// + w) + s (start = the tile's first pair): tiles never share a word.
+__host__ __device__ inline int64_t cmask_word(int tile, int start, int strip, int chunk)
+{
+    return 4 * ((int64_t)(start >> 6) + tile + chunk) + strip;
+}
+
+// OR of a 64-bit value over the wave (every lane gets the result).
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64), hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        v |= ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+// A mask word (wave-uniform) in scalar registers; all ones without a mask.
+__device__ __forceinline__ uint64_t mask_word(const uint64_t *cm, int idx)
+{
+    if (!cm) return ~0ull;
+    const uint64_t w = cm[idx];
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(w >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)w);
+}
+
 __device__ __forceinline__ bool strip_of_block(int64_t ntiles, int &strip, int &tslot)
 {
     const int j = (int)(blockIdx.x & 31u);
@@ -385,7 +414,8 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
                                          const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                                          const double2 *__restrict__ tables, float *__restrict__ stT_all,
                                          int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all,
-                                         int64_t total_pixels, RasterRec *sbuf, uint8_t *sidx)
+                                         int64_t total_pixels, uint64_t *__restrict__ cmask, RasterRec *sbuf,
+                                         uint8_t *sidx)
 {
     const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -404,6 +434,8 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
+    // the words of the strip holding this sub-strip (its four sub-strips OR into them)
+    uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, sub >> 2, 0) : nullptr;
     // list entry c + lane travels as six 16-byte words in registers (a record
     // copied as a struct would be placed in scratch memory)
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -440,6 +472,7 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t contrib = 0;   // chunk entries this lane's pixel composited
         for (int q = 0; q < nact; q += 4) {
             if (__ballot(!done) == 0) break;
             const int k = q + slot;
@@ -466,12 +499,19 @@ __device__ __forceinline__ void fwd_quad(const FrameDesc &fd, int tile, int sub,
                             N2 = fmaf(w, sbuf[q + u].n[2], N2);
                             O += w;
                             T = tT;
-                            last = c + sidx[q + u] + 1 - rg.x;
+                            const int su = sidx[q + u];
+                            last = c + su + 1 - rg.x;
                             ++n_con;
+                            contrib |= 1ull << su;
                         }
                     }
                 }
             }
+        }
+        if (cm) {
+            contrib = wave_or64(contrib);
+            if (lane == 0 && contrib)
+                atomicOr(reinterpret_cast<unsigned long long *>(cm + 4 * ((c - rg.x) >> 6)), (unsigned long long)contrib);
         }
         __builtin_amdgcn_wave_barrier();   // sbuf is rewritten by the next chunk
     }
@@ -516,7 +556,8 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
                                            const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
                                            float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
                                            int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
-                                           int64_t nquad, RasterRec *sbuf, uint8_t *sidx)
+                                           int64_t nquad, uint64_t *__restrict__ cmask, RasterRec *sbuf,
+                                           uint8_t *sidx)
 {
     int strip, tslot;
     const int kind = fwd_work_of_block(b, ntiles, nquad, strip, tslot);
@@ -524,7 +565,7 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
     if (kind == 2) {
         const int qt = (int)order[tslot];
         fwd_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all, census_all,
-                 total_pixels, sbuf, sidx);
+                 total_pixels, cmask, sbuf, sidx);
         return;
     }
     const int tile = order ? (int)order[tslot] : tslot;
@@ -550,6 +591,8 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
     float T = 1.0f, D = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, O = 0.0f;
     int last = 0, n_eval = 0, n_con = 0;
     bool done = !inside;
+    // this strip's words of the contribution mask (one bit per list entry)
+    uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, strip, 0) : nullptr;
     RasterRec nxt;
     if (rg.x + lane < rg.y) nxt = rec[pval[rg.x + lane]];
     for (int c = rg.x; c < rg.y; c += 64) {
@@ -567,6 +610,8 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
         const int nact = __popcll(m);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         int q = 0;
+        uint64_t contrib = 0;   // chunk entries composited by some pixel of the strip (few-pixels mode)
+        uint64_t mine = 0;      // chunk entries this lane's pixel composited (many-pixels mode)
         if (__popcll(live) > kStragglers) {
             if (meets) { sbuf[rank] = r; sidx[rank] = (uint8_t)lane; }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -594,8 +639,10 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
                             N2 = fmaf(w, sbuf[k0].n[2], N2);
                             O += w;
                             T = tT;
-                            last = c + sidx[k0] + 1 - rg.x;
+                            const int s0 = sidx[k0];
+                            last = c + s0 + 1 - rg.x;
                             ++n_con;
+                            mine |= 1ull << s0;
                         }
                     }
                 }
@@ -613,19 +660,20 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
                             N2 = fmaf(w, sbuf[k1].n[2], N2);
                             O += w;
                             T = tT;
-                            last = c + sidx[k1] + 1 - rg.x;
+                            const int s1 = sidx[k1];
+                            last = c + s1 + 1 - rg.x;
                             ++n_con;
+                            mine |= 1ull << s1;
                         }
                     }
                 }
             }
             __builtin_amdgcn_wave_barrier();   // sbuf is rewritten by the next chunk
         }
-        if (q >= nact) continue;
         // few unfinished pixels: the chunk's remaining entries (compacted rank >= q)
         // are evaluated by their own lanes for one pixel at a time
         const bool rem = meets && rank >= q;
-        live = __ballot(!done);
+        live = q < nact ? __ballot(!done) : 0ull;
         while (live) {
             const int pl = (int)__builtin_ctzll(live);
             live &= live - 1;
@@ -658,11 +706,16 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
                 sT = tT;
                 sLast = c + jl + 1 - rg.x;
                 ++sCon;
+                contrib |= 1ull << jl;
             }
             if (lane == pl) {
                 T = sT; D = sD; N0 = sN0; N1 = sN1; N2 = sN2; O = sO;
                 last = sLast; n_eval += counted; n_con += sCon; done = sDone;
             }
+        }
+        if (cm) {
+            contrib |= wave_or64(mine);
+            if (lane == 0) cm[4 * ((c - rg.x) >> 6)] = contrib;   // this strip is the word's only writer
         }
     }
     if (inside) {
@@ -687,14 +740,15 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, float *__restrict__ stT_all, int32_t *__restrict__ stN_all,
                int32_t *__restrict__ census_all, int64_t total_pixels, int64_t ntiles,
-               const uint32_t *__restrict__ nquad_dev, uint32_t *__restrict__ queue, int64_t nitems)
+               const uint32_t *__restrict__ nquad_dev, uint64_t *__restrict__ cmask, uint32_t *__restrict__ queue,
+               int64_t nitems)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ uint8_t sidx[64];
     const int64_t nquad = (order && nquad_dev) ? (int64_t)*nquad_dev : 0;
     if (!QUEUE) {
         fwd_w_item((int64_t)blockIdx.x, descs, tile_frame, order, rec, pval, ranges, tables, stT_all, stN_all,
-                   census_all, total_pixels, ntiles, nquad, sbuf, sidx);
+                   census_all, total_pixels, ntiles, nquad, cmask, sbuf, sidx);
         return;
     }
     for (;;) {
@@ -703,7 +757,7 @@ k_raster_fwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
         const int64_t item = (int64_t)__shfl(v, 0, 64);
         if (item >= nitems) break;
         fwd_w_item(item, descs, tile_frame, order, rec, pval, ranges, tables, stT_all, stN_all, census_all,
-                   total_pixels, ntiles, nquad, sbuf, sidx);
+                   total_pixels, ntiles, nquad, cmask, sbuf, sidx);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -1026,7 +1080,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges, const double2 *__restrict__ tables,
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
-             double *__restrict__ pose_part, int pose_only, uint32_t *__restrict__ queue, int ntiles)
+             double *__restrict__ pose_part, int pose_only, uint32_t *__restrict__ queue, int ntiles,
+             const uint64_t *__restrict__ cmask)
 {
     __shared__ RasterRec srec[BATCH];
     __shared__ ChatRec schat[BATCH];
@@ -1119,7 +1174,9 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                 bool meets = false;
                 if (kk < cnt) {
                     const uint32_t rows = srec[kk].rows;
-                    meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
+                    const int pos = b0 + kk - rg.x;
+                    meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && pos < wlast &&
+                            (!cmask || ((cmask[cmask_word(tile, rg.x, wid, pos >> 6)] >> (pos & 63)) & 1ull));
                 }
                 const uint64_t m = __ballot(meets);
                 if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -1229,7 +1286,8 @@ __device__ __forceinline__ void bwd_quad(const FrameDesc &fd, int tile, int sub,
                                          const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                                          const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all,
                                          int64_t total_pixels, double *prow, int frame, int pose_only,
-                                         RasterRec *sbuf, ChatRec *schat, float (*sred)[64], uint8_t *slist)
+                                         const uint64_t *__restrict__ cmask, RasterRec *sbuf, ChatRec *schat,
+                                         float (*sred)[64], uint8_t *slist)
 {
     const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -1268,10 +1326,14 @@ __device__ __forceinline__ void bwd_quad(const FrameDesc &fd, int tile, int sub,
     float *acc_base = pose_only ? nullptr : fd.acc;
     const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the sub-strip
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    // the words of the strip holding this sub-strip: entries no pixel of the strip
+    // composited are not walked
+    const uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, sub >> 2, 0) : nullptr;
     for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
         bool meets = false;
         uint32_t id = 0;
-        if (c + lane < end) {
+        const uint64_t cw = mask_word(cm, 4 * ((c - rg.x) >> 6));
+        if (c + lane < end && ((cw >> lane) & 1ull)) {
             id = pval[c + lane];
             const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + id);
             u32x4 w[6];
@@ -1388,14 +1450,14 @@ __device__ __forceinline__ void bwd_quad(const FrameDesc &fd, int tile, int sub,
 // list): each of them in turn takes the wave, the lanes evaluate their own
 // records for it and the contributing ones are visited in reverse order.  At
 // the end of a chunk every lane flushes its own record's sums.
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 3)   // 3 waves per SIMD: at most 168 VGPRs
 k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
                const uint32_t *__restrict__ order,
                const RasterRec *__restrict__ rec, const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
                double *__restrict__ pose_part, int pose_only, int64_t ntiles,
-               const uint32_t *__restrict__ nquad_dev)
+               const uint32_t *__restrict__ nquad_dev, const uint64_t *__restrict__ cmask)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ ChatRec schat[64];
@@ -1411,7 +1473,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     if (kind == 2) {
         const int qt = (int)order[tslot];
         bwd_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all, census_all,
-                 total_pixels, pose_part + 8 * (size_t)blockIdx.x, tile_frame[qt], pose_only, sbuf, schat, sred, slist);
+                 total_pixels, pose_part + 8 * (size_t)blockIdx.x, tile_frame[qt], pose_only, cmask, sbuf, schat, sred,
+                 slist);
         return;
     }
     const int tile = order ? (int)order[tslot] : tslot;
@@ -1459,19 +1522,25 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     u32x4 nrec[6];
     uint32_t nid = 0;
-    if (c >= rg.x && c + lane < end) {
+    // this strip's words of the contribution mask: entries no pixel of the strip
+    // composited are neither read nor walked
+    const uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, strip, 0) : nullptr;
+    uint64_t cw = c >= rg.x ? mask_word(cm, 4 * ((c - rg.x) >> 6)) : ~0ull;
+    if (c >= rg.x && c + lane < end && ((cw >> lane) & 1ull)) {
         nid = pval[c + lane];
         const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
 #pragma unroll
         for (int f = 0; f < 6; ++f) nrec[f] = src[f];
     }
     for (; c >= rg.x; c -= 64) {
-        const bool inr = c + lane < end;
+        const bool inr = c + lane < end && ((cw >> lane) & 1ull);
         const uint32_t id = nid;
         bool meets = false;
         if (inr) {
             const uint32_t rows = nrec[5].w;
             meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+        }
+        if (meets) {
             u32x4 *dst = reinterpret_cast<u32x4 *>(&sbuf[lane]);
 #pragma unroll
             for (int f = 0; f < 6; ++f) dst[f] = nrec[f];
@@ -1480,7 +1549,8 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
         // keep the next chunk's loads below the staging arithmetic (their
         // registers would otherwise be live across it)
         __builtin_amdgcn_sched_barrier(0);
-        if (c - 64 >= rg.x) {   // the previous chunk's records, read while this one is processed
+        cw = c - 64 >= rg.x ? mask_word(cm, 4 * ((c - 64 - rg.x) >> 6)) : ~0ull;
+        if (c - 64 >= rg.x && ((cw >> lane) & 1ull)) {   // the previous chunk's records, read while this one is processed
             nid = pval[c - 64 + lane];
             const u32x4 *src = reinterpret_cast<const u32x4 *>(rec + nid);
 #pragma unroll
@@ -1619,7 +1689,7 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
             const uint32_t *__restrict__ order, const RasterRec *__restrict__ rec,
             const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
             const double2 *__restrict__ tables, const float *__restrict__ stT_all,
-            const int32_t *__restrict__ stN_all, double *__restrict__ gn_part)
+            const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, const uint64_t *__restrict__ cmask)
 {
     __shared__ RasterRec srec[kBwdBatch];
     __shared__ float sab[kBwdBatch][6];   // b_alpha, b_beta in FP32
@@ -1687,7 +1757,9 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
             bool meets = false;
             if (kk < cnt) {
                 const uint32_t rows = srec[kk].rows;
-                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && b0 + kk - rg.x < wlast;
+                const int pos = b0 + kk - rg.x;
+                meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1) && pos < wlast &&
+                        (!cmask || ((cmask[cmask_word(tile, rg.x, wid, pos >> 6)] >> (pos & 63)) & 1ull));
             }
             const uint64_t m = __ballot(meets);
             if (meets) slist[wid][nact + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -1850,7 +1922,8 @@ __device__ __forceinline__ void gn_quad(const FrameDesc &fd, int tile, int sub, 
                                         const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
                                         const double2 *__restrict__ tables, const float *__restrict__ stT_all,
                                         const int32_t *__restrict__ stN_all, double *row, int frame,
-                                        RasterRec *sbuf, float (*sab)[6], double *stau, uint8_t *slist)
+                                        const uint64_t *__restrict__ cmask, RasterRec *sbuf, float (*sab)[6],
+                                        double *stau, uint8_t *slist)
 {
     const int TW = fd.tw, TH = fd.th, tws = __builtin_ctz((unsigned)fd.tw);
     const int H = fd.H, W = fd.W, tiles_x = fd.tiles_x;
@@ -1879,12 +1952,17 @@ __device__ __forceinline__ void gn_quad(const FrameDesc &fd, int tile, int sub, 
     const BwdUpstream up = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, Tfin};   // dL/dD = 1
     float J[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     const int end = rg.x + wlast;
+    // the words of the strip holding this sub-strip: entries no pixel of the strip composited are skipped
+    const uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, sub >> 2, 0) : nullptr;
     for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
         bool meets = false;
-        if (c + lane < end) {
+        const uint64_t cw = mask_word(cm, 4 * ((c - rg.x) >> 6));
+        if (c + lane < end && ((cw >> lane) & 1ull)) {
             sbuf[lane] = rec[pval[c + lane]];
             const uint32_t rows = sbuf[lane].rows;
             meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+        }
+        if (meets) {
             double ba[3], bb[3], bc[3];
             record_axes(sbuf[lane], ba, bb, bc);
 #pragma unroll
@@ -1960,7 +2038,7 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
               const uint32_t *__restrict__ pval, const int2 *__restrict__ ranges,
               const double2 *__restrict__ tables, const float *__restrict__ stT_all,
               const int32_t *__restrict__ stN_all, double *__restrict__ gn_part, int64_t ntiles,
-              const uint32_t *__restrict__ nquad_dev)
+              const uint32_t *__restrict__ nquad_dev, const uint64_t *__restrict__ cmask)
 {
     __shared__ RasterRec sbuf[64];
     __shared__ float sab[64][6];   // b_alpha, b_beta in FP32
@@ -1973,7 +2051,8 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
     if (kind == 2) {   // 16 rows per quad tile, in sub-strip order
         const int qt = (int)order[tslot];
         gn_quad(descs[tile_frame[qt]], qt, strip, rec, pval, ranges, tables, stT_all, stN_all,
-                gn_part + (size_t)kGnRow * (16 * (size_t)tslot + strip), tile_frame[qt], sbuf, sab, stau, slist);
+                gn_part + (size_t)kGnRow * (16 * (size_t)tslot + strip), tile_frame[qt], cmask, sbuf, sab, stau,
+                slist);
         return;
     }
     const int tile = order ? (int)order[tslot] : tslot;
@@ -2006,12 +2085,17 @@ k_raster_gn_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ t
     const BwdUpstream up = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, Tfin};   // dL/dD = 1
     float J[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     const int end = rg.x + wlast;   // entries at or beyond end precede no contributor of the strip
+    // this strip's words of the contribution mask: entries no pixel of the strip composited are skipped
+    const uint64_t *cm = cmask ? cmask + cmask_word(tile, rg.x, strip, 0) : nullptr;
     for (int c = wlast > 0 ? rg.x + ((wlast - 1) & ~63) : rg.x - 64; c >= rg.x; c -= 64) {
         bool meets = false;
-        if (c + lane < end) {
+        const uint64_t cw = mask_word(cm, 4 * ((c - rg.x) >> 6));
+        if (c + lane < end && ((cw >> lane) & 1ull)) {
             sbuf[lane] = rec[pval[c + lane]];
             const uint32_t rows = sbuf[lane].rows;
             meets = !((int)(rows >> 16) < wr0 || (int)(rows & 0xffffu) > wr1);
+        }
+        if (meets) {
             double ba[3], bb[3], bc[3];
             record_axes(sbuf[lane], ba, bb, bc);
 #pragma unroll
@@ -2087,6 +2171,8 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
         uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQueueFwd);
         const int64_t grid = queue ? resident_grid(kern, 64, items) : items;
         if (queue) launch_fill_u32(counter, 0u, 1, stream);
+        uint64_t *cmask = reinterpret_cast<uint64_t *>(ws + L.cmask);
+        launch_fill_u32(cmask, 0u, 2 * L.cmask_words, stream);   // the quad sub-strips OR into their strip's words
         hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame),
@@ -2096,7 +2182,7 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
                            reinterpret_cast<float *>(ws + L.stateT), reinterpret_cast<int32_t *>(ws + L.stateN),
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels, L.tiles,
                            longest ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr,
-                           counter, items);
+                           cmask, counter, items);
         return;
     }
     hipLaunchKernelGGL(L.variant == SLR_VARIANT_SCALAR ? k_raster_fwd_s : k_raster_fwd,
@@ -2108,9 +2194,16 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
                        reinterpret_cast<int32_t *>(ws + L.stateN), reinterpret_cast<int32_t *>(ws + L.census), L.pixels);
 }
 
+// The contribution mask, when the forward that preceded (same layout) wrote one.
+inline const uint64_t *contribution_mask(const Layout &L, const char *ws)
+{
+    return L.variant == SLR_VARIANT_WAVE ? reinterpret_cast<const uint64_t *>(ws + L.cmask) : nullptr;
+}
+
 void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    const uint64_t *cmask = contribution_mask(L, ws);
     const bool wave = L.bwd_variant == SLR_VARIANT_WAVE;
     const uint32_t *ord = longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (wave) {
@@ -2123,7 +2216,7 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                            reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                            reinterpret_cast<int32_t *>(ws + L.census), L.pixels,
                            reinterpret_cast<double *>(ws + L.pose_part), pose_only ? 1 : 0, L.tiles,
-                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
+                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr, cmask);
         return;
     }
     const bool queue = L.schedule == SLR_SCHEDULE_QUEUE;
@@ -2138,12 +2231,13 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<double *>(ws + L.pose_part),
-                       pose_only ? 1 : 0, counter, (int)L.tiles);
+                       pose_only ? 1 : 0, counter, (int)L.tiles, cmask);
 }
 
 void gn_launch(const Layout &L, char *ws, hipStream_t stream)
 {
     const uint32_t *pval = reinterpret_cast<const uint32_t *>(ws + (L.tile_in_1 ? L.pv1 : L.pv0));
+    const uint64_t *cmask = contribution_mask(L, ws);
     const uint32_t *ord = longest_order(L) ? reinterpret_cast<const uint32_t *>(ws + L.order) : nullptr;
     if (L.bwd_variant == SLR_VARIANT_WAVE) {
         const int64_t grid = wave_blocks(L.tiles) + (ord ? 16 * quad_tile_cap(L.tiles) : 0);
@@ -2154,14 +2248,14 @@ void gn_launch(const Layout &L, char *ws, hipStream_t stream)
                            reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                            reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                            reinterpret_cast<double *>(ws + L.gn_part), L.tiles,
-                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr);
+                           ord ? reinterpret_cast<const uint32_t *>(ws + L.misc + kMiscQuadTiles) : nullptr, cmask);
         return;
     }
     hipLaunchKernelGGL(k_raster_gn, dim3((unsigned)L.tiles), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), reinterpret_cast<const int32_t *>(ws + L.tile_frame),
                        ord, reinterpret_cast<const RasterRec *>(ws + L.rec), pval, reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
-                       reinterpret_cast<double *>(ws + L.gn_part));
+                       reinterpret_cast<double *>(ws + L.gn_part), cmask);
 }
 
 }  // namespace

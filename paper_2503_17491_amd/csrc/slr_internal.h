@@ -128,6 +128,8 @@ struct Layout {
     bool depth_in_1, tile_in_1;
     size_t desc, tables, tile_frame, rec, box, skey, key0, val0, key1, val1, cnt, off, estart, blocksum;
     size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
+    size_t cmask;          // contribution mask of the one-wave forward (cmask_words u64)
+    int64_t cmask_words;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
