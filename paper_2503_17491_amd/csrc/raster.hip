@@ -373,6 +373,14 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
     return v;
 }
 
+// Whether some strip of the tile composited list entry pos (true without a mask).
+__device__ __forceinline__ bool any_strip_wants(const uint64_t *cmask, int tile, int start, int pos)
+{
+    if (!cmask) return true;
+    const uint64_t *w = cmask + cmask_word(tile, start, 0, pos >> 6);
+    return (((w[0] | w[1] | w[2] | w[3]) >> (pos & 63)) & 1ull) != 0;
+}
+
 // A mask word (wave-uniform) in scalar registers; all ones without a mask.
 __device__ __forceinline__ uint64_t mask_word(const uint64_t *cm, int idx)
 {
@@ -1160,7 +1168,8 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             const int b0 = max(rg.x, b_end - BATCH);
             const int cnt = b_end - b0;
             __syncthreads();
-            if ((int)threadIdx.x < cnt) {
+            // records no strip walks are not staged (no wave's compaction takes them)
+            if ((int)threadIdx.x < cnt && any_strip_wants(cmask, tile, rg.x, b0 + (int)threadIdx.x - rg.x)) {
                 const uint32_t id = pval[b0 + threadIdx.x];
                 srec[threadIdx.x] = rec[id];
                 centre_dir(srec[threadIdx.x], schat[threadIdx.x]);
@@ -1738,7 +1747,8 @@ k_raster_gn(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ til
         const int b0 = max(rg.x, b_end - kBwdBatch);
         const int cnt = b_end - b0;
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
+        // records no strip walks are not staged (no wave's compaction takes them)
+        if ((int)threadIdx.x < cnt && any_strip_wants(cmask, tile, rg.x, b0 + (int)threadIdx.x - rg.x)) {
             const uint32_t id = pval[b0 + threadIdx.x];
             srec[threadIdx.x] = rec[id];
             double ba[3], bb[3], bc[3];
