@@ -327,11 +327,14 @@ slr_status slr_batch_autotune(int32_t n_sets, const slr_surfels *sets, const slr
                               int32_t n_candidates, int64_t pair_capacity, void *workspace, size_t workspace_bytes,
                               int32_t reps, double *ms, int32_t *best, void *stream);
 
-/* Device address of four uint64 words in the workspace (the per-tile lists
- * of Sec. 3.2.1): the pair count K
- * of the last render, the overflow word (K when K > pair_capacity, else 0),
- * the pair count actually binned and the number of surfel records that bin
- * into at least one tile. */
+/* Device address of seven uint64 words in the workspace (the per-tile lists
+ * of Sec. 3.2.1): [0] the pair count K of the last render, [1] the overflow
+ * word (K when K > pair_capacity, else 0), [2] the pair count actually
+ * binned, [3] the number of surfel records that bin into at least one tile,
+ * [4], [5] internal scheduling words, [6] the number of (frame, surfel)
+ * records culled for invalid parameters (a non-finite mean, quaternion,
+ * log-scale or logit, or a zero quaternion); such a surfel takes no part in
+ * the render and gets zero gradients. */
 slr_status slr_batch_counters(int32_t n_sets, const slr_surfels *sets, int32_t n_frames, const slr_frame *frames,
                               const slr_tiling *tiling, int64_t pair_capacity, void *workspace,
                               size_t workspace_bytes, const uint64_t **counters);

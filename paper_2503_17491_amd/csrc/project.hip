@@ -271,7 +271,8 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
 __global__ void __launch_bounds__(256)
 k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ tables, double cm, double sm,
           RasterRec *__restrict__ rec, PixBox *__restrict__ box,
-          uint32_t *__restrict__ keys, int32_t *__restrict__ counts, int box_mode)
+          uint32_t *__restrict__ keys, int32_t *__restrict__ counts, int box_mode,
+          unsigned long long *__restrict__ n_invalid)
 {
     const FrameDesc &fd = descs[blockIdx.y];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,6 +290,7 @@ k_project(const FrameDesc *__restrict__ descs, const double2 *__restrict__ table
     double w = fq.x, x = fq.y, y = fq.z, z = fq.w;
     double qq = ((w * w + x * x) + y * y) + z * z;
     bool ok = fin && qq > 0.0;
+    if (!ok) atomicAdd(n_invalid, 1ull);   // culled: a non-finite parameter or a zero quaternion (rare)
     double rad = 3.0;
     if (ok && box_mode == SLR_BOX_OPACITY) {
         rad = support_radius((double)flg);
@@ -416,6 +418,7 @@ void launch_tile_frame(const Layout &L, char *ws, hipStream_t stream)
 
 void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream)
 {
+    launch_fill_u32(ws + L.misc + kMiscInvalid, 0u, 2, stream);
     if (max_n <= 0 || L.frames == 0) return;
     const int blocks = (int)((max_n + 255) / 256);
     hipLaunchKernelGGL(k_project, dim3(blocks, L.frames), dim3(256), 0, stream,
@@ -423,7 +426,8 @@ void launch_project(const Layout &L, char *ws, int64_t max_n, hipStream_t stream
                        cos(kBoxMargin), sin(kBoxMargin), reinterpret_cast<RasterRec *>(ws + L.rec),
                        reinterpret_cast<PixBox *>(ws + L.box),
                        reinterpret_cast<uint32_t *>(ws + L.skey),
-                       reinterpret_cast<int32_t *>(ws + L.cnt), (int)L.box_mode);
+                       reinterpret_cast<int32_t *>(ws + L.cnt), (int)L.box_mode,
+                       reinterpret_cast<unsigned long long *>(ws + L.misc + kMiscInvalid));
 }
 
 }  // namespace slr

@@ -106,6 +106,7 @@ constexpr int64_t kQuadBudget = 8192;
 constexpr size_t kMiscQuadTiles = 32;
 constexpr size_t kMiscQueue = 40;      // u32 work-queue head of the persistent workgroup backward
 constexpr size_t kMiscQueueFwd = 44;   // u32 work-queue head of the persistent one-wave forward
+constexpr size_t kMiscInvalid = 48;    // u64 records culled for invalid parameters (counter word 6)
 __host__ __device__ inline int64_t quad_tile_cap(int64_t tiles)
 {
     const int64_t by_budget = (kQuadBudget - 4 * tiles) / 12;

@@ -5,6 +5,7 @@ provides device memory and the current stream.  If the library is missing the
 import fails loudly: there is no fallback path.
 """
 import ctypes as C
+import json
 import math
 import os
 
@@ -310,6 +311,49 @@ TUNE_CANDIDATES = [(th, tw, VARIANT_WAVE, SCHEDULE_LONGEST, bv) for th, tw in ((
                                                              (32, 8, VARIANT_WAVE, SCHEDULE_QUEUE, VARIANT_LDS)]
 _tuned = {}   # image-size class -> tiling chosen by the autotuner
 
+# The autotuner's choices persist across processes in a JSON file when
+# SLR_AUTOTUNE_CACHE names one: one entry per (device name, frame image sizes,
+# set sizes), the chosen tiling as a list.  A missing or unreadable file is an
+# empty cache; entries are written by replacing the file.
+AUTOTUNE_CACHE_ENV = "SLR_AUTOTUNE_CACHE"
+
+
+def _cache_key(key, device_name):
+    frames, sets = key
+    return json.dumps({"device": device_name, "frames": [list(f) for f in frames], "sets": list(sets)},
+                      sort_keys=True)
+
+
+def _cache_read(path):
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def autotune_cache_lookup(key, device_name, path=None):
+    """The cached tiling of an image-size class on a device, or None."""
+    path = path or os.environ.get(AUTOTUNE_CACHE_ENV)
+    if not path:
+        return None
+    t = _cache_read(path).get(_cache_key(key, device_name))
+    return tuple(int(x) for x in t) if isinstance(t, list) and len(t) >= 5 else None
+
+
+def autotune_cache_store(key, device_name, tiling, path=None):
+    """Record the tiling of an image-size class on a device (no-op without a path)."""
+    path = path or os.environ.get(AUTOTUNE_CACHE_ENV)
+    if not path:
+        return
+    data = _cache_read(path)
+    data[_cache_key(key, device_name)] = [int(x) for x in tiling]
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
 
 class BatchRenderer:
     """Batched form: many frames (each its own pose, sensor and image size;
@@ -331,6 +375,10 @@ class BatchRenderer:
         self._key = (tuple((int(f["sensor"]["height"]), int(f["sensor"]["width"])) for f in frames),
                      tuple(int(st["means"].shape[0]) for st in sets))
         auto = isinstance(tiling, str) and tiling == "auto"
+        if auto and self._key not in _tuned:
+            cached = autotune_cache_lookup(self._key, torch.cuda.get_device_name(device))
+            if cached is not None:
+                _tuned[self._key] = cached
         self.tiling = _tuned.get(self._key, TUNE_CANDIDATES[0]) if auto else tuple(tiling)
         self.capacity = int(capacity)
         self.device = device
@@ -433,6 +481,7 @@ class BatchRenderer:
                                         C.byref(best), _stream()), "slr_batch_autotune")
         self.tiling = cands[best.value]
         _tuned[self._key] = self.tiling
+        autotune_cache_store(self._key, torch.cuda.get_device_name(self.device), self.tiling)
         self.prepare()
         return {c: ms[k] for k, c in enumerate(cands)}
 
@@ -450,7 +499,7 @@ class BatchRenderer:
         _check(lib().slr_batch_counters(*self._args(), _ptr(self.ws), self.ws.numel(), C.byref(ptr)),
                "slr_batch_counters")
         off = ptr.value - self.ws.data_ptr()
-        self.counters = self.ws[off:off + 32].view(torch.int64)
+        self.counters = self.ws[off:off + 56].view(torch.int64)
 
     def render(self):
         _check(lib().slr_batch_render(*self._args(), _ptr(self.ws), self.ws.numel(), _stream()), "slr_batch_render")
@@ -500,6 +549,11 @@ class BatchRenderer:
     def binned_records(self):
         """Number of surfel records of the last render that bin into some tile (synchronises)."""
         return int(self.counters[3].cpu())
+
+    def invalid_records(self):
+        """Number of (frame, surfel) records of the last render culled for a non-finite
+        parameter or a zero quaternion (synchronises)."""
+        return int(self.counters[6].cpu())
 
     def ensure_capacity(self, margin=1.25):
         """Grow the pair capacity if the last render overflowed; True if it did."""

@@ -226,3 +226,27 @@ def test_loss_frames_rejects_bad_arguments_without_gpu():
     # an image without pixels needs no buffers
     arr = (slr.LossFrame * 1)(slr.LossFrame(0, None, None, None, None, 1.0, 1.0, None, None))
     assert L.slr_loss_l1_normal_frames(1, arr, None, None) != slr.SLR_E_INVALID
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """The persistent autotune cache: a tiling stored for an image-size class
+    and device is found again (also through the environment variable), other
+    classes and devices miss, and an unreadable file is an empty cache."""
+    path = str(tmp_path / "tune.json")
+    key = (((128, 1024), (64, 512)), (1000000,))
+    assert slr.autotune_cache_lookup(key, "gpu-a", path) is None
+    slr.autotune_cache_store(key, "gpu-a", (32, 8, 3, 2, 1, 0, 192), path)
+    assert slr.autotune_cache_lookup(key, "gpu-a", path) == (32, 8, 3, 2, 1, 0, 192)
+    assert slr.autotune_cache_lookup(key, "gpu-b", path) is None
+    assert slr.autotune_cache_lookup((((128, 1024),), (1000000,)), "gpu-a", path) is None
+    slr.autotune_cache_store(key, "gpu-b", (16, 16, 3, 2, 3, 0), path)
+    assert slr.autotune_cache_lookup(key, "gpu-a", path) == (32, 8, 3, 2, 1, 0, 192)
+    monkeypatch.setenv(slr.AUTOTUNE_CACHE_ENV, path)
+    assert slr.autotune_cache_lookup(key, "gpu-b") == (16, 16, 3, 2, 3, 0)
+    with open(path, "w") as f:
+        f.write("{ not json")
+    assert slr.autotune_cache_lookup(key, "gpu-a") is None
+    slr.autotune_cache_store(key, "gpu-a", (8, 32, 3, 2, 1, 0), path)
+    assert slr.autotune_cache_lookup(key, "gpu-a") == (8, 32, 3, 2, 1, 0)
+    monkeypatch.delenv(slr.AUTOTUNE_CACHE_ENV)
+    assert slr.autotune_cache_lookup(key, "gpu-a") is None   # no path: process-local only

@@ -129,6 +129,48 @@ def test_queue_schedule_matches_longest(slr, batch):
         np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=1e-6, atol=1e-12)
 
 
+def test_invalid_surfels_counted_and_inert(slr):
+    """Surfels with a non-finite parameter or a zero quaternion are culled in
+    every frame that renders their set, counted in the batch's counter word,
+    and take no part: finite images and gradients, zero gradients for them."""
+    say("invalid surfels: counted, culled, zero gradients")
+    sc = synth.shell_scene(5000, 41)
+    bad = {3: ("means", 0, np.nan), 10: ("quats", None, 0.0), 17: ("log_scales", 1, np.inf),
+           25: ("logits", None, np.nan), 31: ("quats", 2, -np.inf), 44: ("means", 2, np.inf)}
+    for i, (key, col, val) in bad.items():
+        if col is None:
+            sc[key][i] = val
+        else:
+            sc[key][i, col] = val
+    other = synth.shell_scene(3000, 42)
+    sets = [dev_set(sc), dev_set(other)]
+    poses = synth.circle_poses(3, 5)
+    frames = [dict(set=0, T_cw=torch.from_numpy(poses[0]).to(DEV), sensor=slr.make_sensor(64, 512)),
+              dict(set=1, T_cw=torch.from_numpy(poses[1]).to(DEV), sensor=slr.make_sensor(32, 1024)),
+              dict(set=0, T_cw=torch.from_numpy(poses[2]).to(DEV), sensor=slr.make_sensor(64, 1024))]
+    br = slr.BatchRenderer(sets, frames, (16, 16), 1 << 20)
+    upstream(br, 5)
+    br.render()
+    br.backward()
+    torch.cuda.synchronize()
+    assert br.invalid_records() == 2 * len(bad)   # two frames render the set with the invalid surfels
+    for o in br.out:
+        for t in o:
+            assert torch.isfinite(t).all()
+    idx = torch.tensor(sorted(bad), device=DEV)
+    for key, g in br.grads[0].items():
+        assert torch.isfinite(g).all(), key
+        assert (g[idx] == 0).all(), key
+    for d in br.dpose:
+        assert torch.isfinite(d).all()
+    # a clean render counts none
+    sets[0] = dev_set(synth.shell_scene(5000, 41))
+    br2 = slr.BatchRenderer(sets, frames, (16, 16), 1 << 20)
+    br2.render()
+    torch.cuda.synchronize()
+    assert br2.invalid_records() == 0
+
+
 MIXED_TILES = [(8, 32), (4, 64), (32, 8), (16, 16)]
 
 
