@@ -95,7 +95,7 @@ def test_batched_matches_plain(slr, tiling):
         assert np.abs(a - b).max() <= 1e-4 * scale, key
 
 
-@pytest.mark.parametrize("batch", [128, 192])
+@pytest.mark.parametrize("batch", [128, 192, "wave"])
 def test_queue_schedule_matches_longest(slr, batch):
     """The persistent workgroup backward (tiles taken from a device work queue
     by an occupancy-sized grid) against the same kernel launched one
@@ -104,7 +104,9 @@ def test_queue_schedule_matches_longest(slr, batch):
     say("work-queue backward vs one workgroup per tile, batch", batch)
     res = []
     for sched in (slr.SCHEDULE_LONGEST, slr.SCHEDULE_QUEUE):
-        tiling = (32, 8, slr.VARIANT_WAVE, sched, slr.VARIANT_LDS, 0, batch)
+        # "wave": the one-wave backward (not persistent) after the persistent forward
+        tiling = ((32, 8, slr.VARIANT_WAVE, sched, slr.VARIANT_WAVE, 0, 0) if batch == "wave"
+                  else (32, 8, slr.VARIANT_WAVE, sched, slr.VARIANT_LDS, 0, batch))
         sets, frames, _, br = make_batch(slr, tiling)
         upstream(br, 3)
         for _ in range(2):   # a second step: the queue head is reset before every launch
