@@ -2182,7 +2182,9 @@ void fwd_launch(const Layout &L, char *ws, hipStream_t stream)
         const int64_t grid = queue ? resident_grid(kern, 64, items) : items;
         if (queue) launch_fill_u32(counter, 0u, 1, stream);
         uint64_t *cmask = reinterpret_cast<uint64_t *>(ws + L.cmask);
-        launch_fill_u32(cmask, 0u, 2 * L.cmask_words, stream);   // the quad sub-strips OR into their strip's words
+        // a strip stores the word of every chunk it walks (and the backward reads no
+        // other); only quad sub-strips OR into their strip's words, which must start clear
+        if (longest && quad_tile_cap(L.tiles) > 0) launch_fill_u32(cmask, 0u, 2 * L.cmask_words, stream);
         hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), 0, stream,
                            reinterpret_cast<const FrameDesc *>(ws + L.desc),
                            reinterpret_cast<const int32_t *>(ws + L.tile_frame),
