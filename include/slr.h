@@ -83,7 +83,15 @@ typedef struct slr_sensor {
  * identical to 2).  bwd_variant selects the form of
  * the compositing backward: 0 = the same as variant (the library default if
  * that is 0), 1 = one workgroup per tile (records staged through LDS, one
- * flush per tile and record), 3 = one wave per 64-pixel strip.  Every variant
+ * flush per tile and record), 3 = one wave per 64-pixel strip, 4 = the
+ * fixed-order (deterministic) form of 1: the four waves' sums of a record
+ * added in wave order, each (tile, record) flush written with plain stores
+ * to a slot of its own (no floating-point atomics) and the slots of every
+ * surfel summed by a gather kernel, frames in batch order and a record's
+ * tiles in binning order, so the surfel and pose gradients are bit-identical
+ * from run to run and for every schedule and forward variant (it stages 64
+ * records per batch, ignoring bwd_batch, and the workspace grows by 64 bytes
+ * per pair of capacity and 4 bytes per record).  Every variant
  * and schedule produces bit-identical forward outputs.  box selects the
  * bounding box of a surfel (Sec. 3.2.3, Supp. B): 0 = the exact angular box
  * of its 3-sigma square; 1 = the same box of the smaller square that can
@@ -110,6 +118,7 @@ typedef struct slr_tiling {
 #define SLR_VARIANT_LDS 1
 #define SLR_VARIANT_SCALAR 2
 #define SLR_VARIANT_WAVE 3
+#define SLR_VARIANT_DETERMINISTIC 4   /* bwd_variant only */
 #define SLR_SCHEDULE_DEFAULT 0
 #define SLR_SCHEDULE_TILE 1
 #define SLR_SCHEDULE_LONGEST 2

@@ -397,20 +397,14 @@ k_emit(const FrameDesc *__restrict__ descs, const uint32_t *__restrict__ order, 
         const uint32_t r = k0 + (uint32_t)i;
         const PixBox b = rbox[r];
         const FrameDesc &fd = descs[b.frame];
-        const int th = fd.th, tw = fd.tw;
-        int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
-        int bx0 = 0, bx1 = -1;
-        if (b.c2 >= 0) {
-            bx0 = b.c2 / tw; bx1 = b.c3 / tw;
-            if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
-        }
+        const TileSpan sp = tile_span(b, fd.th, fd.tw);
         s_off[i] = offsets[r];
         s_id[i] = order[r];
-        s_ty0[i] = b.r0 / th;
-        s_ax0[i] = ax0;
-        s_na[i] = ax1 - ax0 + 1;
-        s_bx0[i] = bx0;
-        s_len[i] = (ax1 - ax0 + 1) + (bx1 - bx0 + 1);
+        s_ty0[i] = sp.ty0;
+        s_ax0[i] = sp.ax0;
+        s_na[i] = sp.na;
+        s_bx0[i] = sp.bx0;
+        s_len[i] = sp.len;
         s_tx[i] = fd.tiles_x;
         s_row0[i] = (uint32_t)fd.tile_off;
     }
@@ -460,9 +454,12 @@ k_ranges(const uint32_t *__restrict__ ptile, const uint64_t *__restrict__ keff, 
 // half-octave scale (bucket 0 = empty) and written out in descending bucket
 // order, so the compositing kernels, which take tile order[blockIdx.x], start
 // the long lists first and fill the end of the launch with short ones.  One
-// workgroup; order within a bucket is arbitrary (it only changes which
-// workgroup runs first, never what a tile computes).
+// workgroup.  Within a bucket the tiles keep their index order (a stable
+// counting sort), so the order depends only on the list lengths: the partial
+// rows the compositing kernels write per tile slot, which fixed-order
+// reductions add up slot by slot, then come out the same on every render.
 constexpr int kOrderBuckets = 65;
+constexpr int kOrderThreads = 1024;
 
 __device__ __forceinline__ int order_bucket(int len)
 {
@@ -472,11 +469,13 @@ __device__ __forceinline__ int order_bucket(int len)
     return 1 + 2 * e + half;
 }
 
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kOrderThreads)
 k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restrict__ order,
              uint32_t *__restrict__ nquad)
 {
+    constexpr int kW = kOrderThreads / 64;
     __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ uint32_t wcnt[kW][kOrderBuckets];   // per wave of a chunk: its tiles per bucket, then their first slot
     for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     for (int64_t t = threadIdx.x; t < tiles; t += blockDim.x) {
@@ -500,10 +499,45 @@ k_tile_order(const int2 *__restrict__ ranges, int64_t tiles, uint32_t *__restric
         const uint64_t n8 = ((uint64_t)nl + 7) & ~uint64_t(7);
         *nquad = (uint32_t)(n8 < cap ? n8 : cap);
     }
-    __syncthreads();
-    for (int64_t t = threadIdx.x; t < tiles; t += blockDim.x) {
-        const int2 r = ranges[t];
-        order[atomicAdd(&hist[order_bucket(r.y - r.x)], 1u)] = (uint32_t)t;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    // chunks of kOrderThreads tiles in index order; in a chunk, waves in order
+    // and lanes in order: a tile's slot is its bucket's next free slot plus the
+    // tiles of its bucket before it in the chunk
+    for (int64_t base = 0; base < tiles; base += kOrderThreads) {
+        for (int e = threadIdx.x; e < kW * kOrderBuckets; e += blockDim.x) (&wcnt[0][0])[e] = 0u;
+        __syncthreads();
+        const int64_t t = base + threadIdx.x;
+        int b = -1;
+        if (t < tiles) {
+            const int2 r = ranges[t];
+            b = order_bucket(r.y - r.x);
+        }
+        // the lanes of this wave with the same bucket (one ballot per distinct bucket)
+        uint64_t peers = 0;
+        uint64_t todo = __ballot(b >= 0);
+        while (todo) {
+            const int lb = __shfl(b, __ffsll((unsigned long long)todo) - 1, 64);
+            const uint64_t m = __ballot(b == lb);
+            if (b == lb) peers = m;
+            todo &= ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (b >= 0 && rank == 0) wcnt[wid][b] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if ((int)threadIdx.x < kOrderBuckets) {
+            const int bb = threadIdx.x;
+            uint32_t acc = hist[bb];
+            for (int w = 0; w < kW; ++w) {
+                const uint32_t c = wcnt[w][bb];
+                wcnt[w][bb] = acc;
+                acc += c;
+            }
+            hist[bb] = acc;
+        }
+        __syncthreads();
+        if (b >= 0) order[wcnt[wid][b] + rank] = (uint32_t)t;
+        __syncthreads();
     }
 }
 
@@ -583,7 +617,7 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
 static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)
 {
     if (!longest_order(L) || L.tiles == 0) return;
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, reinterpret_cast<const int2 *>(ws + L.ranges),
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, stream, reinterpret_cast<const int2 *>(ws + L.ranges),
                        L.tiles, reinterpret_cast<uint32_t *>(ws + L.order),
                        reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQuadTiles));
 }

@@ -88,8 +88,9 @@ slr_status check_tiling(const slr_tiling *t)
     if (!tile_shape_ok(t->tile_h, t->tile_w)) return fail(SLR_E_INVALID, "unsupported tile shape %dx%d", t->tile_h, t->tile_w);
     if (t->variant < SLR_VARIANT_DEFAULT || t->variant > SLR_VARIANT_WAVE)
         return fail(SLR_E_INVALID, "unknown compositing variant %d", t->variant);
-    if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE)
-        return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1 or 3)", t->bwd_variant);
+    if (t->bwd_variant != SLR_VARIANT_DEFAULT && t->bwd_variant != SLR_VARIANT_LDS && t->bwd_variant != SLR_VARIANT_WAVE &&
+        t->bwd_variant != SLR_VARIANT_DETERMINISTIC)
+        return fail(SLR_E_INVALID, "unknown backward variant %d (0, 1, 3 or 4)", t->bwd_variant);
     if (t->bwd_batch != 0 && t->bwd_batch != 128 && t->bwd_batch != 192)
         return fail(SLR_E_INVALID, "unsupported backward batch %d (0, 128 or 192)", t->bwd_batch);
     if (t->schedule < SLR_SCHEDULE_DEFAULT || t->schedule > SLR_SCHEDULE_QUEUE)
@@ -215,7 +216,8 @@ slr_status check_batch(int32_t n_sets, const slr_surfels *sets, int32_t n_frames
         if (sets[fr.set].n > b->max_n) b->max_n = sets[fr.set].n;
     }
     if (items >= (int64_t(1) << 31)) return fail(SLR_E_INVALID, "batch has %lld records, limit 2^31", (long long)items);
-    b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w);
+    b->L = slr::make_layout(n_frames, b->geom.data(), n_sets, b->set_n.data(), cap, tiling->tile_h, tiling->tile_w,
+                            tiling->bwd_variant == SLR_VARIANT_DETERMINISTIC);
     b->L.variant = tiling->variant == SLR_VARIANT_DEFAULT ? slr::kDefaultVariant : tiling->variant;
     // the backward form: as asked, else the forward's (the scalar-cache forward pairs with the workgroup backward)
     b->L.bwd_variant = tiling->bwd_variant != SLR_VARIANT_DEFAULT ? tiling->bwd_variant
@@ -318,7 +320,16 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
                       bool pose_only, bool accumulate, hipStream_t s)
 {
     const Layout &L = B.L;
-    if (!pose_only) slr::launch_fill_u32(ws + L.acc, 0u, L.acc_floats, s);
+    // the fixed-order form writes every accumulator entry it uses in its gather
+    const bool fixed = L.bwd_variant == SLR_VARIANT_DETERMINISTIC;
+    if (!pose_only) {
+        if (fixed) {
+            slr::launch_fill_u32(ws + L.slot_bits, 0u, L.slot_words, s);
+            slr::launch_record_rank(L, ws, s);
+        } else {
+            slr::launch_fill_u32(ws + L.acc, 0u, L.acc_floats, s);
+        }
+    }
     {
         StageScope t(5, s);
         slr::launch_raster_bwd(L, ws, pose_only, s);
@@ -329,6 +340,8 @@ void enqueue_backward(const Batch &B, const slr_surfels *sets, const slr_surfel_
     int64_t off = 0;
     for (int32_t k = 0; k < L.sets; ++k) {
         const slr_surfel_grads &g = grads[k];
+        if (g.means && fixed)
+            slr::launch_slot_gather(L, ws, k, sets[k].n, reinterpret_cast<float *>(ws + L.acc) + off, s);
         if (g.means)
             slr::launch_surfel_grad(sets[k].quats, sets[k].log_scales, sets[k].logits, sets[k].n,
                                     reinterpret_cast<const float *>(ws + L.acc) + off, g.means, g.quats, g.log_scales,
@@ -361,7 +374,7 @@ slr_status check_grads(int32_t n_sets, const slr_surfel_grads *grads, bool pose_
 namespace slr {
 
 Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, const int64_t *set_n, int64_t cap,
-                   int32_t th, int32_t tw)
+                   int32_t th, int32_t tw, bool fixed_order)
 {
     Layout L{};
     L.frames = nframes; L.sets = nsets; L.th = th; L.tw = tw; L.cap = cap;
@@ -416,6 +429,12 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.cmask_words = 4 * (L.cap / 64 + L.tiles + 2);
     L.cmask = take(8 * (size_t)L.cmask_words);
     L.acc = take(4 * (size_t)L.acc_floats);
+    if (fixed_order) {
+        L.rank = take(4 * (size_t)nn);
+        L.slots = take(4 * (size_t)kSlotFloats * (size_t)cc);
+        L.slot_words = (cc + 31) / 32;
+        L.slot_bits = take(4 * (size_t)L.slot_words);
+    }
     L.scratch_pose = take(48 * (size_t)(nframes > 0 ? nframes : 1));
     L.misc = take(4096);
     L.total = o;
@@ -478,7 +497,8 @@ slr_status slr_workspace_size(const slr_sensor *sensor, const slr_tiling *tiling
     if (n < 0 || pair_capacity < 0 || pair_capacity > 0x7fffffffLL || n > (int64_t(1) << 30))
         return fail(SLR_E_INVALID, "n and pair_capacity out of range");
     FrameGeom g{sensor->height, sensor->width, 0, tiling->tile_h, tiling->tile_w};
-    *bytes = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w).total;
+    *bytes = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w,
+                              tiling->bwd_variant == SLR_VARIANT_DETERMINISTIC).total;
     return SLR_OK;
 }
 
@@ -985,7 +1005,8 @@ slr_status slr_workspace_views(const slr_sensor *sensor, const slr_tiling *tilin
     if (!workspace || !v) return fail(SLR_E_INVALID, "workspace and views must be non-NULL");
     if (n < 0 || pair_capacity < 0) return fail(SLR_E_INVALID, "negative size");
     FrameGeom g{sensor->height, sensor->width, 0, tiling->tile_h, tiling->tile_w};
-    Layout L = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w);
+    Layout L = slr::make_layout(1, &g, 1, &n, pair_capacity, tiling->tile_h, tiling->tile_w,
+                                tiling->bwd_variant == SLR_VARIANT_DETERMINISTIC);
     if (workspace_bytes < L.total) return fail(SLR_E_INVALID, "workspace too small");
     char *ws = reinterpret_cast<char *>(workspace);
     v->keys = reinterpret_cast<const uint32_t *>(ws + L.skey);

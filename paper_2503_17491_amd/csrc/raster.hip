@@ -840,6 +840,7 @@ k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
 }
 
 constexpr int kBwdBatch = 192;   // default records staged per backward batch (fits 4 workgroups per CU)
+constexpr int kDetBatch = 64;    // the fixed-order form's batch (its four rows of sums take 4x the LDS)
 constexpr int kNg = 18;
 
 __device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
@@ -1024,7 +1025,9 @@ __device__ __forceinline__ FrameRec flush_axes(const RasterRec &r)
 // FP64 (dPv = E_a + A_a ch, dQv = E_b + A_b ch; g_alpha = E_b x b_c + b_beta x C_s
 // + T_a M, g_beta = b_c x E_a + C_s x b_alpha + T_b M, g_c = dPv x b_beta +
 // b_alpha x dQv + T_c M), their se(3) pose contribution into pacc, and (acc not
-// NULL) the world-frame gradients added to the record's accumulator.
+// NULL) the world-frame gradients added to the record's accumulator, or with
+// STORE written with plain stores to a 64-B aligned slot of its own.
+template <bool STORE = false>
 __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRec &fr, const double *M,
                                              const double *ch, const double *pose, float *acc, double (&pacc)[6])
 {
@@ -1060,18 +1063,25 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
         for (int e = 0; e < 3; ++e) {
             R[3 * e] = pose[4 * e]; R[3 * e + 1] = pose[4 * e + 1]; R[3 * e + 2] = pose[4 * e + 2];
         }
+        float w[kAccStride];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double wa = R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2];
-            const double wb = R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2];
-            const double wc = R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2];
-            const double wn = R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2];
-            atomicAdd(acc + c, (float)wa);
-            atomicAdd(acc + 3 + c, (float)wb);
-            atomicAdd(acc + 6 + c, (float)wc);
-            atomicAdd(acc + 9 + c, (float)wn);
+            w[c] = (float)(R[c] * ga[0] + R[3 + c] * ga[1] + R[6 + c] * ga[2]);
+            w[3 + c] = (float)(R[c] * gb[0] + R[3 + c] * gb[1] + R[6 + c] * gb[2]);
+            w[6 + c] = (float)(R[c] * gc[0] + R[3 + c] * gc[1] + R[6 + c] * gc[2]);
+            w[9 + c] = (float)(R[c] * gn[0] + R[3 + c] * gn[1] + R[6 + c] * gn[2]);
         }
-        atomicAdd(acc + 12, s[14]);
+        w[12] = s[14];
+        if (STORE) {
+            float4 *q = reinterpret_cast<float4 *>(acc);
+            q[0] = make_float4(w[0], w[1], w[2], w[3]);
+            q[1] = make_float4(w[4], w[5], w[6], w[7]);
+            q[2] = make_float4(w[8], w[9], w[10], w[11]);
+            acc[12] = w[12];
+        } else {
+#pragma unroll
+            for (int c = 0; c < kAccStride; ++c) atomicAdd(acc + c, w[c]);
+        }
     }
 }
 
@@ -1079,8 +1089,15 @@ __device__ __forceinline__ void flush_record(const float (&s)[18], const FrameRe
 // QUEUE: the persistent form.  An occupancy-sized grid whose workgroups take
 // the tiles' slots of the longest-first order from a device counter (zeroed
 // before the launch) until the order is exhausted; otherwise workgroup b takes
-// slot b.  Either way slot k writes pose row k, so the results are the same.
-template <int BATCH, bool QUEUE>
+// slot b.  Either way tile t writes pose row t, so the results are the same
+// (and do not depend on the tile schedule either).
+// DET: the fixed-order form.  Each wave keeps its own row of record sums, the
+// flush adds the four rows in wave order, and a (tile, record) flush goes with
+// plain stores to the slot of the pair (its index in the record's emission
+// order: rank, off and rbox of the binning give it), whose bit it sets in
+// slot_bits; the slots are summed per surfel afterwards in a fixed order.  The
+// results then do not depend on the order in which workgroups run.
+template <int BATCH, bool QUEUE, bool DET>
 __global__ void __launch_bounds__(256, 4)  // 4 waves per SIMD: at most 128 VGPRs
 k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ tile_frame,
              const uint32_t *__restrict__ order,
@@ -1089,11 +1106,14 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
              const float *__restrict__ stT_all,
              const int32_t *__restrict__ stN_all, int32_t *__restrict__ census_all, int64_t total_pixels,
              double *__restrict__ pose_part, int pose_only, uint32_t *__restrict__ queue, int ntiles,
-             const uint64_t *__restrict__ cmask)
+             const uint64_t *__restrict__ cmask, const uint32_t *__restrict__ rank,
+             const uint32_t *__restrict__ off, const PixBox *__restrict__ rbox, float *__restrict__ slots,
+             uint32_t *__restrict__ slot_bits)
 {
+    constexpr int NROW = DET ? 4 : 1;
     __shared__ RasterRec srec[BATCH];
     __shared__ ChatRec schat[BATCH];
-    __shared__ float sred[kNg][BATCH];   // wave sums of the four waves, added in LDS
+    __shared__ float sred[NROW][kNg][BATCH];   // wave sums: added in LDS by the four waves, or one row per wave
     __shared__ int sflag[BATCH];
     __shared__ uint8_t slist[4][BATCH];
     __shared__ int s_last;
@@ -1145,7 +1165,7 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
         const float gn1 = (inside && gN) ? gN[3 * p + 1] : 0.0f;
         const float gn2 = (inside && gN) ? gN[3 * p + 2] : 0.0f;
         if (threadIdx.x == 0) s_last = 0;
-        for (int e = threadIdx.x; e < kNg * BATCH; e += blockDim.x) (&sred[0][0])[e] = 0.0f;
+        for (int e = threadIdx.x; e < NROW * kNg * BATCH; e += blockDim.x) (&sred[0][0][0])[e] = 0.0f;
         for (int e = threadIdx.x; e < BATCH; e += blockDim.x) sflag[e] = 0;
         if (threadIdx.x < 24) (&s_pose[0][0])[threadIdx.x] = 0.0;
         __syncthreads();
@@ -1218,7 +1238,10 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                         }
                         static_assert(kNg == 18, "wave_sum18 reduces 18 values");
                         const float tot = wave_sum18(g, lane);
-                        if (red_val < kNg) atomicAdd(&sred[red_val][k], tot);
+                        if (red_val < kNg) {
+                            if (DET) sred[DET ? wid : 0][red_val][k] = tot;
+                            else atomicAdd(&sred[0][red_val][k], tot);
+                        }
                         if (lane == 0) sflag[k] = 1;
                     }
                 }
@@ -1234,11 +1257,33 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                     // take the record's sums and leave the slots zeroed for the next batch
                     float s[kNg];
 #pragma unroll
-                    for (int v = 0; v < kNg; ++v) { s[v] = sred[v][k]; sred[v][k] = 0.0f; }
+                    for (int v = 0; v < kNg; ++v) {
+                        if constexpr (DET) {
+                            s[v] = ((sred[0][v][k] + sred[NROW - 3][v][k]) + sred[NROW - 2][v][k]) + sred[NROW - 1][v][k];
+#pragma unroll
+                            for (int w = 0; w < NROW; ++w) sred[w][v][k] = 0.0f;
+                        } else {
+                            s[v] = sred[0][v][k];
+                            sred[0][v][k] = 0.0f;
+                        }
+                    }
                     sflag[k] = 0;
                     const uint32_t id = pval[b0 + k];
                     const FrameRec fr = flush_axes(srec[k]);
-                    flush_record(s, fr, srec[k].M, schat[k].c, pose, pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
+                    if constexpr (DET) {
+                        float *slot = nullptr;
+                        if (!pose_only) {
+                            // the pair's index in its record's emission order
+                            const uint32_t r = rank[id];
+                            const uint32_t e = off[r] + (uint32_t)span_index(tile_span(rbox[r], TH, TW), ty, tx);
+                            slot = slots + (size_t)kSlotFloats * e;
+                            atomicOr(slot_bits + (e >> 5), 1u << (e & 31));
+                        }
+                        flush_record<true>(s, fr, srec[k].M, schat[k].c, pose, slot, pacc);
+                    } else {
+                        flush_record(s, fr, srec[k].M, schat[k].c, pose,
+                                     pose_only ? nullptr : acc + (size_t)(id - fd.item_off) * kAccStride, pacc);
+                    }
                 }
             }
             if (__any(flushed)) {
@@ -1255,15 +1300,15 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
             census[2 * total_pixels + p] = n_eval;
             census[3 * total_pixels + p] = n_con;
         }
-        // the four waves' pose sums into the slot's own row (summed per keyframe in
+        // the four waves' pose sums into the tile's own row (summed per keyframe in
         // a fixed order by k_pose_reduce; no atomics)
         __syncthreads();
         if (threadIdx.x < 6) {
-            pose_part[8 * (size_t)item + threadIdx.x] =
+            pose_part[8 * (size_t)tile + threadIdx.x] =
                 s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
         }
         if (threadIdx.x == 6) {
-            pose_part[8 * (size_t)item + 6] = (double)tile_frame[tile];
+            pose_part[8 * (size_t)tile + 6] = (double)tile_frame[tile];
         }
 
     }
@@ -2232,8 +2277,10 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
         return;
     }
     const bool queue = L.schedule == SLR_SCHEDULE_QUEUE;
-    auto kern = L.bwd_batch == 128 ? (queue ? k_raster_bwd<128, true> : k_raster_bwd<128, false>)
-                                   : (queue ? k_raster_bwd<kBwdBatch, true> : k_raster_bwd<kBwdBatch, false>);
+    const bool det = L.bwd_variant == SLR_VARIANT_DETERMINISTIC;
+    auto kern = det ? (queue ? k_raster_bwd<kDetBatch, true, true> : k_raster_bwd<kDetBatch, false, true>)
+                : L.bwd_batch == 128 ? (queue ? k_raster_bwd<128, true, false> : k_raster_bwd<128, false, false>)
+                                     : (queue ? k_raster_bwd<kBwdBatch, true, false> : k_raster_bwd<kBwdBatch, false, false>);
     uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.misc + kMiscQueue);
     const int64_t grid = queue ? resident_grid(kern, 256, L.tiles) : L.tiles;
     if (queue) launch_fill_u32(counter, 0u, 1, stream);
@@ -2243,7 +2290,11 @@ void bwd_launch(const Layout &L, char *ws, bool pose_only, hipStream_t stream)
                        reinterpret_cast<const int2 *>(ws + L.ranges), reinterpret_cast<const double2 *>(ws + L.tables),
                        reinterpret_cast<const float *>(ws + L.stateT), reinterpret_cast<const int32_t *>(ws + L.stateN),
                        reinterpret_cast<int32_t *>(ws + L.census), L.pixels, reinterpret_cast<double *>(ws + L.pose_part),
-                       pose_only ? 1 : 0, counter, (int)L.tiles, cmask);
+                       pose_only ? 1 : 0, counter, (int)L.tiles, cmask,
+                       det ? reinterpret_cast<const uint32_t *>(ws + L.rank) : nullptr,
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const PixBox *>(ws + L.rbox),
+                       det ? reinterpret_cast<float *>(ws + L.slots) : nullptr,
+                       det ? reinterpret_cast<uint32_t *>(ws + L.slot_bits) : nullptr);
 }
 
 void gn_launch(const Layout &L, char *ws, hipStream_t stream)

@@ -57,6 +57,32 @@ struct __align__(16) PixBox {
     uint16_t cnt;
 };
 
+// The tiles of a record's pixel box in the order its pairs are emitted: row
+// by row, and in a row the tiles of the first column interval, then those of
+// the second (a box that wraps past column W - 1 has two; intervals that
+// touch or overlap in tile columns are merged into the first).  Tile rows and
+// columns are frame-local.
+struct TileSpan {
+    int ty0, ax0, na, bx0, len;   // first row, first interval [ax0, ax0 + na), second from bx0, tiles per row
+};
+__host__ __device__ inline TileSpan tile_span(const PixBox &b, int th, int tw)
+{
+    int ax0 = b.c0 / tw, ax1 = b.c1 / tw;
+    int bx0 = 0, bx1 = -1;
+    if (b.c2 >= 0) {
+        bx0 = b.c2 / tw; bx1 = b.c3 / tw;
+        if (bx0 <= ax1) { ax1 = bx1 > ax1 ? bx1 : ax1; bx0 = 0; bx1 = -1; }
+    }
+    return TileSpan{b.r0 / th, ax0, ax1 - ax0 + 1, bx0, (ax1 - ax0 + 1) + (bx1 - bx0 + 1)};
+}
+// Position of tile (ty, tx) among the emitted pairs of a record with span sp
+// (the tile must be in the record's box).
+__host__ __device__ inline int span_index(const TileSpan &sp, int ty, int tx)
+{
+    const int cc = (tx >= sp.ax0 && tx < sp.ax0 + sp.na) ? tx - sp.ax0 : sp.na + (tx - sp.bx0);
+    return (ty - sp.ty0) * sp.len + cc;
+}
+
 // Per-frame descriptor (device memory).
 struct __align__(16) FrameDesc {
     const double *pose;                                  // [4,4] T_cw
@@ -131,6 +157,11 @@ struct Layout {
     size_t pt0, pv0, pt1, pv1, rcnt, rbox, pose_part, gn_part, ranges, order, hist, stateT, stateN, census, acc, scratch_pose, misc, total;
     size_t cmask;          // contribution mask of the one-wave forward (cmask_words u64)
     int64_t cmask_words;
+    // fixed-order backward (bwd_variant SLR_VARIANT_DETERMINISTIC; 0 otherwise): the range-order
+    // index of each record, one 64-B slot per pair for a (tile, record) flush and a bit per
+    // pair marking the slots written by the current backward
+    size_t rank, slots, slot_bits;
+    int64_t slot_words;
     // misc: [0] u64 K, [8] u64 overflow (required K, 0 = fits), [64..) u32 digit totals
 };
 
@@ -147,7 +178,10 @@ struct FrameGeom {
 };
 
 Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, const int64_t *set_n, int64_t cap,
-                   int32_t th, int32_t tw);
+                   int32_t th, int32_t tw, bool fixed_order);
+
+// Floats of a pair slot of the fixed-order backward (13 used).
+constexpr int kSlotFloats = 16;
 
 // ---- launchers (all enqueue on `stream`) ----
 void launch_write_desc(const FrameDesc *host_descs, int32_t count, FrameDesc *dev, hipStream_t stream);
@@ -159,6 +193,12 @@ void launch_emit_and_tile_sort(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_fwd(const Layout &L, char *ws, hipStream_t stream);
 void launch_raster_bwd(const Layout &L, char *ws, bool pose_only, hipStream_t stream);
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream);
+// Fixed-order backward: the range-order index of every binned record (before
+// the compositing backward), and each surfel's slots summed into its set's
+// accumulator, frames in batch order and a record's pairs in emission order
+// (after it; acc of set `set`, n surfels).
+void launch_record_rank(const Layout &L, char *ws, hipStream_t stream);
+void launch_slot_gather(const Layout &L, char *ws, int32_t set, int64_t n, float *acc, hipStream_t stream);
 void launch_raster_gn(const Layout &L, char *ws, hipStream_t stream);
 void launch_gn_reduce(const Layout &L, char *ws, hipStream_t stream);
 

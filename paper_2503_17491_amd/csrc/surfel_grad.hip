@@ -173,7 +173,82 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
     d_logits[k] = go;
 }
 
+// ---- fixed-order backward ----
+
+// rank[order[r]] = r for the binned records r < nvis (range order).  Entries of
+// records that bin into no tile keep whatever they held; readers accept an
+// entry only if it is below nvis and order maps it back to the record.
+__global__ void __launch_bounds__(256)
+k_record_rank(const uint32_t *__restrict__ order, const uint64_t *__restrict__ nvis, uint32_t *__restrict__ rank)
+{
+    const uint64_t n = *nvis;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x)
+        rank[order[r]] = (uint32_t)r;
+}
+
+// One thread per surfel of a set: the slots its records' flushes wrote, frames
+// in batch order and a record's pairs in emission order, summed in FP64 and
+// written (not added) to the set's accumulator.  A record's pairs are the
+// emission slots [off[r], off[r] + rcnt[r]) below the emitted count keff; a
+// slot counts if the backward set its bit.
+__global__ void __launch_bounds__(256)
+k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
+              const uint32_t *__restrict__ order, const uint64_t *__restrict__ misc, const uint32_t *__restrict__ rank,
+              const uint32_t *__restrict__ off, const uint32_t *__restrict__ rcnt, const float *__restrict__ slots,
+              const uint32_t *__restrict__ bits, float *__restrict__ acc)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint64_t keff = misc[2], nvis = misc[3];
+    double a[kAccStride];
+#pragma unroll
+    for (int v = 0; v < kAccStride; ++v) a[v] = 0.0;
+    for (int32_t f = 0; f < nframes; ++f) {
+        const FrameDesc &fd = descs[f];
+        if (fd.set != set) continue;
+        const uint32_t item = (uint32_t)(fd.item_off + k);
+        const uint32_t r = rank[item];
+        if ((uint64_t)r >= nvis || order[r] != item) continue;   // the record bins into no tile
+        const uint64_t e0 = off[r];
+        uint64_t e1 = e0 + rcnt[r];
+        e1 = e1 < keff ? e1 : keff;
+        for (uint64_t e = e0; e < e1; ++e) {
+            if (!((bits[e >> 5] >> (e & 31)) & 1u)) continue;
+            const float4 *q = reinterpret_cast<const float4 *>(slots + (size_t)kSlotFloats * e);
+            const float4 x0 = q[0], x1 = q[1], x2 = q[2];
+            const float x3 = slots[(size_t)kSlotFloats * e + 12];
+            a[0] += x0.x; a[1] += x0.y; a[2] += x0.z; a[3] += x0.w;
+            a[4] += x1.x; a[5] += x1.y; a[6] += x1.z; a[7] += x1.w;
+            a[8] += x2.x; a[9] += x2.y; a[10] += x2.z; a[11] += x2.w;
+            a[12] += x3;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < kAccStride; ++v) acc[kAccStride * k + v] = (float)a[v];
+}
+
 }  // namespace
+
+void launch_record_rank(const Layout &L, char *ws, hipStream_t stream)
+{
+    if (L.items == 0) return;
+    const int64_t blocks = (L.items + 255) / 256;
+    hipLaunchKernelGGL(k_record_rank, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0)),
+                       reinterpret_cast<const uint64_t *>(ws + L.misc) + 3, reinterpret_cast<uint32_t *>(ws + L.rank));
+}
+
+void launch_slot_gather(const Layout &L, char *ws, int32_t set, int64_t n, float *acc, hipStream_t stream)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_slot_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const FrameDesc *>(ws + L.desc), L.frames, set, n,
+                       reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0)),
+                       reinterpret_cast<const uint64_t *>(ws + L.misc), reinterpret_cast<const uint32_t *>(ws + L.rank),
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
+                       reinterpret_cast<const float *>(ws + L.slots), reinterpret_cast<const uint32_t *>(ws + L.slot_bits),
+                       acc);
+}
 
 void launch_pose_reduce(const Layout &L, char *ws, hipStream_t stream)
 {

@@ -33,6 +33,7 @@ class Tiling(C.Structure):
 
 
 VARIANT_DEFAULT, VARIANT_LDS, VARIANT_SCALAR, VARIANT_WAVE = 0, 1, 2, 3
+VARIANT_DETERMINISTIC = 4   # backward form only: fixed-order sums, bit-reproducible gradients
 SCHEDULE_DEFAULT, SCHEDULE_TILE, SCHEDULE_LONGEST, SCHEDULE_QUEUE = 0, 1, 2, 3
 
 

@@ -59,6 +59,17 @@ def test_workspace_size_and_validation():
     with pytest.raises(slr.SlrError) as e:
         slr.workspace_size(s, (32, 8, 3, 4, 1, 0, 0), 10, 10)
     assert e.value.status == slr.SLR_E_INVALID and "schedule" in str(e.value)
+    # backward forms 0, 1, 3 and 4 (4: the fixed-order form, whose workspace adds a
+    # 64-B slot and a bit per pair of capacity and a rank per record)
+    for bv in (0, 1, 3, 4):
+        assert slr.workspace_size(s, (32, 8, 3, 2, bv, 0, 0), 10, 10) > 0
+    for bv in (2, 5, -1):
+        with pytest.raises(slr.SlrError) as e:
+            slr.workspace_size(s, (32, 8, 3, 2, bv, 0, 0), 10, 10)
+        assert e.value.status == slr.SLR_E_INVALID and "backward variant" in str(e.value)
+    base = slr.workspace_size(s, (32, 8, 3, 2, 1, 0, 0), 100000, 1 << 20)
+    det = slr.workspace_size(s, (32, 8, 3, 2, 4, 0, 0), 100000, 1 << 20)
+    assert 64 * (1 << 20) + 4 * 100000 + (1 << 20) // 8 <= det - base <= 64 * (1 << 20) + 4 * 100000 + (1 << 20) // 8 + 768
     pole = slr.make_sensor(64, 512, el=(math.radians(-89.5), math.radians(10)))
     with pytest.raises(slr.SlrError) as e:
         slr.workspace_size(pole, (16, 16), 10, 10)

@@ -131,6 +131,65 @@ def test_queue_schedule_matches_longest(slr, batch):
         np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=1e-6, atol=1e-12)
 
 
+def test_fixed_order_backward_is_deterministic(slr):
+    """The fixed-order backward (bwd_variant 4): surfel and pose gradients bit
+    for bit the same over repeated steps, every tile schedule (tile order,
+    longest first, the persistent work queue) and every forward variant, with
+    outputs overwritten whatever they held; equal to the float-atomic
+    workgroup backward up to the order of its sums.  Also for a batch whose
+    frames have their own tile shapes.  The one-wave backward's pose gradients
+    (per-slot partial rows over a tile order that depends only on the list
+    lengths) are also equal over re-renders."""
+    det = slr.VARIANT_DETERMINISTIC
+
+    def run(tiling, tiles=None, fill=0.0):
+        sets, frames, _, br = make_batch(slr, tiling, tiles=tiles)
+        upstream(br, 3)
+        out = []
+        for _ in range(2):
+            for g in br.grads:
+                for t in g.values():
+                    t.fill_(fill)
+            br.render()
+            br.backward()
+            torch.cuda.synchronize()
+            out.append(([{k: v.clone() for k, v in g.items()} for g in br.grads], [d.clone() for d in br.dpose]))
+        return out
+
+    def same(a, b, what):
+        for ga, gb in zip(a[0], b[0]):
+            for key in ga:
+                assert torch.equal(ga[key], gb[key]), (what, key)
+        for da, db in zip(a[1], b[1]):
+            assert torch.equal(da, db), (what, "pose")
+
+    ref = None
+    for fv, sched in ((3, 2), (3, 1), (3, 3), (1, 2), (2, 1)):
+        say(f"fixed-order backward, forward variant {fv}, schedule {sched}")
+        for got in run((16, 16, fv, sched, det), fill=7.0 if sched == 1 else 0.0):
+            if ref is None:
+                ref = got
+            same(ref, got, (fv, sched))
+    say("float-atomic workgroup backward on the same batch")
+    atom = run((16, 16, 3, 2, slr.VARIANT_LDS, 0, 192))[0]
+    for ga, gb in zip(ref[0], atom[0]):
+        for key in ga:
+            a, b = ga[key].cpu().numpy(), gb[key].cpu().numpy()
+            assert np.isfinite(a).all()
+            assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), key
+    for da, db in zip(ref[1], atom[1]):
+        np.testing.assert_allclose(da.cpu().numpy(), db.cpu().numpy(), rtol=1e-6, atol=1e-12)
+    say("one-wave backward: pose gradients (fixed-order sums over tile slots) equal over re-renders")
+    wave = run((16, 16, 3, 2, slr.VARIANT_WAVE))
+    for da, db in zip(wave[0][1], wave[1][1]):
+        assert torch.equal(da, db)
+    say("fixed-order backward, mixed tile shapes")
+    mixed = run((16, 16, 3, 3, det), tiles=MIXED_TILES)
+    same(mixed[0], mixed[1], "mixed tiles")
+    mixed2 = run((16, 16, 3, 1, det), tiles=MIXED_TILES)
+    same(mixed[0], mixed2[0], "mixed tiles, tile order")
+
+
 def test_invalid_surfels_counted_and_inert(slr):
     """Surfels with a non-finite parameter or a zero quaternion are culled in
     every frame that renders their set, counted in the batch's counter word,
@@ -176,13 +235,15 @@ def test_invalid_surfels_counted_and_inert(slr):
 MIXED_TILES = [(8, 32), (4, 64), (32, 8), (16, 16)]
 
 
-@pytest.mark.parametrize("bwd", [1, 3])
+@pytest.mark.parametrize("bwd", [1, 3, 4])
 def test_batched_mixed_tiles(slr, bwd):
     """Every frame with its own tile shape in one batch (one compositing launch
     over tiles of four shapes): each frame's sorted (tile, surfel) lists and
     tile ranges equal the oracle's binning at that shape, its images equal the
     plain form's at that shape bit for bit, its pose gradient and the set
-    gradients match the plain form's; the images also match the oracle."""
+    gradients match the plain form's; the images also match the oracle.  With
+    the fixed-order backward (4) the gradients of the set only one frame
+    renders equal the plain form's bit for bit."""
     from tests import gpu_checks as GC
     say("mixed tile shapes, backward form", bwd)
     sets, frames, host_sets, br = make_batch(slr, (16, 16, 3, 2, bwd), tiles=MIXED_TILES)
@@ -217,6 +278,9 @@ def test_batched_mixed_tiles(slr, bwd):
         if f["set"] == 0:
             for key in sum_g:
                 sum_g[key] += g[key]
+        elif bwd == slr.VARIANT_DETERMINISTIC:   # the same flushes, summed in the same order
+            for key in g:
+                assert torch.equal(br.grads[1][key], g[key]), key
         else:   # the same sums up to the order of the float atomics
             for key in g:
                 a, b = br.grads[1][key].cpu().numpy(), g[key].cpu().numpy()

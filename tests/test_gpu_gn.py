@@ -144,6 +144,16 @@ def test_pose_gn_repeatable_and_degenerate(slr):
     b = [t.clone() for t in r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, wt)]
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+    # also after a fresh render (binning and tile order recomputed), for both forms
+    for tl in ((16, 16), (16, 16, 3, 2, 1)):
+        rr = slr.Renderer(sensor, tl, 1 << 18)
+        outs = []
+        for _ in range(2):
+            Dr, _, _ = rr.forward(d["means"], d["quats"], d["log_scales"], d["logits"], Td)
+            outs.append([t.clone() for t in rr.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, Dr,
+                                                       tg, wt)])
+        for x, y in zip(*outs):
+            assert torch.equal(x, y), tl
     z = r.pose_gn(d["means"], d["quats"], d["log_scales"], d["logits"], Td, D, tg, torch.zeros_like(wt))
     for x in z:
         assert not x.cpu().numpy().any()

@@ -14,9 +14,10 @@ the horizon.
   (Sec. 3.2.1 Eqs. ab_depth, ab_normal, ab_opacity); see tests/gpu_checks.py
   for the admissible-result rule.
 * Backward of keyframe 0 with random upstream gradients on every pixel whose
-  decisions lie away from all thresholds, for both LDS batch sizes and the
-  one-wave backward (whose longest tiles take the quad mode), against the
-  oracle's analytic gradients (Supp. D; the se(3) pose gradient).
+  decisions lie away from all thresholds, for both LDS batch sizes, the
+  one-wave backward (whose longest tiles take the quad mode) and the
+  fixed-order backward, against the oracle's analytic gradients (Supp. D; the
+  se(3) pose gradient).
 * The eight-keyframe batch: each keyframe's sorted lists and tile ranges are
   the oracle's binning of that keyframe; keyframe 0's images equal the plain
   form's bit for bit; the other keyframes' images match the oracle on 2048
@@ -134,13 +135,14 @@ def dense_upstream(case):
     return pix, gD, gN, gO, ref
 
 
-@pytest.mark.parametrize("batch", [128, 192, "wave"])
+@pytest.mark.parametrize("batch", [128, 192, "wave", "fixed"])
 def test_headline_backward_dense(slr, case, dense_upstream, batch):
-    """The workgroup backward at both LDS batch sizes, and the one-wave
+    """The workgroup backward at both LDS batch sizes, the one-wave
     backward, whose longest tiles (lists of 1536 entries or more) a single
-    keyframe takes in quad mode."""
+    keyframe takes in quad mode, and the fixed-order backward."""
     pix, gD, gN, gO, ref = dense_upstream
-    tl = tiling(slr, 0, slr.VARIANT_WAVE) if batch == "wave" else tiling(slr, batch)
+    tl = (tiling(slr, 0, slr.VARIANT_WAVE) if batch == "wave"
+          else tiling(slr, 0, slr.VARIANT_DETERMINISTIC) if batch == "fixed" else tiling(slr, batch))
     r = slr.Renderer(case["sensor"], tl, 4 << 20)
     d = case["d"]
     Td = GC.pose_dev(torch, case["poses"][0])
@@ -152,7 +154,8 @@ def test_headline_backward_dense(slr, case, dense_upstream, batch):
     torch.cuda.synchronize()
     GC.backward_verdict({k: v.cpu().numpy() for k, v in g.items()}, dp.cpu().numpy(), ref,
                         label=f"1M surfels, keyframe 0, {pix.shape[0]} pixels, "
-                              + ("one-wave backward (quad mode)" if batch == "wave" else f"LDS batch {batch}"))
+                              + ("one-wave backward (quad mode)" if batch == "wave"
+                                 else "fixed-order backward" if batch == "fixed" else f"LDS batch {batch}"))
 
 
 def test_headline_batch_lists_and_images(slr, case):

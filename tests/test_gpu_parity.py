@@ -254,6 +254,28 @@ def test_backward_parity_fullsize_dense(slr):
                    1 << 20)
 
 
+@pytest.mark.parametrize("tiling", [(16, 16, 3, 2, 4), (4, 64, 1, 1, 4), (8, 32, 2, 3, 4)])
+def test_backward_parity_fixed_order(slr, tiling):
+    """The fixed-order backward (flushes written to per-pair slots, summed
+    per surfel in binning order) against the oracle's analytic gradients on
+    every clean pixel of the shell scene, whose surfels at the seam have
+    pixel boxes of two column intervals; three tile shapes, every schedule."""
+    say("backward shell-2k-64x512 fixed order", tiling)
+    sc = synth.shell_scene(2000, 1)
+    sensor = slr.make_sensor(64, 512)
+    T = synth.perturbed_pose(1, 0.3, 5.0)
+    pix = clean_pixels(sc, T, sensor)
+    g = np.random.default_rng(1)
+    P = pix.shape[0]
+    r, *_ = check_backward(slr, sc, T, sensor, pix, g.normal(size=P).astype(np.float32),
+                           g.normal(size=(P, 3)).astype(np.float32), g.normal(size=P).astype(np.float32), tiling)
+    v = r.views()
+    box = v["pixbox"].cpu().numpy()
+    wraps = int(((v["counts"].cpu().numpy() > 0) & (box[:, 4] >= 0)).sum())
+    say(f"   {wraps} binned surfels with a box wrapping past the seam")
+    assert wraps > 0
+
+
 def test_backward_batch_sizes_agree(slr):
     """The workgroup backward stages 128 or 192 records per LDS batch
     (slr_tiling.bwd_batch): the same pairs in the same per-pixel order, so the
