@@ -133,7 +133,7 @@ def profiled_tilings(kernel):
 
 
 def tiling_label(th, tw, var, bvar, bbatch, sch=0):
-    vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave"}
+    vnames = {0: "default", 1: "lds", 2: "scalar", 3: "wave", 4: "fixed"}
     return f"{th}x{tw} fwd {vnames[var]} bwd {vnames[bvar]}" + (
         f" batch {bbatch}" if bvar == 1 and bbatch not in (0, 192) else "") + (" queue" if sch == 3 else "")
 
@@ -342,8 +342,9 @@ def main():
                     help="HxW tile shape, or auto: the autotuner picks shape, form and schedule (untimed)")
     ap.add_argument("--variant", choices=["default", "lds", "scalar", "wave"], default="default",
                     help="forward compositing kernel: records staged in LDS, or read through the scalar cache")
-    ap.add_argument("--bwd-variant", choices=["default", "lds", "wave"], default="default",
-                    help="backward compositing kernel: one workgroup per tile, or one wave per strip")
+    ap.add_argument("--bwd-variant", choices=["default", "lds", "wave", "fixed"], default="default",
+                    help="backward compositing kernel: one workgroup per tile, one wave per strip, or the "
+                         "fixed-order (deterministic) workgroup form")
     ap.add_argument("--schedule", choices=["default", "tile", "longest", "queue"], default="default",
                     help="order in which the compositing kernels take tiles")
     ap.add_argument("--only", choices=["both", "batched"], default="both",
@@ -381,7 +382,8 @@ def main():
     sch = {"default": slr.SCHEDULE_DEFAULT, "tile": slr.SCHEDULE_TILE, "longest": slr.SCHEDULE_LONGEST,
            "queue": slr.SCHEDULE_QUEUE}[args.schedule]
     th = tw = None
-    bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE}[args.bwd_variant]
+    bvar = {"default": 0, "lds": slr.VARIANT_LDS, "wave": slr.VARIANT_WAVE,
+            "fixed": slr.VARIANT_DETERMINISTIC}[args.bwd_variant]
     box = {"exact": slr.BOX_EXACT, "opacity": slr.BOX_OPACITY, "vertex": slr.BOX_VERTEX}[args.box]
     bbatch = args.bwd_batch
     if args.tile != "auto":
@@ -574,13 +576,13 @@ def main():
                                f"map, fwd + L1 range/normal loss + bwd per keyframe",
                    "form": args.form, "graph": graph is not None, "tile": f"{th}x{tw}", "variant": {0: "default", 1: "lds", 2: "scalar", 3: "wave"}[var],
                    "schedule": {0: "default", 1: "tile", 2: "longest", 3: "queue"}[sch],
-                   "bwd_variant": {0: "default", 1: "lds", 3: "wave"}[bvar],
+                   "bwd_variant": {0: "default", 1: "lds", 3: "wave", 4: "fixed"}[bvar],
                    "bwd_batch": bbatch if bbatch else 192, "autotuned": tune_ms is not None,
                    "box": args.box,
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3),
-                   "plain_bwd_variant": {0: "default", 1: "lds", 3: "wave"}[plain_tiling[4]],
+                   "plain_bwd_variant": {0: "default", 1: "lds", 3: "wave", 4: "fixed"}[plain_tiling[4]],
                    "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
         "roofline": roof, "cpu_baseline": cpu, "stage_ms_per_step": stage_ms, "pose_gn": gn, "photo_gn": photo, "mapping": mapping,

@@ -175,9 +175,9 @@ k_surfel_grad(int64_t n, const float *__restrict__ quats, const float *__restric
 
 // ---- fixed-order backward ----
 
-// rank[order[r]] = r for the binned records r < nvis (range order).  Entries of
-// records that bin into no tile keep whatever they held; readers accept an
-// entry only if it is below nvis and order maps it back to the record.
+// rank[order[r]] = r for the binned records r < nvis (range order); the
+// entries of records that bin into no tile keep the ~0u the launcher fills
+// the array with first.
 __global__ void __launch_bounds__(256)
 k_record_rank(const uint32_t *__restrict__ order, const uint64_t *__restrict__ nvis, uint32_t *__restrict__ rank)
 {
@@ -188,13 +188,13 @@ k_record_rank(const uint32_t *__restrict__ order, const uint64_t *__restrict__ n
 
 // One thread per surfel of a set: the slots its records' flushes wrote, frames
 // in batch order and a record's pairs in emission order, summed in FP64 and
-// written (not added) to the set's accumulator.  A record's pairs are the
-// emission slots [off[r], off[r] + rcnt[r]) below the emitted count keff; a
-// slot counts if the backward set its bit.
+// written (not added) to the set's accumulator.  The pairs of record r are
+// the emission slots [off[r], off[r + 1]) (the last record's run to the
+// emitted count keff), below keff; a slot counts if the backward set its bit.
 __global__ void __launch_bounds__(256)
 k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
-              const uint32_t *__restrict__ order, const uint64_t *__restrict__ misc, const uint32_t *__restrict__ rank,
-              const uint32_t *__restrict__ off, const uint32_t *__restrict__ rcnt, const float *__restrict__ slots,
+              const uint64_t *__restrict__ misc, const uint32_t *__restrict__ rank,
+              const uint32_t *__restrict__ off, const float *__restrict__ slots,
               const uint32_t *__restrict__ bits, float *__restrict__ acc)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,9 +208,9 @@ k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set,
         if (fd.set != set) continue;
         const uint32_t item = (uint32_t)(fd.item_off + k);
         const uint32_t r = rank[item];
-        if ((uint64_t)r >= nvis || order[r] != item) continue;   // the record bins into no tile
+        if (r == ~0u) continue;   // the record bins into no tile
         const uint64_t e0 = off[r];
-        uint64_t e1 = e0 + rcnt[r];
+        uint64_t e1 = (uint64_t)r + 1 < nvis ? (uint64_t)off[r + 1] : keff;
         e1 = e1 < keff ? e1 : keff;
         for (uint64_t e = e0; e < e1; ++e) {
             if (!((bits[e >> 5] >> (e & 31)) & 1u)) continue;
@@ -232,6 +232,7 @@ k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set,
 void launch_record_rank(const Layout &L, char *ws, hipStream_t stream)
 {
     if (L.items == 0) return;
+    launch_fill_u32(ws + L.rank, ~0u, L.items, stream);
     const int64_t blocks = (L.items + 255) / 256;
     hipLaunchKernelGGL(k_record_rank, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, stream,
                        reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0)),
@@ -243,10 +244,8 @@ void launch_slot_gather(const Layout &L, char *ws, int32_t set, int64_t n, float
     if (n == 0) return;
     hipLaunchKernelGGL(k_slot_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const FrameDesc *>(ws + L.desc), L.frames, set, n,
-                       reinterpret_cast<const uint32_t *>(ws + (L.depth_in_1 ? L.val1 : L.val0)),
                        reinterpret_cast<const uint64_t *>(ws + L.misc), reinterpret_cast<const uint32_t *>(ws + L.rank),
-                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const uint32_t *>(ws + L.rcnt),
-                       reinterpret_cast<const float *>(ws + L.slots), reinterpret_cast<const uint32_t *>(ws + L.slot_bits),
+                       reinterpret_cast<const uint32_t *>(ws + L.off), reinterpret_cast<const float *>(ws + L.slots), reinterpret_cast<const uint32_t *>(ws + L.slot_bits),
                        acc);
 }
 
