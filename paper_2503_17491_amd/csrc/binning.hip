@@ -30,6 +30,8 @@ namespace {
 
 constexpr int kWaves = kSortThreads / 64;
 constexpr int kEmitThreads = 256;
+constexpr int kScanItems = 16;                         // per thread in the per-digit scan over blocks
+constexpr int kScanChunk = kSortThreads * kScanItems;
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
@@ -57,6 +59,7 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t *s_wave, uint32_t *total)
     return pre + x - v;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift,
              int bits, uint32_t *__restrict__ hist, int nblocks)
@@ -66,10 +69,10 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_max, const uint64_t *_
     const int nb = 1 << bits;
     for (int d = threadIdx.x; d < nb; d += kSortThreads) h[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
     const uint32_t mask = (uint32_t)nb - 1u;
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
     }
@@ -82,31 +85,31 @@ __global__ void __launch_bounds__(kSortThreads)
 k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ totals)
 {
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ uint32_t s_items[kSortTile];
+    __shared__ uint32_t s_items[kScanChunk];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
-    // chunks of kSortTile counts: coalesced loads into LDS, kSortItems
+    // chunks of kScanChunk counts: coalesced loads into LDS, kScanItems
     // consecutive counts per thread, one block scan per chunk
-    for (int c0 = 0; c0 < nblocks; c0 += kSortTile) {
+    for (int c0 = 0; c0 < nblocks; c0 += kScanChunk) {
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < kScanItems; ++i) {
             const int b = c0 + i * kSortThreads + threadIdx.x;
             s_items[i * kSortThreads + threadIdx.x] = b < nblocks ? row[b] : 0u;
         }
         __syncthreads();
-        uint32_t local[kSortItems], sum = 0;
+        uint32_t local[kScanItems], sum = 0;
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < kScanItems; ++i) {
             local[i] = sum;
-            sum += s_items[threadIdx.x * kSortItems + i];
+            sum += s_items[threadIdx.x * kScanItems + i];
         }
         uint32_t tot;
         const uint32_t pre = carry + block_exscan(sum, s_wave, &tot);
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) s_items[threadIdx.x * kSortItems + i] = pre + local[i];
+        for (int i = 0; i < kScanItems; ++i) s_items[threadIdx.x * kScanItems + i] = pre + local[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < kScanItems; ++i) {
             const int b = c0 + i * kSortThreads + threadIdx.x;
             if (b < nblocks) row[b] = s_items[i * kSortThreads + threadIdx.x];
         }
@@ -116,6 +119,7 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                 uint32_t *__restrict__ vout, int64_t n_max, const uint64_t *__restrict__ n_dev, int shift, int bits,
@@ -124,11 +128,11 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
 {
     const int64_t n = n_dev ? (int64_t)min((uint64_t)n_max, *n_dev) : n_max;
     // the grid is sized for the capacity: blocks past the items have nothing to move
-    if ((int64_t)blockIdx.x * kSortTile >= n) return;
+    if ((int64_t)blockIdx.x * (kSortThreads * ITEMS) >= n) return;
     __shared__ uint32_t s_base[256], s_start[256], s_gbase[256];
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ uint32_t s_key[kSortTile], s_val[kSortTile];
+    __shared__ uint32_t s_key[(kSortThreads * ITEMS)], s_val[(kSortThreads * ITEMS)];
     const int nb = 1 << bits;
     const uint32_t mask = (uint32_t)nb - 1u;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -142,11 +146,11 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     for (int d = lane; d < 256; d += 64) s_cnt[wid][d] = 0;
     __syncthreads();
 
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (kSortTile / kWaves);
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS) + (int64_t)wid * ((kSortThreads * ITEMS) / kWaves);
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = base + (int64_t)i * 64 + lane;
         bool valid = idx < n;
         key[i] = valid ? kin[idx] : 0u;
@@ -187,7 +191,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     __syncthreads();
     // the block's items in LDS in digit order (stable: wave, then item order)
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * 64 + lane;
         if (idx < n) {
             const uint32_t d = (key[i] >> shift) & mask;
@@ -198,8 +202,8 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     }
     __syncthreads();
     // each digit's run goes out to consecutive addresses from consecutive threads
-    const int64_t b0 = (int64_t)blockIdx.x * kSortTile;
-    const int nvalid = (int)min((int64_t)kSortTile, n - b0);
+    const int64_t b0 = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
+    const int nvalid = (int)min((int64_t)(kSortThreads * ITEMS), n - b0);
     for (int j = threadIdx.x; j < nvalid; j += kSortThreads) {
         const uint32_t k = s_key[j], v = s_val[j];
         const uint32_t d = (k >> shift) & mask;
@@ -216,16 +220,17 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
 }
 
 // ---- scan of tile counts in range order ----
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_reduce(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t *__restrict__ n_dev,
               uint32_t *__restrict__ blocksum)
 {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t n = (int64_t)min((uint64_t)n_max, *n_dev);
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
     uint32_t acc = 0;
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) acc += rcounts[idx];
     }
@@ -258,35 +263,36 @@ k_scan_blocks(uint32_t *__restrict__ blocksum, int nblocks, uint64_t *__restrict
     }
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t *__restrict__ n_dev,
              const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ offsets, uint32_t *__restrict__ estart,
              uint64_t cap)
 {
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ uint32_t s_items[kSortTile];
+    __shared__ uint32_t s_items[(kSortThreads * ITEMS)];
     const int64_t n = (int64_t)min((uint64_t)n_max, *n_dev);
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         s_items[i * kSortThreads + threadIdx.x] = idx < n ? rcounts[idx] : 0u;
     }
     __syncthreads();
-    // each thread scans a contiguous run of kSortItems
-    uint32_t local[kSortItems], sum = 0;
+    // each thread scans a contiguous run of ITEMS
+    uint32_t local[ITEMS], sum = 0;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         local[i] = sum;
-        sum += s_items[threadIdx.x * kSortItems + i];
+        sum += s_items[threadIdx.x * ITEMS + i];
     }
     uint32_t tot;
     uint32_t pre = block_exscan(sum, s_wave, &tot) + blocksum[blockIdx.x];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) s_items[threadIdx.x * kSortItems + i] = pre + local[i];
+    for (int i = 0; i < ITEMS; ++i) s_items[threadIdx.x * ITEMS + i] = pre + local[i];
     __syncthreads();
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) {
             const uint32_t o = s_items[i * kSortThreads + threadIdx.x];
@@ -305,14 +311,15 @@ k_scan_apply(const uint32_t *__restrict__ rcounts, int64_t n_max, const uint64_t
 // Records without a tile (culled, behind, outside the image: count 0) do not
 // enter the range sort.  The visible ones keep their index order, so the
 // stable sort still breaks range ties by index.
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_vis_count(const int32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ blocksum)
 {
     __shared__ uint32_t s_wave[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
     uint32_t acc = 0;
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) acc += cnt[idx] > 0 ? 1u : 0u;
     }
@@ -323,17 +330,18 @@ k_vis_count(const int32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ b
 
 // Ranks are row-major like the radix scatter's: items base + i kSortThreads +
 // t, so every wave's surviving lanes of one row write consecutive slots.
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_vis_write(const uint32_t *__restrict__ keys, const int32_t *__restrict__ cnt, int64_t n,
             const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout)
 {
-    constexpr int kSlots = kSortItems * kWaves;
+    constexpr int kSlots = ITEMS * kWaves;
     __shared__ uint32_t s_pre[kSlots];   // (row, wave) -> rank of its first survivor in the block
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    uint64_t mask[kSortItems];
+    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * ITEMS);
+    uint64_t mask[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         mask[i] = __ballot(idx < n && cnt[idx] > 0);
         if (lane == 0) s_pre[i * kWaves + wid] = (uint32_t)__popcll(mask[i]);
@@ -358,7 +366,7 @@ k_vis_write(const uint32_t *__restrict__ keys, const int32_t *__restrict__ cnt, 
     const uint64_t lt = lanemask_lt();
     const uint32_t b0 = blocksum[blockIdx.x];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         if ((mask[i] >> lane) & 1ull) {
             const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
             const uint32_t pos = b0 + s_pre[i * kWaves + wid] + (uint32_t)__popcll(mask[i] & lt);
@@ -549,16 +557,49 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint
 
 // One LSD pass; swaps the roles of (k0,v0) and (k1,v1).
 // n_max sizes the grid; n_dev (nullable) holds the actual count on the device.
+template <int ITEMS>
+void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+                  const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream,
+                  const PixBox *box_in, uint32_t *cnt_out, PixBox *box_out)
+{
+    const int nblocks = (int)((n_max + kSortThreads * ITEMS - 1) / (kSortThreads * ITEMS));
+    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits,
+                       hist, nblocks);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
+    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max,
+                       n_dev, shift, bits, hist, totals, nblocks, box_in, cnt_out, box_out);
+}
+
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint64_t *n_dev, int shift, int bits, uint32_t *hist, uint32_t *totals, hipStream_t stream,
                 const PixBox *box_in = nullptr, uint32_t *cnt_out = nullptr, PixBox *box_out = nullptr)
 {
-    int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, n_max, n_dev, shift, bits, hist,
-                       nblocks);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(kSortThreads), 0, stream, hist, nblocks, totals);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n_max, n_dev,
-                       shift, bits, hist, totals, nblocks, box_in, cnt_out, box_out);
+    switch (sort_items(n_max)) {
+    case 4: radix_pass_t<4>(kin, vin, kout, vout, n_max, n_dev, shift, bits, hist, totals, stream, box_in, cnt_out, box_out); break;
+    case 8: radix_pass_t<8>(kin, vin, kout, vout, n_max, n_dev, shift, bits, hist, totals, stream, box_in, cnt_out, box_out); break;
+    default: radix_pass_t<16>(kin, vin, kout, vout, n_max, n_dev, shift, bits, hist, totals, stream, box_in, cnt_out, box_out);
+    }
+}
+
+template <int ITEMS>
+void compact_visible_t(const uint32_t *ks, const int32_t *cnt, int64_t items, uint32_t *bs, uint64_t *nvis, uint32_t *k0,
+                       uint32_t *v0, hipStream_t stream)
+{
+    const int nblocks = (int)((items + kSortThreads * ITEMS - 1) / (kSortThreads * ITEMS));
+    hipLaunchKernelGGL(k_vis_count<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, cnt, items, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, nvis, (int64_t)-1);
+    hipLaunchKernelGGL(k_vis_write<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, ks, cnt, items, bs, k0, v0);
+}
+
+template <int ITEMS>
+void scan_counts_t(const uint32_t *rcounts, int64_t items, const uint64_t *nvis, uint32_t *bs, uint64_t *misc,
+                   int64_t cap, uint32_t *off, uint32_t *estart, hipStream_t stream)
+{
+    const int nblocks = (int)((items + kSortThreads * ITEMS - 1) / (kSortThreads * ITEMS));
+    hipLaunchKernelGGL(k_scan_reduce<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, items, nvis, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc, cap);
+    hipLaunchKernelGGL(k_scan_apply<ITEMS>, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, items, nvis, bs, off,
+                       estart, (uint64_t)cap);
 }
 
 }  // namespace
@@ -582,10 +623,11 @@ void launch_depth_sort(const Layout &L, char *ws, hipStream_t stream)
     // the records that bin into some tile, in index order, into (key0, val0)
     const int32_t *cnt = reinterpret_cast<const int32_t *>(ws + L.cnt);
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
-    const int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_vis_count, dim3(nblocks), dim3(kSortThreads), 0, stream, cnt, L.items, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, nvis, (int64_t)-1);
-    hipLaunchKernelGGL(k_vis_write, dim3(nblocks), dim3(kSortThreads), 0, stream, ks, cnt, L.items, bs, k0, v0);
+    switch (sort_items(L.items)) {
+    case 4: compact_visible_t<4>(ks, cnt, L.items, bs, nvis, k0, v0, stream); break;
+    case 8: compact_visible_t<8>(ks, cnt, L.items, bs, nvis, k0, v0, stream); break;
+    default: compact_visible_t<16>(ks, cnt, L.items, bs, nvis, k0, v0, stream);
+    }
     for (int p = 0; p < L.depth_passes; ++p) {
         const bool even = (p % 2) == 0;
         const bool last = p == L.depth_passes - 1;
@@ -606,12 +648,12 @@ void launch_scan_counts(const Layout &L, char *ws, hipStream_t stream)
     const uint64_t *nvis = misc + 3;
     const uint32_t *rcounts = reinterpret_cast<const uint32_t *>(ws + L.rcnt);   // in range order
     uint32_t *bs = reinterpret_cast<uint32_t *>(ws + L.blocksum);
-    int nblocks = (int)((L.items + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kSortThreads), 0, stream, bs, nblocks, misc, (int64_t)L.cap);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(kSortThreads), 0, stream, rcounts, L.items, nvis, bs,
-                       reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.estart),
-                       (uint64_t)L.cap);
+    uint32_t *off = reinterpret_cast<uint32_t *>(ws + L.off), *est = reinterpret_cast<uint32_t *>(ws + L.estart);
+    switch (sort_items(L.items)) {
+    case 4: scan_counts_t<4>(rcounts, L.items, nvis, bs, misc, L.cap, off, est, stream); break;
+    case 8: scan_counts_t<8>(rcounts, L.items, nvis, bs, misc, L.cap, off, est, stream); break;
+    default: scan_counts_t<16>(rcounts, L.items, nvis, bs, misc, L.cap, off, est, stream);
+    }
 }
 
 static void launch_tile_order(const Layout &L, char *ws, hipStream_t stream)

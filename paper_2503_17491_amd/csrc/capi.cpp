@@ -405,7 +405,8 @@ Layout make_layout(int32_t nframes, const FrameGeom *frames, int32_t nsets, cons
     L.off = take(4 * nn);
     // per emit block: the record holding its first pair slot
     L.estart = take(4 * (size_t)(cc / kEmitSlots + 2));
-    const int64_t nb_n = (nn + kSortTile - 1) / kSortTile, nb_k = (cc + kSortTile - 1) / kSortTile;
+    const int64_t tn = kSortThreads * sort_items(nn), tk = kSortThreads * sort_items(cc);
+    const int64_t nb_n = (nn + tn - 1) / tn, nb_k = (cc + tk - 1) / tk;
     L.blocksum = take(4 * nb_n);
     L.pt0 = take(4 * cc); L.pv0 = take(4 * cc); L.pt1 = take(4 * cc); L.pv1 = take(4 * cc);
     // tile counts and boxes of the records in range order (written by the range sort's last pass)

@@ -108,8 +108,15 @@ constexpr int kAccStride = 13;
 
 // Radix sort geometry.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                       // per thread
-constexpr int kSortTile = kSortThreads * kSortItems; // items per block
+// Items per thread of the radix-sort, compaction and count-scan kernels,
+// chosen per sort from the size its grid is launched for: blocks of 1024, 2048
+// or 4096 items, so that the few hundred thousand records of a single frame
+// still spread over the chip in enough blocks, while a batch's millions move
+// in larger ones.
+__host__ __device__ inline int sort_items(int64_t n_max)
+{
+    return n_max >= (int64_t(1) << 23) ? 16 : (n_max >= (int64_t(1) << 20) ? 8 : 4);
+}
 constexpr int kEmitSlots = 512;                      // (tile, surfel) pairs per emit block (a power of two)
 constexpr int kMaxDigitBits = 8;
 
