@@ -691,12 +691,12 @@ __device__ __forceinline__ void fwd_w_item(int64_t b, const FrameDesc *__restric
             int sLast = bcast(last, pl), sCon = 0;
             PairEval ev;
             const bool ok = eval_pair_flat(r, pvx, pvy, pvz, near_m, ev) && rem;
-            uint64_t cm = __ballot(ok);
+            uint64_t hits = __ballot(ok);
             int counted = nact - q;
             bool sDone = false;
-            while (cm) {
-                const int jl = (int)__builtin_ctzll(cm);
-                cm &= cm - 1;
+            while (hits) {
+                const int jl = (int)__builtin_ctzll(hits);
+                hits &= hits - 1;
                 const float a = bcast(ev.alpha, jl), tj = bcast(ev.t, jl);
                 const float tT = sT * (1.0f - a);
                 if (tT < kTMin) {
@@ -1665,11 +1665,11 @@ k_raster_bwd_w(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
                 PairEval ev;
                 const bool ok = eval_pair_flat(sbuf[lane], pvx, pvy, pvz, near_m, ev) && cand;
                 const int pe = __popcll(__ballot(cand));
-                uint64_t cm = __ballot(ok);
-                const int pc = __popcll(cm);
-                while (cm) {
-                    const int jl = 63 - (int)__builtin_clzll(cm);   // reverse list order
-                    cm &= ~(1ull << jl);
+                uint64_t hits = __ballot(ok);
+                const int pc = __popcll(hits);
+                while (hits) {
+                    const int jl = 63 - (int)__builtin_clzll(hits);   // reverse list order
+                    hits &= ~(1ull << jl);
                     PairEval ej;
                     ej.sa = bcast(ev.sa, jl); ej.sb = bcast(ev.sb, jl); ej.t = bcast(ev.t, jl);
                     ej.rc = bcast(ev.rc, jl); ej.G = bcast(ev.G, jl); ej.alpha = bcast(ev.alpha, jl);
