@@ -134,7 +134,7 @@ inline int64_t wave_blocks(int64_t tiles) { return 32 * ((tiles + 7) / 8); }
 // long tile in quad mode, a 128x2048 frame (1024 tiles) about a third of them
 // and a batch of eight 128x1024 frames none.  The count is decided on the
 // device after binning (a u32 at misc + kMiscQuadTiles).
-constexpr int kQuadMinList = 1536;   // a boundary of the half-octave length buckets of the tile order
+constexpr int kQuadMinList = 768;    // a boundary of the half-octave length buckets of the tile order
 constexpr int64_t kQuadBudget = 8192;
 constexpr size_t kMiscQuadTiles = 32;
 constexpr size_t kMiscQueue = 40;      // u32 work-queue head of the persistent workgroup backward

@@ -138,7 +138,7 @@ def dense_upstream(case):
 @pytest.mark.parametrize("batch", [128, 192, "wave", "fixed"])
 def test_headline_backward_dense(slr, case, dense_upstream, batch):
     """The workgroup backward at both LDS batch sizes, the one-wave
-    backward, whose longest tiles (lists of 1536 entries or more) a single
+    backward, whose longest tiles (lists of 768 entries or more) a single
     keyframe takes in quad mode, and the fixed-order backward."""
     pix, gD, gN, gO, ref = dense_upstream
     tl = (tiling(slr, 0, slr.VARIANT_WAVE) if batch == "wave"
