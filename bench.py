@@ -38,6 +38,7 @@ GN_CONTRIB_FLOPS = 96    # recompute alpha, reverse step with a unit range gradi
 PEAK_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), unpacked FP32 / FP64
 PEAK_HBM_GBS = 8000.0
 TUNE_MARGIN = 0.01       # autotune times closer than this are a tie (run-to-run spread is about 1 %)
+SINGLE_FRAME_SHAPES = ((16, 16), (32, 8), (8, 32))   # tile shapes the single-frame forms are timed on
 # Algorithmic HBM bytes of the compositing launches: per (tile, surfel) pair the
 # 4-B id and the 64-B compositing record are gathered (+52 B of gradient
 # accumulation in the backward); per pixel the forward writes 20 B of outputs
@@ -164,37 +165,61 @@ def roofline(kernel, flops, nbytes, ms, traffic):
     return roof
 
 
-def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
+def measure_gn(torch, slr, d, sensor, kf, tiling, steps):
     """Pose-only Gauss-Newton iterations on keyframe 0 (plain form): render at
     the pose, then the normal equations against the keyframe's target (least
     squares, weight 1 where the target has a return).  The 6x6 solve is the
-    caller's and is not timed.  The kernel walks the pairs the backward walks,
-    so its algorithmic FLOP come from keyframe 0's backward census.  The
-    normal equations take their one-wave-per-strip form (backward form 3):
-    on one keyframe's 512 tiles the workgroup form waits at its barrier."""
-    tiling = tuple(tiling[:4]) + (slr.VARIANT_WAVE,) + tuple(tiling[5:])
-    r = slr.Renderer(sensor, tiling, capacity=4 << 20)
+    caller's and is not timed.  The normal equations take their
+    one-wave-per-strip form (backward form 3): on one keyframe's 512 tiles the
+    workgroup form waits at its barrier; the tile shape is picked by timing
+    (untimed).  The kernel walks the pairs the backward walks, so its
+    algorithmic FLOP come from the backward census of the same tiling."""
     m = (kf["Dt"] > 0).float()
     buf = torch.empty(43, dtype=torch.float64, device="cuda")
     a5 = (d["means"], d["quats"], d["log_scales"], d["logits"], kf["T"])
 
-    def one():
-        D, _, _ = r.forward(*a5)
-        r.pose_gn(*a5, D, kf["Dt"], m, 0.0, out=buf)
+    def one(rr):
+        D, _, _ = rr.forward(*a5)
+        rr.pose_gn(*a5, D, kf["Dt"], m, 0.0, out=buf)
+
+    best = None
+    for th, tw in SINGLE_FRAME_SHAPES:
+        cand = (th, tw) + tuple(tiling[2:4]) + (slr.VARIANT_WAVE,) + tuple(tiling[5:])
+        rr = slr.Renderer(sensor, cand, capacity=4 << 20)
+        for _ in range(3):
+            one(rr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            one(rr)
+        torch.cuda.synchronize()
+        dt_c = time.perf_counter() - t0
+        if best is None or dt_c < best[0]:
+            best = (dt_c, cand)
+        del rr
+    tiling = best[1]
+    r = slr.Renderer(sensor, tiling, capacity=4 << 20)
+    zero = torch.zeros_like(kf["Dt"])
+    D, _, _ = r.forward(*a5)
+    r.backward(*a5, zero, None, None, pose_only=True)   # fills the backward census of this tiling
+    census0 = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
+
+    def one_r():
+        one(r)
 
     for _ in range(3):
-        one()
+        one_r()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        one()
+        one_r()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     slr.stage_timer(True)
     slr.stage_times()
     n = max(3, steps // 2)
     for _ in range(n):
-        one()
+        one_r()
     st = slr.stage_times()
     slr.stage_timer(False)
     ms = st["pose_gn"][0] / max(st["pose_gn"][1], 1)
@@ -202,6 +227,7 @@ def measure_gn(torch, slr, d, sensor, kf, tiling, steps, census0):
     ach = flops / (ms * 1e-3) / 1e12
     return {"workload": "keyframe 0 of the map, 128x1024: render + Gauss-Newton normal equations per iteration",
             "iter_s": round(steps / dt, 3), "kernel": "raster_gn_w", "form": "one wave per 64-pixel strip",
+            "tile": f"{tiling[0]}x{tiling[1]}",
             "kernel_ms": round(ms, 4),
             "render_ms": round(sum(st[k][0] for k in ("project", "range_sort", "count_scan", "emit_tile_sort",
                                                        "raster_fwd")) / n, 4),
@@ -435,11 +461,12 @@ def main():
     plain_tiling = tiling
     if tune_ms is not None and args.only == "both":
         # the plain loop renders one keyframe per launch, where the backward's
-        # workgroup barrier weighs more: its backward form is picked by timing
-        # both on the same shape (untimed)
+        # workgroup barrier weighs more and a single frame's 512 tiles fill the
+        # chip differently: its tile shape and backward form are picked by
+        # timing them on the plain loop (untimed)
         best = None
-        for bv in (slr.VARIANT_LDS, slr.VARIANT_WAVE):
-            cand = (th, tw, var, sch, bv, box, bbatch)
+        for ph, pw, bv in [(a, b, v) for a, b in SINGLE_FRAME_SHAPES for v in (slr.VARIANT_LDS, slr.VARIANT_WAVE)]:
+            cand = (ph, pw, var, sch, bv, box, bbatch)
             rr = [slr.Renderer(sensor, cand, capacity=4 << 20) for _ in kfs]
             plain_step(torch, slr, d, kfs, rr, grads, dposes, scratch, loss)
             torch.cuda.synchronize()
@@ -473,7 +500,6 @@ def main():
         plain_step(torch, slr, d, kfs, rend, grads, dposes, scratch, loss)
         torch.cuda.synchronize()
     ef = cf = eb = cb = 0
-    census0 = None
     if plain_tiling != tiling:   # the census of the batched form's tiling
         del rend
         rend = [slr.Renderer(sensor, tiling, capacity=4 << 20) for _ in kfs]
@@ -482,7 +508,6 @@ def main():
     for r in rend:  # per-keyframe work census (the backward's equals the batched form's)
         c = r.views()["census"].to(torch.int64).sum(dim=(1, 2)).tolist()
         ef += c[0]; cf += c[1]; eb += c[2]; cb += c[3]
-        census0 = c if census0 is None else census0
     pairs = int(sum(r.K for r in rend))
     del rend
     torch.cuda.empty_cache()
@@ -556,7 +581,7 @@ def main():
 
     gn = photo = mapping = None
     if not args.no_gn:
-        gn = measure_gn(torch, slr, d, sensor, kfs[0], tiling, args.steps, census0)
+        gn = measure_gn(torch, slr, d, sensor, kfs[0], tiling, args.steps)
         log("pose-only Gauss-Newton:", gn)
         photo = measure_photo(torch, slr, sensor, kfs[0], br.out[0][0], args.steps)
         log("photometric registration:", photo)
@@ -582,6 +607,7 @@ def main():
                    "keyframes": N_KF,
                    "surfels": N_SURFELS, "batched_iter_s": round(batched_iters, 3),
                    "plain_iter_s": None if plain_iters is None else round(plain_iters, 3),
+                   "plain_tile": f"{plain_tiling[0]}x{plain_tiling[1]}",
                    "plain_bwd_variant": {0: "default", 1: "lds", 3: "wave", 4: "fixed"}[plain_tiling[4]],
                    "pairs_per_step": pairs,
                    "census": {"fwd_eval": ef, "fwd_contrib": cf, "bwd_eval": eb, "bwd_contrib": cb}},
