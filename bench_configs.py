@@ -242,7 +242,23 @@ def config_odometry(torch, slr, synth, targets, args):
     Nz = torch.zeros(128, 1024, 3, device="cuda")
     T0 = synth.perturbed_pose(3, 0.5, 3.0)
     e0 = _pose_err(T0, T_true)
-    res = {}
+    # the tile shape of the single-frame loop by timing render + normal equations at the start pose
+    # (untimed; the images do not depend on it)
+    best = None
+    Td0 = torch.from_numpy(T0).cuda()
+    for th, tw in ((16, 16), (32, 8), (8, 32)):
+        cand = (th, tw, slr.VARIANT_WAVE, slr.SCHEDULE_LONGEST, slr.VARIANT_WAVE)
+        rr = slr.Renderer(sensor, cand, capacity=4 << 20)
+
+        def probe(rr=rr):
+            D0, _, _ = rr.forward(*a4, Td0)
+            rr.pose_gn(*a4, Td0, D0, Dt, m, 0.1)
+
+        dt = _time(torch, probe, 5, 2)
+        if best is None or dt < best[0]:
+            best = (dt, cand, rr)
+    tiling, r = best[1], best[2]
+    res = {"tile": f"{tiling[0]}x{tiling[1]}"}
     # Adam on the se(3) increment: gradient of mean |D - D_t| over O_t > 0.5
     T = T0.copy()
     mom, vel = np.zeros(6), np.zeros(6)
