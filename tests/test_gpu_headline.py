@@ -195,3 +195,41 @@ def test_headline_batch_lists_and_images(slr, case):
                                label=f"batched keyframe {f}")
         p0 += k
     assert p0 == K
+
+
+def test_batch_of_nine_matches_plain(slr, case):
+    """Nine keyframes of the 1M-surfel map in one batch (9 M records: the range
+    sort, compaction and count scan take their 4096-item blocks, which the
+    eight-keyframe batch does not reach) against the plain form of each
+    keyframe (2048-item blocks): identical sorted lists, tile ranges and
+    images, bit for bit."""
+    sensor, d = case["sensor"], case["d"]
+    poses = synth.circle_poses(9, 3)
+    frames = [dict(set=0, T_cw=GC.pose_dev(torch, T), sensor=sensor) for T in poses]
+    br = slr.BatchRenderer([d], frames, tiling(slr, 192), capacity=28 << 20)
+    br.render()
+    torch.cuda.synchronize()
+    K, over = br.pairs()
+    assert over == 0
+    v = br.views()
+    st, sid, rg = v["sorted_tile"].cpu().numpy(), v["sorted_id"].cpu().numpy(), v["ranges"].cpu().numpy()
+    r = slr.Renderer(sensor, tiling(slr, 192), 4 << 20)
+    p0 = 0
+    for f, fr in enumerate(frames):
+        D, N, A = r.forward(d["means"], d["quats"], d["log_scales"], d["logits"], fr["T_cw"])
+        torch.cuda.synchronize()
+        pv = r.views()
+        k, t0, i0 = pv["K"], v["tile_off"][f], v["item_off"][f]
+        np.testing.assert_array_equal(st[p0:p0 + k] - t0, pv["sorted_tile"].cpu().numpy())
+        np.testing.assert_array_equal(sid[p0:p0 + k] - i0, pv["sorted_id"].cpu().numpy())
+        nt = pv["ranges"].shape[0]
+        mine = rg[t0:t0 + nt].copy()
+        full = mine[:, 1] > mine[:, 0]
+        mine[full] -= p0
+        np.testing.assert_array_equal(mine, pv["ranges"].cpu().numpy())
+        for a, b in zip(br.out[f], (D, N, A)):
+            assert torch.equal(a, b), f"keyframe {f}"
+        p0 += k
+    assert p0 == K
+    say(f"nine keyframes: {K} pairs, lists, ranges and images equal the plain form's")
+
