@@ -89,7 +89,7 @@ typedef struct slr_sensor {
  * to a slot of its own (no floating-point atomics) and the slots of every
  * surfel summed by a gather kernel, frames in batch order and a record's
  * tiles in binning order, so the surfel and pose gradients are bit-identical
- * from run to run and for every schedule and forward variant (it stages 64
+ * from run to run and for every schedule and forward variant (it stages 96
  * records per batch, ignoring bwd_batch, and the workspace grows by 64 bytes
  * per pair of capacity and 4 bytes per record).  Every variant
  * and schedule produces bit-identical forward outputs.  box selects the

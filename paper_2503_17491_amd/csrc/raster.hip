@@ -840,7 +840,8 @@ k_raster_fwd_s(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ 
 }
 
 constexpr int kBwdBatch = 192;   // default records staged per backward batch (fits 4 workgroups per CU)
-constexpr int kDetBatch = 64;    // the fixed-order form's batch (its four rows of sums take 4x the LDS)
+constexpr int kDetBatch = 96;    // the fixed-order form's batch (its four rows of sums take 4x the LDS;
+                                 // 96 records still fit 4 workgroups per CU)
 constexpr int kNg = 18;
 
 __device__ __forceinline__ void dcross(const double *a, const double *b, double *o)
