@@ -191,6 +191,11 @@ k_record_rank(const uint32_t *__restrict__ order, const uint64_t *__restrict__ n
 // written (not added) to the set's accumulator.  The pairs of record r are
 // the emission slots [off[r], off[r + 1]) (the last record's run to the
 // emitted count keff), below keff; a slot counts if the backward set its bit.
+// Frames are taken kGatherFrames at a time with every rank, offset pair and
+// first mask word loaded before the sums, so the scattered loads of a group
+// are in flight together instead of one dependent chain per frame.
+constexpr int kGatherFrames = 8;
+
 __global__ void __launch_bounds__(256)
 k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set, int64_t n,
               const uint64_t *__restrict__ misc, const uint32_t *__restrict__ rank,
@@ -203,24 +208,42 @@ k_slot_gather(const FrameDesc *__restrict__ descs, int32_t nframes, int32_t set,
     double a[kAccStride];
 #pragma unroll
     for (int v = 0; v < kAccStride; ++v) a[v] = 0.0;
-    for (int32_t f = 0; f < nframes; ++f) {
-        const FrameDesc &fd = descs[f];
-        if (fd.set != set) continue;
-        const uint32_t item = (uint32_t)(fd.item_off + k);
-        const uint32_t r = rank[item];
-        if (r == ~0u) continue;   // the record bins into no tile
-        const uint64_t e0 = off[r];
-        uint64_t e1 = (uint64_t)r + 1 < nvis ? (uint64_t)off[r + 1] : keff;
-        e1 = e1 < keff ? e1 : keff;
-        for (uint64_t e = e0; e < e1; ++e) {
-            if (!((bits[e >> 5] >> (e & 31)) & 1u)) continue;
-            const float4 *q = reinterpret_cast<const float4 *>(slots + (size_t)kSlotFloats * e);
-            const float4 x0 = q[0], x1 = q[1], x2 = q[2];
-            const float x3 = slots[(size_t)kSlotFloats * e + 12];
-            a[0] += x0.x; a[1] += x0.y; a[2] += x0.z; a[3] += x0.w;
-            a[4] += x1.x; a[5] += x1.y; a[6] += x1.z; a[7] += x1.w;
-            a[8] += x2.x; a[9] += x2.y; a[10] += x2.z; a[11] += x2.w;
-            a[12] += x3;
+    for (int32_t f0 = 0; f0 < nframes; f0 += kGatherFrames) {
+        uint32_t r[kGatherFrames];
+#pragma unroll
+        for (int g = 0; g < kGatherFrames; ++g) {
+            const int32_t f = f0 + g;
+            r[g] = ~0u;
+            if (f < nframes && descs[f].set == set) r[g] = rank[(uint32_t)(descs[f].item_off + k)];
+        }
+        uint64_t e0[kGatherFrames], e1[kGatherFrames];
+#pragma unroll
+        for (int g = 0; g < kGatherFrames; ++g) {
+            e0[g] = 0;
+            e1[g] = 0;
+            if (r[g] != ~0u) {   // else the record bins into no tile
+                e0[g] = off[r[g]];
+                const uint64_t end = (uint64_t)r[g] + 1 < nvis ? (uint64_t)off[r[g] + 1] : keff;
+                e1[g] = end < keff ? end : keff;
+            }
+        }
+        uint32_t w[kGatherFrames];
+#pragma unroll
+        for (int g = 0; g < kGatherFrames; ++g) w[g] = e0[g] < e1[g] ? bits[e0[g] >> 5] : 0u;
+#pragma unroll
+        for (int g = 0; g < kGatherFrames; ++g) {
+            uint32_t word = w[g];
+            for (uint64_t e = e0[g]; e < e1[g]; ++e) {
+                if (e > e0[g] && (e & 31) == 0) word = bits[e >> 5];   // the run crosses into the next word
+                if (!((word >> (e & 31)) & 1u)) continue;
+                const float4 *q = reinterpret_cast<const float4 *>(slots + (size_t)kSlotFloats * e);
+                const float4 x0 = q[0], x1 = q[1], x2 = q[2];
+                const float x3 = slots[(size_t)kSlotFloats * e + 12];
+                a[0] += x0.x; a[1] += x0.y; a[2] += x0.z; a[3] += x0.w;
+                a[4] += x1.x; a[5] += x1.y; a[6] += x1.z; a[7] += x1.w;
+                a[8] += x2.x; a[9] += x2.y; a[10] += x2.z; a[11] += x2.w;
+                a[12] += x3;
+            }
         }
     }
 #pragma unroll
