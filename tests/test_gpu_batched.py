@@ -179,6 +179,19 @@ def test_fixed_order_backward_is_deterministic(slr):
             assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), key
     for da, db in zip(ref[1], atom[1]):
         np.testing.assert_allclose(da.cpu().numpy(), db.cpu().numpy(), rtol=1e-6, atol=1e-12)
+    say("fixed-order backward with SLR_ACCUMULATE: a second backward adds exactly the same gradients")
+    sets, frames, _, br = make_batch(slr, (16, 16, 3, 2, det))
+    upstream(br, 3)
+    br.render()
+    br.backward()
+    torch.cuda.synchronize()
+    once = [{k: v.clone() for k, v in g.items()} for g in br.grads]
+    br.backward(accumulate=True)
+    torch.cuda.synchronize()
+    for ga, gb in zip(once, br.grads):
+        for key in ga:
+            assert torch.equal(gb[key], ga[key] * 2), key
+            assert torch.equal(ga[key], ref[0][0][key] if ga is once[0] else ref[0][1][key]), key
     say("one-wave backward: pose gradients (fixed-order sums over tile slots) equal over re-renders")
     wave = run((16, 16, 3, 2, slr.VARIANT_WAVE))
     for da, db in zip(wave[0][1], wave[1][1]):
