@@ -40,18 +40,20 @@ def huber(r, k):
     return rho, w
 
 
-def pose_jacobian(means, quats, log_scales, logits, T_cw, sensor, pix, exact=False):
-    """[P, 6] rows dD(u)/d delta (rho; phi) of the listed pixels ([P, 2] (row, col))."""
+def pose_jacobian(means, quats, log_scales, logits, T_cw, sensor, pix, exact=False, cull=False):
+    """[P, 6] rows dD(u)/d delta (rho; phi) of the listed pixels ([P, 2] (row, col)).
+    cull: the oracle's result-identical angular-cull mode (faster on large maps)."""
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 2)
     J = np.zeros((pix.shape[0], 6))
     one = np.ones(1)
     for p in range(pix.shape[0]):
         J[p] = backward_pixels(means, quats, log_scales, logits, T_cw, sensor, pix[p:p + 1], one, None, None,
-                               exact=exact)["pose"]
+                               exact=exact, cull=cull)["pose"]
     return J
 
 
-def pose_gn(means, quats, log_scales, logits, T_cw, sensor, target, weight=None, huber_k=0.0, exact=False):
+def pose_gn(means, quats, log_scales, logits, T_cw, sensor, target, weight=None, huber_k=0.0, exact=False,
+            cull=False):
     """Normal equations of the pose-only Gauss-Newton step (see the module text).
 
     target, weight: [H, W] (weight None = all ones).  Returns dict with H [6,6],
@@ -59,7 +61,7 @@ def pose_gn(means, quats, log_scales, logits, T_cw, sensor, target, weight=None,
     (rows of zero-weight pixels are left zero).
     """
     Hh, Ww = int(sensor["height"]), int(sensor["width"])
-    img = render_image(means, quats, log_scales, logits, T_cw, sensor, exact=exact)
+    img = render_image(means, quats, log_scales, logits, T_cw, sensor, exact=exact, cull=cull)
     D = img["depth"].reshape(-1)
     t = np.asarray(target, np.float64).reshape(-1)
     m = np.ones(Hh * Ww) if weight is None else np.asarray(weight, np.float64).reshape(-1)
@@ -68,7 +70,7 @@ def pose_gn(means, quats, log_scales, logits, T_cw, sensor, target, weight=None,
     sel = np.nonzero(m != 0)[0]
     J = np.zeros((Hh * Ww, 6))
     if sel.size:
-        J[sel] = pose_jacobian(means, quats, log_scales, logits, T_cw, sensor, all_pixels(sensor)[sel], exact)
+        J[sel] = pose_jacobian(means, quats, log_scales, logits, T_cw, sensor, all_pixels(sensor)[sel], exact, cull)
     mw = m * w
     H = (J * mw[:, None]).T @ J
     g = J.T @ (mw * r)

@@ -8,6 +8,11 @@ Sec. 3.3.3) through the C ABI.
   relative, with a floor of 1e-2 of the entry's Cauchy-Schwarz scale
   (sqrt(H_ii H_jj) for H_ij, sqrt(H_ii S) for g_i with S = sum m w r^2, the
   largest either can be); the cost at 1e-4.
+* On the benchmark's map (1M surfels, 128x1024, keyframe 0 moved by a small
+  step, the oracle's image at the keyframe pose as the target): every entry
+  of H and g against the oracle as above on 48 pixels, half of them in the
+  longest tiles that the one-wave form composites in quad mode, for both
+  forms; the cost within the bound the forward's range tolerance implies.
 * At the benchmark's size (1M surfels, 128x1024, the analytic target): H is
   symmetric positive semidefinite, the cost equals the plain sum over pixels,
   and g equals the pose gradient that slr_backward computes for the upstream
@@ -247,6 +252,64 @@ def test_pose_gn_fullsize_properties(slr):
         assert np.linalg.norm(gn - dp) <= 1e-3 * np.linalg.norm(dp), (gn, dp)
         del r
         torch.cuda.empty_cache()
+
+
+_HEADLINE = {}
+
+
+def headline_case():
+    """The benchmark's map (1M structured-scene surfels, seed 0) and keyframe 0
+    moved by a small pose step; the target is the oracle's range image at the
+    keyframe's own pose; weight 1 on 32 pixels of the 4 longest-list tiles at
+    32x8 (composited in quad mode by the one-wave form) and 16 random pixels,
+    all with the oracle's decisions at the moved pose away from every
+    threshold and a return in the target.  (The oracle forms each pixel's
+    Jacobian row with a backward call of its own, about a second each on this
+    map, which bounds the pixel count.)"""
+    if _HEADLINE:
+        return _HEADLINE["case"]
+    sc, _ = synth.structured_scene(1_000_000, 0)
+    T_true = synth.circle_poses(8, 0)[0]
+    T = h.perturb_cw(T_true, np.array([0.02, -0.015, 0.01, 0.002, -0.003, 0.0025]))
+    sensor = O.make_sensor(128, 1024)
+    say("oracle renders of the 1M map at the keyframe pose and the moved pose")
+    args = (sc["means"], sc["quats"], sc["log_scales"], sc["logits"])
+    tgt = O.render_image(*args, T_true, sensor, cull=True)
+    cur = O.render_image(*args, T, sensor, cull=True)
+    bins = O.bin_surfels(*args, T, sensor, 32, 8)
+    L = bins["ranges"][:, 1] - bins["ranges"][:, 0]
+    ok = (tgt["alpha"] > 0.5) & ((cur["flags"] & (EXCL | O.FLAG_CLAMP)) == 0)
+    g = np.random.default_rng(71)
+    weight = np.zeros((128, 1024))
+    for t in np.argsort(-L, kind="stable")[:4]:
+        ty, tx = divmod(int(t), bins["tiles_x"])
+        ii, jj = np.nonzero(ok[ty * 32:(ty + 1) * 32, tx * 8:(tx + 1) * 8])
+        pick = g.permutation(ii.size)[:8]
+        weight[ty * 32 + ii[pick], tx * 8 + jj[pick]] = 1.0
+    ii, jj = np.nonzero(ok & (weight == 0))
+    pick = g.permutation(ii.size)[:16]
+    weight[ii[pick], jj[pick]] = 1.0
+    target = tgt["depth"].astype(np.float32).astype(np.float64)
+    say(f"oracle normal equations over {int(weight.sum())} pixels (longest list {int(L.max())})")
+    ref = O.pose_gn(*args, T, sensor, target, weight, 0.05, cull=True)
+    _HEADLINE["case"] = (sc, sensor, T, target, weight, ref)
+    return _HEADLINE["case"]
+
+
+@pytest.mark.parametrize("tiling", [(32, 8, 3, 2, 3), (32, 8, 3, 2, 1)])
+def test_pose_gn_headline_map_matches_oracle(slr, tiling):
+    """Gauss-Newton normal equations on the benchmark's map against the
+    oracle, entry by entry: the one-wave form (its longest tiles in quad mode)
+    and the workgroup form."""
+    sc, sensor, T, target, weight, ref = headline_case()
+    say("1M map, keyframe 0 moved, tiling", tiling)
+    Hm, g, c, _ = gpu_gn(slr, sc, T, sensor, target, weight, 0.05, tiling)
+    assert_gn_close(Hm, g, ref, weight, 0.05)
+    # the cost moves with the range by |d rho / d r| <= |r|: a range within the
+    # forward's 1e-4 relative bound keeps it within sum m |r| 1e-4 D
+    bound = 1e-4 * float((weight * np.abs(ref["residual"]) * np.abs(ref["depth"])).sum())
+    say(f"   cost {c:.6e} against {ref['cost']:.6e} (bound {bound:.1e})")
+    assert abs(c - ref["cost"]) <= bound, (c, ref["cost"], bound)
 
 
 def test_gauss_newton_iterations_converge(slr):
