@@ -77,7 +77,7 @@ typedef struct slr_sensor {
  * 0 = library default, 1 = tile-id order, 2 = longest surfel list first
  * (computed on the device after binning), 3 = the same order taken from a
  * device work queue by the one-wave forward (variant 3) and the workgroup
- * backward (bwd_variant 1), which then run as persistent kernels: as many
+ * backward (bwd_variant 1 or 4), which then run as persistent kernels: as many
  * workgroups as the device holds at once, each taking the next item (strip
  * or tile) until none is left (the other kernels behave as with 2; results
  * identical to 2).  bwd_variant selects the form of
