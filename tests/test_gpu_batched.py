@@ -192,6 +192,24 @@ def test_fixed_order_backward_is_deterministic(slr):
         for key in ga:
             assert torch.equal(gb[key], ga[key] * 2), key
             assert torch.equal(ga[key], ref[0][0][key] if ga is once[0] else ref[0][1][key]), key
+    say("fixed-order backward over ten keyframes of one set (the gather takes frames eight at a time)")
+    shared, _ = synth.structured_scene(30000, 23)
+    dset = dev_set(shared)
+    poses10 = synth.circle_poses(10, 6)
+    fr10 = [dict(set=0, T_cw=torch.from_numpy(T).to(DEV), sensor=slr.make_sensor(64, 512)) for T in poses10]
+    outs = []
+    for tl in ((16, 16, 3, 2, det), (16, 16, 3, 3, det), (16, 16, 3, 2, slr.VARIANT_LDS, 0, 192)):
+        b10 = slr.BatchRenderer([dset], fr10, tl, 1 << 22)
+        upstream(b10, 9)
+        b10.render()
+        b10.backward()
+        torch.cuda.synchronize()
+        outs.append({k: v.clone() for k, v in b10.grads[0].items()})
+        del b10
+    for key in outs[0]:
+        assert torch.equal(outs[0][key], outs[1][key]), key
+        a, b = outs[0][key].cpu().numpy(), outs[2][key].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), key
     say("one-wave backward: pose gradients (fixed-order sums over tile slots) equal over re-renders")
     wave = run((16, 16, 3, 2, slr.VARIANT_WAVE))
     for da, db in zip(wave[0][1], wave[1][1]):
