@@ -1213,7 +1213,11 @@ k_raster_bwd(const FrameDesc *__restrict__ descs, const int32_t *__restrict__ ti
                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint8_t)kk;
                 nact += __popcll(m);
             }
-            __syncthreads();
+            // a wave's walk reads only its own list and the records staged before the
+            // barrier above, so only the wave's own slist writes need to be visible
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int q = nact - 1; q >= 0; q -= 2) {
                 // two entries per step: both evaluations are independent of the
                 // reverse chain, which then takes them in list order
